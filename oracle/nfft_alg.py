@@ -1,0 +1,235 @@
+"""Plain FP64 NFFT following the paper's Algorithms 1 and 2 (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module.  It shares no code with the GPU library.
+It is pinned against the direct NDFT (``oracle.ndft``) and against closed forms
+in ``tests/test_oracle_*.py``.
+
+Notation (paper, section "Mathematical Description"):
+
+* ``N``   equispaced size, ``Nt`` = oversampled size (Ntilde = sigma * N),
+* ``m``   window half-width; the truncated window has support [-m/Nt, m/Nt),
+* nodes ``x`` (the paper's k_j) in T^D = [-1/2, 1/2)^D, node-major (J, D),
+* coefficients ``f`` on the centred index set I_N, stored row-major with
+  storage index i_d = n_d + N_d/2.
+
+Window (readings stated in the design doc): Kaiser-Bessel with shape parameter
+beta_d = pi * m * (2 - 1/sigma_d), sigma_d = Nt_d / N_d.
+
+* convolution side, psi_hat_Base(u) = sinh(beta sqrt(1-u^2)) / (pi sqrt(1-u^2))
+  on u in [-1, 1), zero outside (truncation, equation (approxTrunc));
+* deconvolution side, phi_Base(xi) = I0(sqrt(beta^2 - 4 pi^2 xi^2)), the Fourier
+  transform of the untruncated psi_hat_Base.
+
+Resampling stencil (reading of the index set I_{Nt,m}(k)): for a node with
+Nt*x = c + frac, c = floor(Nt*x), frac in [0, 1), the 2m taps are the grid
+points l = c - m + 1 + t, t = 0..2m-1, with window argument
+u_t = (Nt*x - l)/m = (frac + m - 1 - t)/m in [-1, 1); storage index l mod Nt
+(DC-first FFT order, the fftshift of the resampling-correction subsection folded
+into the index map).
+"""
+import numpy as np
+import scipy.special
+
+# ---------------------------------------------------------------------------
+# sizes and window
+
+
+def oversampled_size(N, sigma):
+    """Ntilde_d: smallest even integer >= sigma*N_d whose prime factors lie in {2, 3, 5}.
+
+    The paper sets Ntilde = sigma * N (subsection NFFT) without saying how a
+    non-integer product is rounded; this rule keeps Ntilde an FFT-friendly even
+    integer and is exact for every configuration used here.
+    """
+    out = []
+    for n in np.atleast_1d(N):
+        target = float(sigma) * int(n)
+        cand = int(np.ceil(target - 1e-9 * target))
+        cand += cand % 2
+        while True:
+            r = cand
+            for p in (2, 3, 5):
+                while r % p == 0:
+                    r //= p
+            if r == 1:
+                break
+            cand += 2
+        out.append(cand)
+    return tuple(out)
+
+
+def kb_beta(m, sigma_d):
+    """Kaiser-Bessel shape parameter beta = pi m (2 - 1/sigma)."""
+    return np.pi * m * (2.0 - 1.0 / sigma_d)
+
+
+def window_hat(u, beta):
+    """psi_hat_Base(u): sinh form on [-1, 1), zero outside; limit beta/pi where sqrt(1-u^2)=0."""
+    u = np.asarray(u, dtype=np.float64)
+    s = np.sqrt(np.clip(1.0 - u * u, 0.0, None))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        val = np.where(s > 0, np.sinh(beta * s) / (np.pi * np.where(s > 0, s, 1.0)), beta / np.pi)
+    inside = (u >= -1.0) & (u < 1.0)
+    return np.where(inside, val, 0.0)
+
+
+def window_phi(xi, beta):
+    """phi_Base(xi) = I0(sqrt(beta^2 - 4 pi^2 xi^2)) for |2 pi xi| <= beta."""
+    xi = np.asarray(xi, dtype=np.float64)
+    arg = beta * beta - (2.0 * np.pi * xi) ** 2
+    if np.any(arg < 0):
+        raise ValueError("phi_Base evaluated outside [-beta/2pi, beta/2pi]")
+    return scipy.special.i0(np.sqrt(arg))
+
+
+def deconv_factors(N_d, Nt_d, m):
+    """beta_tensor_d[n_d] = 1 / (m * phi_Base(m n_d / Nt_d)), n_d in I_{N_d}.
+
+    Resampling-correction subsection: the product over d equals 1/(|I_Nt| phi(n)).
+    """
+    beta = kb_beta(m, Nt_d / N_d)
+    n = np.arange(-(N_d // 2), N_d - N_d // 2, dtype=np.float64)
+    return 1.0 / (m * window_phi(m * n / Nt_d, beta))
+
+
+def poly_coeffs(m, beta, Z=None, Theta=None):
+    """Piecewise-polynomial window approximation (POLYNOMIAL precomputation).
+
+    For each tap t = 0..2m-1 a polynomial P_t of degree Z-1 (default 2m) in
+    zeta = frac - 1/2 in [-1/2, 1/2] is fitted by least squares to Theta = 2Z
+    equispaced samples of psi_hat_Base((zeta + m - 1/2 - t)/m); returns
+    mu[t, z] so that P_t(zeta) = sum_z mu[t, z] zeta^z.  The continuous sinh form
+    is sampled (its value at |u| = 1 is the limit beta/pi).
+    """
+    Z = 2 * m + 1 if Z is None else Z
+    Theta = 2 * Z if Theta is None else Theta
+    zeta = -0.5 + np.arange(Theta) / (Theta - 1.0)
+    V = zeta[:, None] ** np.arange(Z)[None, :]
+    mu = np.zeros((2 * m, Z))
+    for t in range(2 * m):
+        u = (zeta + m - 0.5 - t) / m
+        s = np.sqrt(np.clip(1.0 - u * u, 0.0, None))
+        b = np.where(s > 0, np.sinh(beta * s) / (np.pi * np.where(s > 0, s, 1.0)), beta / np.pi)
+        mu[t] = np.linalg.lstsq(V, b, rcond=None)[0]
+    return mu
+
+
+def tap_weights(frac, m, beta, window="poly"):
+    """Window weights for the 2m taps of nodes with fractional offset ``frac``; shape (..., 2m)."""
+    frac = np.asarray(frac, dtype=np.float64)
+    t = np.arange(2 * m)
+    if window == "direct":
+        return window_hat((frac[..., None] + m - 1 - t) / m, beta)
+    if window == "poly":
+        mu = poly_coeffs(m, beta)
+        zeta = frac - 0.5
+        powers = zeta[..., None] ** np.arange(mu.shape[1])
+        return powers @ mu.T
+    raise ValueError("window must be 'poly' or 'direct'")
+
+
+# ---------------------------------------------------------------------------
+# the two transforms
+
+
+def _wrap(x):
+    x = np.asarray(x, dtype=np.float64)
+    return x - np.floor(x + 0.5)
+
+
+def _stencil(x, Nt, m):
+    """Per node and axis: stencil origin c - m + 1 (unwrapped) and frac."""
+    y = _wrap(x) * np.asarray(Nt, dtype=np.float64)[None, :]
+    c = np.floor(y)
+    return (c - m + 1).astype(np.int64), y - c
+
+
+def _band_index(N_d, Nt_d):
+    """Storage index (n mod Nt) on the oversampled grid of each n in I_{N_d}, in storage order."""
+    n = np.arange(-(N_d // 2), N_d - N_d // 2)
+    return np.mod(n, Nt_d)
+
+
+def _weights_per_axis(x, N, Nt, m, window):
+    origin, frac = _stencil(x, Nt, m)
+    ws = []
+    for d in range(len(N)):
+        beta = kb_beta(m, Nt[d] / N[d])
+        ws.append(tap_weights(frac[:, d], m, beta, window))
+    return origin, ws
+
+
+def forward(x, f, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False):
+    """Direct NFFT, Algorithm 1 (resampling correction, FFT, resampling)."""
+    f = np.asarray(f, dtype=np.complex128)
+    N = f.shape
+    D = len(N)
+    Nt = oversampled_size(N, sigma) if Nt is None else tuple(Nt)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, D)
+
+    # step 1: g_n = f_n / (|I_Nt| phi(n)) on I_N, zero elsewhere, stored at n mod Nt
+    g = np.zeros(Nt, dtype=np.complex128)
+    scale = np.ones(N)
+    for d in range(D):
+        shape = [1] * D
+        shape[d] = N[d]
+        scale = scale * deconv_factors(N[d], Nt[d], m).reshape(shape)
+    g[np.ix_(*[_band_index(N[d], Nt[d]) for d in range(D)])] = f * scale
+
+    # step 2: ghat_l = sum_n g_n exp(-2 pi i n.l/Nt)  (unnormalised)
+    ghat = np.fft.fftn(g)
+
+    # step 3: fhat_j = sum over the (2m)^D stencil of prod_d w_d * ghat[l mod Nt]
+    origin, ws = _weights_per_axis(x, N, Nt, m, window)
+    J = x.shape[0]
+    fhat = np.zeros(J, dtype=np.complex128)
+    for taps in np.ndindex(*([2 * m] * D)):
+        w = np.ones(J)
+        flat = np.zeros(J, dtype=np.int64)
+        for d in range(D):
+            w = w * ws[d][:, taps[d]]
+            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
+        fhat += w * ghat.reshape(-1)[flat]
+    if return_steps:
+        return fhat, {"g": g, "ghat": ghat, "Nt": Nt}
+    return fhat
+
+
+def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False):
+    """Adjoint NFFT, Algorithm 2 (adjoint resampling, adjoint FFT, resampling correction)."""
+    N = tuple(int(v) for v in N)
+    D = len(N)
+    Nt = oversampled_size(N, sigma) if Nt is None else tuple(Nt)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, D)
+    fhat = np.asarray(fhat, dtype=np.complex128).reshape(-1)
+    J = x.shape[0]
+    G = int(np.prod(Nt))
+
+    # step 1: ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt)
+    origin, ws = _weights_per_axis(x, N, Nt, m, window)
+    acc_re = np.zeros(G)
+    acc_im = np.zeros(G)
+    for taps in np.ndindex(*([2 * m] * D)):
+        w = np.ones(J)
+        flat = np.zeros(J, dtype=np.int64)
+        for d in range(D):
+            w = w * ws[d][:, taps[d]]
+            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
+        v = w * fhat
+        acc_re += np.bincount(flat, weights=v.real, minlength=G)
+        acc_im += np.bincount(flat, weights=v.imag, minlength=G)
+    ghat = (acc_re + 1j * acc_im).reshape(Nt)
+
+    # step 2: g_n = sum_l ghat_l exp(+2 pi i n.l/Nt)  (unnormalised)
+    g = np.fft.ifftn(ghat) * G
+
+    # step 3: y_n = g_n / (|I_Nt| phi(n)) for n in I_N
+    y = g[np.ix_(*[_band_index(N[d], Nt[d]) for d in range(D)])]
+    for d in range(D):
+        shape = [1] * D
+        shape[d] = N[d]
+        y = y * deconv_factors(N[d], Nt[d], m).reshape(shape)
+    if return_steps:
+        return y, {"ghat": ghat, "g": g, "Nt": Nt}
+    return y

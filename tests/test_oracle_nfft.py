@@ -1,0 +1,152 @@
+"""Pins of the plain FP64 NFFT oracle (Algorithms 1 and 2) against the direct NDFT.
+
+The NFFT approximates the NDFT (paper, subsections "Direct NFFT", "Adjoint NFFT");
+its error decays exponentially in m (subsection "Algorithmic Complexity") and
+saturates near machine precision at m = 8 for sigma = 2 (section "Results",
+accuracy analysis).  The approximate pair is exactly adjoint, since
+A ~= B F D and A^H ~= D^T F^H B^T (subsection "Matrix-Vector Notation").
+
+Gates (relative l2 against the NDFT) come from the closed-form Kaiser-Bessel
+error estimates -- aliasing 1/I0(2 pi m sqrt(1 - 1/sigma)), truncation
+beta/sinh(beta) -- with margin for dimension and accumulation:
+"""
+import numpy as np
+import pytest
+
+from oracle import ndft
+from oracle import nfft_alg as na
+import nfft_workloads as wl
+
+GATE = {(3, 2.0): 3e-5, (4, 2.0): 1e-6, (6, 2.0): 1e-9, (8, 2.0): 1e-12, (4, 1.25): 2e-4}
+
+SHAPES = {1: ((256,), 512), 2: ((32, 32), 1024), 3: ((16, 16, 16), 4096)}
+
+
+def _rel2(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b))
+
+
+_cache = {}
+
+
+def _case(D):
+    if D not in _cache:
+        N, M = SHAPES[D]
+        x = wl.uniform_nodes(M, D, config=0, stream=0)
+        f = wl.cn01(N, config=0, stream=1)
+        fh = wl.cn01((M,), config=0, stream=2)
+        _cache[D] = (N, x, f, fh, ndft.ndft_forward(x, f), ndft.ndft_adjoint(x, fh, N))
+    return _cache[D]
+
+
+def _errors(D, m, sigma, window="poly"):
+    N, x, f, fh, ef, ea = _case(D)
+    return (_rel2(na.forward(x, f, m, sigma, window=window), ef),
+            _rel2(na.adjoint(x, fh, N, m, sigma, window=window), ea))
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+@pytest.mark.parametrize("m,sigma", sorted(GATE))
+def test_nfft_matches_ndft(D, m, sigma):
+    ef, ea = _errors(D, m, sigma)
+    assert ef < GATE[(m, sigma)] and ea < GATE[(m, sigma)], (ef, ea)
+
+
+@pytest.mark.parametrize("D", [1, 2])
+def test_direct_window_matches_ndft(D):
+    for m, sigma in [(4, 2.0), (6, 2.0)]:
+        ef, ea = _errors(D, m, sigma, window="direct")
+        assert ef < GATE[(m, sigma)] and ea < GATE[(m, sigma)]
+
+
+def test_error_decays_exponentially_in_m():
+    e3 = max(_errors(2, 3, 2.0))
+    e4 = max(_errors(2, 4, 2.0))
+    e6 = max(_errors(2, 6, 2.0))
+    assert e4 < e3 / 20 and e6 < e4 / 1000
+
+
+@pytest.mark.parametrize("D,m,sigma", [(1, 4, 2.0), (2, 6, 2.0), (3, 4, 1.25)])
+def test_approximate_pair_is_exactly_adjoint(D, m, sigma):
+    N, x, f, fh, _, _ = _case(D)
+    lhs = np.vdot(fh, na.forward(x, f, m, sigma))
+    rhs = np.vdot(na.adjoint(x, fh, N, m, sigma), f)
+    scale = np.linalg.norm(fh) * np.linalg.norm(na.forward(x, f, m, sigma))
+    assert abs(lhs - rhs) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("N", [(32,), (16, 16)])
+def test_grid_aligned_and_boundary_nodes(N):
+    """Nodes with Nt*x integral (the tie case of the half-open support), at -1/2 and at 0."""
+    D = len(N)
+    Nt = na.oversampled_size(N, 2.0)
+    g = wl.rng(96, 0)
+    x = g.integers(-Nt[0] // 2, Nt[0] // 2, size=(60, D)) / np.asarray(Nt, float)
+    x[0] = -0.5
+    x[1] = 0.0
+    f = wl.cn01(N, config=96, stream=1)
+    fh = wl.cn01((60,), config=96, stream=2)
+    assert _rel2(na.forward(x, f, 4, 2.0), ndft.ndft_forward(x, f)) < GATE[(4, 2.0)]
+    assert _rel2(na.adjoint(x, fh, N, 4, 2.0), ndft.ndft_adjoint(x, fh, N)) < GATE[(4, 2.0)]
+
+
+def test_nodes_outside_torus_are_wrapped():
+    N = (16, 16)
+    x = wl.uniform_nodes(40, 2, config=97, stream=0)
+    f = wl.cn01(N, config=97, stream=1)
+    a = na.forward(x, f, 4, 2.0)
+    b = na.forward(x + np.array([1.0, -2.0]), f, 4, 2.0)
+    assert _rel2(b, a) < 1e-13
+
+
+def test_empty_node_set():
+    N = (16,)
+    x = np.zeros((0, 1))
+    assert na.forward(x, np.ones(N, complex)).shape == (0,)
+    assert np.array_equal(na.adjoint(x, np.zeros(0, complex), N), np.zeros(N, complex))
+
+
+# --- planted mistakes: each plausible error in the oracle must fail a pin above ---
+
+def _fails_pin(monkeypatch, target, replacement):
+    monkeypatch.setattr(target[0], target[1], replacement)
+    ef, ea = _errors(2, 4, 2.0)
+    return ef > GATE[(4, 2.0)] or ea > GATE[(4, 2.0)]
+
+
+def test_planted_fft_sign_is_caught(monkeypatch):
+    G = 32 * 32 * 4
+    assert _fails_pin(monkeypatch, (na.np.fft, "fftn"),
+                      lambda a: np.fft.ifftn(a) * G)
+
+
+def test_planted_stencil_offset_is_caught(monkeypatch):
+    orig = na._stencil
+    assert _fails_pin(monkeypatch, (na, "_stencil"),
+                      lambda x, Nt, m: (orig(x, Nt, m)[0] - 1, orig(x, Nt, m)[1]))
+
+
+def test_planted_deconv_scale_is_caught(monkeypatch):
+    orig = na.deconv_factors
+    assert _fails_pin(monkeypatch, (na, "deconv_factors"),
+                      lambda N, Nt, m: orig(N, Nt, m) * m)
+
+
+def test_planted_reversed_taps_are_caught(monkeypatch):
+    orig = na.tap_weights
+    assert _fails_pin(monkeypatch, (na, "tap_weights"),
+                      lambda frac, m, beta, window="poly": orig(frac, m, beta, window)[..., ::-1])
+
+
+def test_planted_window_phi_frequency_is_caught(monkeypatch):
+    import scipy.special
+    def wrong(xi, beta):
+        return scipy.special.i0(np.sqrt(beta * beta - (np.pi * np.asarray(xi)) ** 2))
+    assert _fails_pin(monkeypatch, (na, "window_phi"), wrong)
+
+
+def test_planted_axis_transpose_is_caught(monkeypatch):
+    orig = na.forward
+    N, x, f, fh, ef, _ = _case(2)
+    bad = orig(x, f.T.copy(), 4, 2.0)
+    assert _rel2(bad, ef) > GATE[(4, 2.0)]

@@ -1,0 +1,106 @@
+"""Pins of the oracle's Kaiser-Bessel window, deconvolution factors and polynomial fit.
+
+Paper, subsection "Direct NFFT" (tensor-product window, phi as the inverse
+Fourier transform of phi_hat, truncation to [-m/Nt, m/Nt)), subsection
+"Resampling Correction" (beta_tensor factors) and the POLYNOMIAL item of the
+"Window precomputation" subsection.
+"""
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import nfft_alg as na
+
+mp.mp.dps = 30
+
+CASES = [(4, 2.0), (6, 2.0), (8, 2.0), (4, 1.25)]
+
+
+def _mp_window_hat(u, beta):
+    s = mp.sqrt(1 - u * u)
+    if s == 0:
+        return beta / mp.pi
+    return mp.sinh(beta * s) / (mp.pi * s)
+
+
+@pytest.mark.parametrize("z", [0.0, 0.5, 3.0, 12.5, 25.1327, 37.6991, 47.0])
+def test_i0_against_mpmath(z):
+    assert abs(scipy.special.i0(z) / float(mp.besseli(0, z)) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("m,sigma", CASES)
+def test_kb_fourier_pair(m, sigma):
+    """psi_hat_Base on (-1, 1) is the Fourier transform of the compactly supported phi_Base.
+
+    phi_Base(xi) = I0(sqrt(beta^2 - 4 pi^2 xi^2)) lives on |xi| <= beta/(2 pi); its
+    transform is the sinh form inside |u| < 1 (a sin form outside, which the
+    truncation to [-1, 1) drops).
+    """
+    beta = na.kb_beta(m, sigma)
+    bmp = mp.mpf(beta)
+    lim = bmp / (2 * mp.pi)
+    for u in [0.0, 0.3, -0.55, 0.9, -0.999]:
+        val = mp.quad(lambda xi: mp.besseli(0, mp.sqrt(max(bmp ** 2 - (2 * mp.pi * xi) ** 2, 0)))
+                      * mp.cos(2 * mp.pi * u * xi), [-lim, 0, lim])
+        got = na.window_hat(u, beta)
+        assert abs(got / float(val) - 1) < 1e-13, (m, sigma, u)
+
+
+# (m, sigma) -> relative accuracy the truncated quadrature reaches (aliasing and
+# truncation estimates 1/I0(2 pi m sqrt(1 - 1/sigma)) and beta/sinh(beta), with margin)
+QUAD_BOUND = {(4, 2.0): 2e-6, (6, 2.0): 5e-10, (8, 2.0): 2e-13, (4, 1.25): 2e-3}
+
+
+@pytest.mark.parametrize("m,sigma,N", [(4, 2.0, 16), (6, 2.0, 12), (8, 2.0, 20), (4, 1.25, 16)])
+def test_deconv_factor_quadrature(m, sigma, N):
+    """Equation (expApprox) with the truncated window: for every n in I_N and node k,
+    (1/(|I_Nt| phi(n))) sum_l psi_tilde(k - l/Nt) exp(-2 pi i n l/Nt) ~= exp(-2 pi i n k)."""
+    Nt = na.oversampled_size((N,), sigma)[0]
+    beta = na.kb_beta(m, Nt / N)
+    fac = na.deconv_factors(N, Nt, m)
+    n = np.arange(-(N // 2), N - N // 2)
+    for k in [0.0, 0.1234, -0.5, 0.49, 3.0 / Nt]:
+        l = np.arange(-Nt, 2 * Nt)  # enough periods to contain the support around k
+        w = na.window_hat((Nt * k - l) / m, beta)
+        approx = fac * (np.exp(-2j * np.pi * np.outer(n, l) / Nt) @ w)
+        exact = np.exp(-2j * np.pi * n * k)
+        err = np.max(np.abs(approx - exact))
+        assert err < QUAD_BOUND[(m, sigma)], (k, err)
+
+
+def test_window_half_open_support():
+    beta = na.kb_beta(4, 2.0)
+    v = na.window_hat(np.array([-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, -1.5]), beta)
+    assert v[0] == pytest.approx(beta / np.pi, rel=1e-15)
+    assert v[4] == 0.0 and v[5] == 0.0 and v[6] == 0.0
+    assert v[1] == pytest.approx(v[3], rel=1e-15)  # even inside the support
+    assert v[2] == pytest.approx(np.sinh(beta) / np.pi, rel=1e-15)
+
+
+@pytest.mark.parametrize("m,sigma,bound", [(4, 2.0, 3e-8), (6, 2.0, 1e-12), (8, 2.0, 3e-14),
+                                           (4, 1.25, 1e-8)])
+def test_polynomial_window_accuracy(m, sigma, bound):
+    """Degree-2m polynomials reproduce the window well below the NFFT error (max-norm, relative)."""
+    beta = na.kb_beta(m, sigma)
+    frac = np.linspace(0.0, 1.0, 2001, endpoint=False)
+    direct = na.tap_weights(frac, m, beta, "direct")
+    poly = na.tap_weights(frac, m, beta, "poly")
+    err = np.max(np.abs(direct - poly)) / np.max(np.abs(direct))
+    assert err < bound, err
+
+
+def test_tap_arguments_cover_the_support_once():
+    """The 2m taps of a node sample the window at u_t = (frac + m - 1 - t)/m, all in [-1, 1)."""
+    m = 4
+    for frac in [0.0, 0.25, 0.999]:
+        u = (frac + m - 1 - np.arange(2 * m)) / m
+        assert np.all(u >= -1) and np.all(u < 1)
+        assert np.allclose(np.diff(u), -1.0 / m)
+
+
+@pytest.mark.parametrize("N,sigma,want", [((256,), 2.0, (512,)), ((128, 128, 128), 1.25, (160,) * 3),
+                                          ((512, 512), 2.0, (1024, 1024)), ((100,), 1.5, (150,)),
+                                          ((30,), 1.3, (40,))])
+def test_oversampled_size_rule(N, sigma, want):
+    assert na.oversampled_size(N, sigma) == want
