@@ -1,0 +1,157 @@
+/*
+ * libnfft -- nonequispaced fast Fourier transform (NFFT) on one AMD Instinct
+ * MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The transform (Knopp, Boberg, Grosser, "NFFT.jl: Generic and Fast Julia
+ * Implementation of the Nonequidistant Fast Fourier Transform", section
+ * "Mathematical Description"):
+ *
+ *   forward (type 2, Algorithm 1 "Direct NFFT") approximates the NDFT
+ *       fhat_j = sum_{n in I_N} f_n exp(-2 pi i n . x_j),   j = 0..M-1
+ *   adjoint (type 1, Algorithm 2 "Adjoint NFFT") approximates
+ *       y_n    = sum_j fhat_j exp(+2 pi i n . x_j),         n in I_N
+ *
+ * with I_N the centred index set (n_d = -N_d/2 .. N_d/2-1, N_d even), an
+ * oversampled grid Ntilde_d ~= sigma N_d, and a Kaiser-Bessel window truncated to
+ * 2m grid points per axis.  Both are computed as resampling correction
+ * (deconvolution), unnormalised oversampled FFT and window resampling
+ * (interpolation for the forward transform, spreading for the adjoint), in the
+ * matrix form A ~= B F D and A^H ~= D^T F^H B^T of subsection
+ * "Matrix-Vector Notation".  The adjoint is not an inverse.
+ *
+ * Layouts (all device memory, C row-major, last axis fastest):
+ *   x      M*D reals, node-major: x[j*D + d].  float for NFFT_C64, double for
+ *          NFFT_C128.  Any real value is accepted; nodes are taken modulo 1
+ *          (the transform is 1-periodic in x).
+ *   f, y   prod(N) complex values (interleaved re, im), storage index
+ *          i_d = n_d + N_d/2 (centred).
+ *   fhat   M complex values in the caller's node order.
+ *
+ * Ownership: the caller owns x, f, fhat and y.  A plan copies what it needs
+ * from x while it is created and keeps no pointer to it.  The plan owns its
+ * oversampled grid, sorted nodes and precomputed factors.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Transforms
+ * are enqueued asynchronously on it.  Calls on one plan must be ordered (one
+ * stream, or synchronised) because they share the plan's grid; a plan is not
+ * re-entrant.  Plan creation synchronises `stream` before returning.
+ *
+ * Errors: every call returns an int status (NFFT_OK or a negative code) and
+ * never throws.  Arguments are validated before any HIP call, so argument
+ * errors are reported without touching the GPU.
+ */
+#ifndef NFFT_MI355X_H
+#define NFFT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nfft_plan_s *nfft_plan_t;
+
+typedef enum {
+    NFFT_C64 = 0,  /* complex float data, float nodes, FP32 accumulation */
+    NFFT_C128 = 1  /* complex double data, double nodes, FP64 throughout */
+} nfft_dtype;
+
+enum {
+    NFFT_OK = 0,
+    NFFT_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, sigma <= 1, ...) */
+    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (odd N, D > 3, ...) */
+    NFFT_ERR_NOMEM = -3,       /* device allocation failed */
+    NFFT_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch failure, ...) */
+    NFFT_ERR_NODES = -5        /* a node coordinate is NaN or infinite */
+};
+
+/* Window evaluation inside the resampling kernels. */
+enum {
+    NFFT_WINDOW_POLY = 0,   /* piecewise polynomial of degree 2m per tap, least-squares fit
+                               to the Kaiser-Bessel window in FP64 (the paper's POLYNOMIAL
+                               precomputation, subsection "Window precomputation") */
+    NFFT_WINDOW_DIRECT = 1  /* evaluate sinh(beta sqrt(1-u^2)) / (pi sqrt(1-u^2)) per tap
+                               (the paper's "no precomputation" option) */
+};
+
+typedef struct {
+    int tile[3];          /* tile edge per axis in grid points, 0 = automatic.  Must divide
+                             Ntilde_d, be >= 2m and leave >= 2 tiles per axis. */
+    int window;           /* NFFT_WINDOW_POLY (default) or NFFT_WINDOW_DIRECT */
+    int max_block_nodes;  /* cap on nodes per interpolation work item, 0 = automatic */
+    int reserved[5];      /* must be zero */
+} nfft_options;
+
+/*
+ * Create a plan (Algorithm 1/2 inputs D, m, N, Ntilde and the nodes).
+ *   out    receives the plan handle (unchanged on error)
+ *   D      1, 2 or 3
+ *   N      host array of D even sizes >= 2
+ *   M      number of nodes, >= 0 (M = 0 is allowed)
+ *   x      device pointer to the nodes (may be NULL when M == 0)
+ *   m      window half-width, 1..10 (the range the paper studies is 3..10)
+ *   sigma  oversampling factor > 1; Ntilde_d is the smallest even integer >=
+ *          sigma N_d whose prime factors are 2, 3 and 5 (see nfft_plan_info)
+ *   dtype  NFFT_C64 or NFFT_C128
+ *   opts   NULL for defaults (nfft_plan_create_ex only)
+ * Work done on `stream`: FP64 Kaiser-Bessel deconvolution factors and window
+ * polynomial, node wrap / cell / fraction in FP64, GPU bin sort of the nodes
+ * into grid tiles.  Returns NFFT_ERR_NODES if a node is NaN or infinite.
+ */
+int nfft_plan_create(nfft_plan_t *out, int D, const int64_t *N, int64_t M, const void *x,
+                     int m, double sigma, nfft_dtype dtype, void *stream);
+int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, const void *x,
+                        int m, double sigma, nfft_dtype dtype, const nfft_options *opts,
+                        void *stream);
+
+/* Release a plan and its device memory (waits for work queued on the plan's grid
+ * by synchronising the device).  NULL is accepted. */
+int nfft_plan_destroy(nfft_plan_t p);
+
+/*
+ * Forward NFFT (Algorithm 1): fhat = B F D f.  f: prod(N) complex (device),
+ * fhat: M complex (device), overwritten (mul! semantics).  With M == 0 nothing
+ * is computed.
+ */
+int nfft_forward(nfft_plan_t p, const void *f, void *fhat, void *stream);
+
+/*
+ * Adjoint NFFT (Algorithm 2): y = D^T F^H B^T fhat.  fhat: M complex (device),
+ * y: prod(N) complex (device), overwritten.  With M == 0, y is set to zero.
+ */
+int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream);
+
+/*
+ * The single steps, for step-wise checking and timing.  `grid` is a device
+ * array of prod(Ntilde) complex values, row-major, storage index l mod Ntilde
+ * (DC first).
+ *   nfft_resample_forward : fhat_j = sum_l ghat_l psi_tilde(x_j - l/Ntilde)
+ *                           (Algorithm 1, resampling step; reads grid)
+ *   nfft_resample_adjoint : ghat_l = sum_j fhat_j psi_tilde(x_j - l/Ntilde)
+ *                           (Algorithm 2, adjoint resampling; overwrites grid)
+ *   nfft_fft_grid         : unnormalised D-variate FFT of grid in place;
+ *                           direction -1 = forward (exp(-2 pi i n.l/Ntilde)),
+ *                           +1 = adjoint (exp(+2 pi i ...)).
+ */
+int nfft_resample_forward(nfft_plan_t p, const void *grid, void *fhat, void *stream);
+int nfft_resample_adjoint(nfft_plan_t p, const void *fhat, void *grid, void *stream);
+int nfft_fft_grid(nfft_plan_t p, void *grid, int direction, void *stream);
+
+/*
+ * Introspection.  Ntilde receives D sizes, sigma_eff = Ntilde_0 / N_0, tile receives
+ * D tile edges (any output pointer may be NULL).
+ */
+int nfft_plan_info(nfft_plan_t p, int64_t *Ntilde, double *sigma_eff, int *tile);
+
+/* Device pointer to the plan's oversampled grid (prod(Ntilde) complex): after
+ * nfft_forward it holds ghat = F D f, after nfft_adjoint it is scratch. */
+int nfft_plan_grid(nfft_plan_t p, void **grid);
+
+/* Static description of an error code (never NULL). */
+const char *nfft_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFFT_MI355X_H */

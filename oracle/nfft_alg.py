@@ -13,7 +13,8 @@ Notation (paper, section "Mathematical Description"):
 * coefficients ``f`` on the centred index set I_N, stored row-major with
   storage index i_d = n_d + N_d/2.
 
-Window (readings stated in the design doc): Kaiser-Bessel with shape parameter
+Window (the paper names the Kaiser-Bessel pair without formulas; this is the
+notation of its reference for the NFFT): Kaiser-Bessel with shape parameter
 beta_d = pi * m * (2 - 1/sigma_d), sigma_d = Nt_d / N_d.
 
 * convolution side, psi_hat_Base(u) = sinh(beta sqrt(1-u^2)) / (pi sqrt(1-u^2))
@@ -181,16 +182,7 @@ def forward(x, f, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False):
     ghat = np.fft.fftn(g)
 
     # step 3: fhat_j = sum over the (2m)^D stencil of prod_d w_d * ghat[l mod Nt]
-    origin, ws = _weights_per_axis(x, N, Nt, m, window)
-    J = x.shape[0]
-    fhat = np.zeros(J, dtype=np.complex128)
-    for taps in np.ndindex(*([2 * m] * D)):
-        w = np.ones(J)
-        flat = np.zeros(J, dtype=np.int64)
-        for d in range(D):
-            w = w * ws[d][:, taps[d]]
-            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
-        fhat += w * ghat.reshape(-1)[flat]
+    fhat = resample_forward(x, ghat, N, m, Nt, window)
     if return_steps:
         return fhat, {"g": g, "ghat": ghat, "Nt": Nt}
     return fhat
@@ -203,23 +195,10 @@ def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=Fal
     Nt = oversampled_size(N, sigma) if Nt is None else tuple(Nt)
     x = np.asarray(x, dtype=np.float64).reshape(-1, D)
     fhat = np.asarray(fhat, dtype=np.complex128).reshape(-1)
-    J = x.shape[0]
     G = int(np.prod(Nt))
 
     # step 1: ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt)
-    origin, ws = _weights_per_axis(x, N, Nt, m, window)
-    acc_re = np.zeros(G)
-    acc_im = np.zeros(G)
-    for taps in np.ndindex(*([2 * m] * D)):
-        w = np.ones(J)
-        flat = np.zeros(J, dtype=np.int64)
-        for d in range(D):
-            w = w * ws[d][:, taps[d]]
-            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
-        v = w * fhat
-        acc_re += np.bincount(flat, weights=v.real, minlength=G)
-        acc_im += np.bincount(flat, weights=v.imag, minlength=G)
-    ghat = (acc_re + 1j * acc_im).reshape(Nt)
+    ghat = resample_adjoint(x, fhat, N, m, Nt, window)
 
     # step 2: g_n = sum_l ghat_l exp(+2 pi i n.l/Nt)  (unnormalised)
     g = np.fft.ifftn(ghat) * G
@@ -233,3 +212,50 @@ def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=Fal
     if return_steps:
         return y, {"ghat": ghat, "g": g, "Nt": Nt}
     return y
+
+
+def resample_forward(x, ghat, N, m, Nt, window="poly"):
+    """Resampling of Algorithm 1 (step 3): fhat_j = sum_l ghat_l psi_tilde(x_j - l/Nt).
+
+    ``ghat`` is the oversampled grid in storage order (index l mod Nt).
+    """
+    N = tuple(int(v) for v in N)
+    D = len(N)
+    Nt = tuple(int(v) for v in Nt)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, D)
+    origin, ws = _weights_per_axis(x, N, Nt, m, window)
+    J = x.shape[0]
+    flat_g = np.asarray(ghat, dtype=np.complex128).reshape(-1)
+    fhat = np.zeros(J, dtype=np.complex128)
+    for taps in np.ndindex(*([2 * m] * D)):
+        w = np.ones(J)
+        flat = np.zeros(J, dtype=np.int64)
+        for d in range(D):
+            w = w * ws[d][:, taps[d]]
+            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
+        fhat += w * flat_g[flat]
+    return fhat
+
+
+def resample_adjoint(x, fhat, N, m, Nt, window="poly"):
+    """Adjoint resampling of Algorithm 2 (step 1): ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt)."""
+    N = tuple(int(v) for v in N)
+    D = len(N)
+    Nt = tuple(int(v) for v in Nt)
+    x = np.asarray(x, dtype=np.float64).reshape(-1, D)
+    fhat = np.asarray(fhat, dtype=np.complex128).reshape(-1)
+    origin, ws = _weights_per_axis(x, N, Nt, m, window)
+    J = x.shape[0]
+    G = int(np.prod(Nt))
+    acc_re = np.zeros(G)
+    acc_im = np.zeros(G)
+    for taps in np.ndindex(*([2 * m] * D)):
+        w = np.ones(J)
+        flat = np.zeros(J, dtype=np.int64)
+        for d in range(D):
+            w = w * ws[d][:, taps[d]]
+            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
+        v = w * fhat
+        acc_re += np.bincount(flat, weights=v.real, minlength=G)
+        acc_im += np.bincount(flat, weights=v.imag, minlength=G)
+    return (acc_re + 1j * acc_im).reshape(Nt)

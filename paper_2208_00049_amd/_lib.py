@@ -1,0 +1,83 @@
+"""ctypes loader for libnfft.so (argument marshalling only).
+
+Raises ``RuntimeError`` when the shared library has not been built: there is no
+fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnfft.so")
+
+# names and status codes of include/nfft.h
+NFFT_OK = 0
+NFFT_ERR_ARG = -1
+NFFT_ERR_UNSUPPORTED = -2
+NFFT_ERR_NOMEM = -3
+NFFT_ERR_HIP = -4
+NFFT_ERR_NODES = -5
+NFFT_C64 = 0
+NFFT_C128 = 1
+NFFT_WINDOW_POLY = 0
+NFFT_WINDOW_DIRECT = 1
+
+EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft_forward",
+           "nfft_adjoint", "nfft_resample_forward", "nfft_resample_adjoint", "nfft_fft_grid",
+           "nfft_plan_info", "nfft_plan_grid", "nfft_strerror"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int * 3), ("window", ctypes.c_int),
+                ("max_block_nodes", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+
+
+class NfftError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, strerror(code), code))
+
+
+_lib = None
+
+
+def load():
+    """Load libnfft.so once and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libnfft.so is not built (%s); run paper_2208_00049_amd/build.py "
+                           "or __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    plan_p = ctypes.POINTER(ctypes.c_void_p)
+    lib.nfft_plan_create.argtypes = [plan_p, ctypes.c_int, i64p, ctypes.c_int64, vp, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, vp]
+    lib.nfft_plan_create_ex.argtypes = [plan_p, ctypes.c_int, i64p, ctypes.c_int64, vp,
+                                        ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                        ctypes.POINTER(Options), vp]
+    lib.nfft_plan_destroy.argtypes = [vp]
+    lib.nfft_forward.argtypes = [vp, vp, vp, vp]
+    lib.nfft_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.nfft_resample_forward.argtypes = [vp, vp, vp, vp]
+    lib.nfft_resample_adjoint.argtypes = [vp, vp, vp, vp]
+    lib.nfft_fft_grid.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.nfft_plan_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int)]
+    lib.nfft_plan_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.nfft_strerror.argtypes = [ctypes.c_int]
+    lib.nfft_strerror.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "nfft_strerror":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().nfft_strerror(int(code)).decode()
+
+
+def check(code: int, where: str) -> None:
+    if code != NFFT_OK:
+        raise NfftError(code, where)

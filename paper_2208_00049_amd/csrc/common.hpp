@@ -1,0 +1,42 @@
+// Device-side helpers shared by the libnfft kernels: complex arithmetic on
+// float2/double2 and the per-type traits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nfft {
+
+template <typename T> struct ctype;
+template <> struct ctype<float> { using type = float2; };
+template <> struct ctype<double> { using type = double2; };
+template <typename T> using cplx = typename ctype<T>::type;
+
+template <typename C> __host__ __device__ inline C cmake(decltype(C::x) re, decltype(C::x) im) {
+    C v;
+    v.x = re;
+    v.y = im;
+    return v;
+}
+template <typename C> __device__ inline C cadd(C a, C b) { return cmake<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ inline C csub(C a, C b) { return cmake<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ inline C cmul(C a, C b) {
+    return cmake<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename C> __device__ inline C cmulc(C a, C b) {
+    return cmake<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename C, typename T> __device__ inline C cscale(C a, T s) { return cmake<C>(a.x * s, a.y * s); }
+// multiply by s*i, s = +1 or -1
+template <typename C> __device__ inline C cmul_si(C a, int s) {
+    return s > 0 ? cmake<C>(-a.y, a.x) : cmake<C>(a.y, -a.x);
+}
+
+// Position on the oversampled axis of the r-th entry of the centred index set
+// I_N (n = r - N/2), i.e. (n mod Nt): r < N/2 -> Nt - N/2 + r, else r - N/2.
+__host__ __device__ inline int band_pos(int r, int N, int Nt) {
+    return r < N / 2 ? Nt - N / 2 + r : r - N / 2;
+}
+
+}  // namespace nfft

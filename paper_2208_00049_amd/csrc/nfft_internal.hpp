@@ -1,0 +1,125 @@
+// Internal interfaces of libnfft: the plan object and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nfft.h"
+
+namespace nfft {
+
+constexpr int kMaxD = 3;
+constexpr int kMaxRadixPasses = 16;
+
+// Geometry of the oversampled grid and of its tiling, passed by value to kernels.
+struct Geom {
+    int D;
+    int m;
+    int Nt[kMaxD];   // oversampled size per axis
+    int Q[kMaxD];    // tile edge per axis (divides Nt)
+    int T[kMaxD];    // tiles per axis = Nt / Q
+    int ntiles;      // prod T
+};
+
+// Sorted node record: stencil origin (c - m + 1) mod Nt per axis and the
+// fractional cell offset frac = Nt*x - floor(Nt*x) in [0, 1).
+template <typename T, int D> struct NodeRec {
+    int o[D];
+    T fr[D];
+};
+
+// Factorisation of one FFT line length and its twiddle table exp(-2 pi i t / L).
+struct FftLine {
+    int L;
+    int npass;
+    int rad[kMaxRadixPasses];
+    int tpl;              // threads per line = L / largest radix
+    const void *tw;       // device, L complex values of the plan's type
+};
+
+// One axis pass of the oversampled FFT over a grid viewed as [outer][L][inner].
+struct AxisPass {
+    int axis;
+    int inner;            // prod of Nt over the axes after `axis` (> 1: strided pass)
+    int outer_len;        // number of outer (prefix) positions processed
+    int outer_band_N;     // 0: outer positions are 0..outer_len-1; else band of I_N (N = this)
+    int outer_Nt;         // oversampled size of the outer axis (band case)
+    long long outer_stride;  // elements between consecutive outer positions
+    int in_band_N;        // 0: load the whole line; else only the band rows (others are zero)
+    int out_band_N;       // 0: store the whole line; else only the band rows
+    int lines_per_block;  // B
+    int dir;              // -1 forward, +1 adjoint
+};
+
+// Last-axis pass with the resampling correction fused in.
+struct ContigPass {
+    int mode;             // 0 plain grid->grid, 1 f -> grid (deconv + pad), 2 grid -> y (crop + deconv)
+    int D;
+    int nlines;           // number of lines processed
+    int outer_len[2];     // lengths of the outer axes 0..D-2 as enumerated
+    int outer_band[2];    // per outer axis: 1 = band of I_N, 0 = full
+    int N[kMaxD];
+    int Nt[kMaxD];
+    int lines_per_block;
+    int dir;
+};
+
+}  // namespace nfft
+
+struct nfft_plan_s {
+    int D;
+    int64_t N[nfft::kMaxD];
+    int64_t Nt[nfft::kMaxD];
+    int64_t M;
+    int m;
+    double sigma;
+    nfft_dtype dtype;
+    int window;
+    int max_block_nodes;
+    nfft::Geom geom;
+    int64_t G;            // prod Nt
+    int nkeys;            // ntiles << D
+    int nsub;             // interpolation work items
+    int device;
+
+    // device buffers
+    void *grid = nullptr;          // G complex
+    void *deconv[nfft::kMaxD] = {nullptr, nullptr, nullptr};  // N_d reals (plan type)
+    void *coef = nullptr;          // 2m x (2m+1) reals (plan type), window polynomial
+    void *nodes = nullptr;         // M sorted NodeRec
+    int *perm = nullptr;           // M: sorted position -> caller's node index
+    int *key_start = nullptr;      // nkeys + 1
+    int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}
+    void *twiddle[nfft::kMaxD] = {nullptr, nullptr, nullptr};
+    nfft::FftLine line[nfft::kMaxD];
+};
+
+namespace nfft {
+
+// precompute.hip
+hipError_t launch_deconv_factors(const nfft_plan_s &p, hipStream_t s);
+hipError_t launch_window_poly(const nfft_plan_s &p, const double *qt, const double *r, int Z,
+                              int Theta, hipStream_t s);
+hipError_t launch_twiddles(const nfft_plan_s &p, int axis, hipStream_t s);
+
+// binsort.hip
+hipError_t launch_fill_int(int *a, int64_t n, int v, hipStream_t s);
+hipError_t launch_fill_zero_complex(void *a, int64_t n, bool dbl, hipStream_t s);
+hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int *counts, int *bad,
+                            hipStream_t s);
+hipError_t launch_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
+hipError_t launch_node_scatter(nfft_plan_s &p, const void *x, const int *keys, int *cursor,
+                               hipStream_t s);
+hipError_t launch_subprob_count(const nfft_plan_s &p, int *counts, hipStream_t s);
+hipError_t launch_subprob_fill(nfft_plan_s &p, const int *sub_start, hipStream_t s);
+
+// fft.hip
+hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, hipStream_t s);
+hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, const ContigPass &c,
+                             hipStream_t s);
+
+// resample.hip
+hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s);
+hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s);
+
+}  // namespace nfft

@@ -1,0 +1,624 @@
+// libnfft host side: argument validation, plan construction and the C ABI.
+//
+// Forward transform (paper, Algorithm 1): resampling correction + zero padding
+// (fused into the last-axis FFT pass), D-variate FFT, interpolation.
+// Adjoint (Algorithm 2): spreading, D-variate adjoint FFT, crop + resampling
+// correction (fused into the last-axis FFT pass).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "nfft_internal.hpp"
+
+using namespace nfft;
+
+namespace {
+
+constexpr int kMaxM = 10;
+constexpr size_t kLdsBudget = 65536;
+constexpr int kDefaultBlockNodes = 1024;
+
+bool is_235_smooth(int64_t v) {
+    for (int p : {2, 3, 5})
+        while (v % p == 0) v /= p;
+    return v == 1;
+}
+
+// Smallest even integer >= sigma*N whose prime factors are 2, 3 and 5 (the paper
+// writes Ntilde = sigma N without saying how a non-integer product is rounded).
+int64_t oversampled(int64_t N, double sigma) {
+    const double target = sigma * (double)N;
+    int64_t c = (int64_t)ceil(target - 1e-9 * target);
+    if (c % 2) ++c;
+    while (!is_235_smooth(c)) c += 2;
+    return c;
+}
+
+size_t csize(nfft_dtype t) { return t == NFFT_C64 ? 8 : 16; }
+size_t rsize(nfft_dtype t) { return t == NFFT_C64 ? 4 : 8; }
+
+size_t node_rec_size(nfft_dtype t, int D) {
+    if (t == NFFT_C64) {
+        switch (D) {
+            case 1: return sizeof(NodeRec<float, 1>);
+            case 2: return sizeof(NodeRec<float, 2>);
+            default: return sizeof(NodeRec<float, 3>);
+        }
+    }
+    switch (D) {
+        case 1: return sizeof(NodeRec<double, 1>);
+        case 2: return sizeof(NodeRec<double, 2>);
+        default: return sizeof(NodeRec<double, 3>);
+    }
+}
+
+// Factor the line length into Stockham passes (radix 8 first, then 4 or 2, 5, 3).
+bool factor_line(int L, FftLine &fl) {
+    int v = L, np = 0, e2 = 0;
+    while (v % 2 == 0) {
+        v /= 2;
+        ++e2;
+    }
+    while (e2 >= 3) {
+        fl.rad[np++] = 8;
+        e2 -= 3;
+    }
+    if (e2 == 2) fl.rad[np++] = 4;
+    if (e2 == 1) fl.rad[np++] = 2;
+    while (v % 5 == 0) {
+        fl.rad[np++] = 5;
+        v /= 5;
+    }
+    while (v % 3 == 0) {
+        fl.rad[np++] = 3;
+        v /= 3;
+    }
+    if (v != 1 || np > kMaxRadixPasses || np == 0) return false;
+    int rmax = 0;
+    for (int i = 0; i < np; ++i) rmax = std::max(rmax, fl.rad[i]);
+    fl.L = L;
+    fl.npass = np;
+    fl.tpl = L / rmax;
+    return fl.tpl <= 1024;
+}
+
+size_t interp_lds(const int *Q, int D, int m, size_t cs) {
+    size_t t = cs;
+    for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + 2 * m - 1);
+    return t;
+}
+
+bool valid_tile(int64_t Nt, int Q, int m) {
+    return Q >= 2 * m && Q > 0 && Nt % Q == 0 && Nt / Q >= 2;
+}
+
+// Largest valid tile edge <= want (a divisor of Nt, >= 2m, >= 2 tiles).
+int pick_edge_down(int64_t Nt, int want, int m) {
+    for (int q = std::min<int64_t>(want, Nt / 2); q >= 2 * m; --q)
+        if (valid_tile(Nt, q, m)) return q;
+    return 0;
+}
+
+// Valid tile edge closest to want: the largest one <= want, else the smallest one above.
+int pick_edge(int64_t Nt, int want, int m) {
+    const int q = pick_edge_down(Nt, want, m);
+    if (q) return q;
+    for (int v = std::max(want, 2 * m); v <= Nt / 2; ++v)
+        if (valid_tile(Nt, v, m)) return v;
+    return 0;
+}
+
+int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req, size_t budget,
+                 int *Q) {
+    const size_t cs = csize(dt);
+    if (req && (req[0] || req[1] || req[2])) {
+        for (int d = 0; d < D; ++d) {
+            if (!valid_tile(Nt[d], req[d], m)) return NFFT_ERR_ARG;
+            Q[d] = req[d];
+        }
+        return interp_lds(Q, D, m, cs) <= budget ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
+    }
+    int want[3];
+    if (D == 1) want[0] = 256;
+    else if (D == 2) want[0] = want[1] = 32;
+    else {
+        want[0] = 8;
+        want[1] = want[2] = 16;
+    }
+    for (int d = 0; d < D; ++d) {
+        Q[d] = pick_edge(Nt[d], std::max(want[d], 2 * m), m);
+        if (!Q[d]) return NFFT_ERR_UNSUPPORTED;
+    }
+    // shrink the largest edge until the interpolation tile (with halo) fits in LDS
+    while (interp_lds(Q, D, m, cs) > budget) {
+        int best = -1;
+        for (int d = 0; d < D; ++d) {
+            const int q = pick_edge_down(Nt[d], Q[d] - 1, m);
+            if (q && (best < 0 || Q[d] > Q[best])) best = d;
+        }
+        if (best < 0) return NFFT_ERR_UNSUPPORTED;
+        Q[best] = pick_edge_down(Nt[best], Q[best] - 1, m);
+    }
+    return NFFT_OK;
+}
+
+// Householder QR of the Theta x Z Vandermonde matrix in s in [-1, 1]; returns
+// Q^T (Z x Theta) and R (Z x Z, upper triangular), row-major.
+void vandermonde_qr(int Z, int Theta, std::vector<double> &qt, std::vector<double> &r) {
+    std::vector<double> A((size_t)Theta * Z), V((size_t)Theta * Z, 0.0);
+    for (int v = 0; v < Theta; ++v) {
+        const double s = -1.0 + 2.0 * v / (double)(Theta - 1);
+        double pw = 1.0;
+        for (int z = 0; z < Z; ++z) {
+            A[(size_t)v * Z + z] = pw;
+            pw *= s;
+        }
+    }
+    for (int k = 0; k < Z; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < Theta; ++i) nrm += A[(size_t)i * Z + k] * A[(size_t)i * Z + k];
+        nrm = sqrt(nrm);
+        const double x0 = A[(size_t)k * Z + k];
+        const double alpha = x0 >= 0 ? -nrm : nrm;
+        double vn = 0.0;
+        for (int i = k; i < Theta; ++i) {
+            const double vi = A[(size_t)i * Z + k] - (i == k ? alpha : 0.0);
+            V[(size_t)i * Z + k] = vi;
+            vn += vi * vi;
+        }
+        vn = sqrt(vn);
+        if (vn > 0)
+            for (int i = k; i < Theta; ++i) V[(size_t)i * Z + k] /= vn;
+        for (int j = k; j < Z; ++j) {
+            double dot = 0.0;
+            for (int i = k; i < Theta; ++i) dot += V[(size_t)i * Z + k] * A[(size_t)i * Z + j];
+            for (int i = k; i < Theta; ++i) A[(size_t)i * Z + j] -= 2.0 * V[(size_t)i * Z + k] * dot;
+        }
+    }
+    r.assign((size_t)Z * Z, 0.0);
+    for (int i = 0; i < Z; ++i)
+        for (int j = i; j < Z; ++j) r[(size_t)i * Z + j] = A[(size_t)i * Z + j];
+    // thin Q = H_0 ... H_{Z-1} applied to the first Z unit vectors
+    std::vector<double> E((size_t)Theta * Z, 0.0);
+    for (int i = 0; i < Z; ++i) E[(size_t)i * Z + i] = 1.0;
+    for (int k = Z - 1; k >= 0; --k) {
+        for (int j = 0; j < Z; ++j) {
+            double dot = 0.0;
+            for (int i = k; i < Theta; ++i) dot += V[(size_t)i * Z + k] * E[(size_t)i * Z + j];
+            for (int i = k; i < Theta; ++i) E[(size_t)i * Z + j] -= 2.0 * V[(size_t)i * Z + k] * dot;
+        }
+    }
+    qt.assign((size_t)Z * Theta, 0.0);
+    for (int i = 0; i < Theta; ++i)
+        for (int j = 0; j < Z; ++j) qt[(size_t)j * Theta + i] = E[(size_t)i * Z + j];
+}
+
+int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double sigma, int dtype,
+             const nfft_options *opts) {
+    if (D < 1) return NFFT_ERR_ARG;
+    if (D > kMaxD) return NFFT_ERR_UNSUPPORTED;
+    if (!N) return NFFT_ERR_ARG;
+    if (M < 0 || (M > 0 && !x)) return NFFT_ERR_ARG;
+    if (M >= (int64_t)1 << 31) return NFFT_ERR_UNSUPPORTED;
+    if (m < 1) return NFFT_ERR_ARG;
+    if (m > kMaxM) return NFFT_ERR_UNSUPPORTED;
+    if (!(sigma > 1.0) || !isfinite(sigma) || sigma > 16.0) return NFFT_ERR_ARG;
+    if (dtype != NFFT_C64 && dtype != NFFT_C128) return NFFT_ERR_ARG;
+    int64_t G = 1;
+    for (int d = 0; d < D; ++d) {
+        if (N[d] < 2) return NFFT_ERR_ARG;
+        if (N[d] % 2) return NFFT_ERR_UNSUPPORTED;
+        const int64_t Nt = oversampled(N[d], sigma);
+        if (Nt < 4 * m) return NFFT_ERR_ARG;
+        if (Nt > (dtype == NFFT_C64 ? 4096 : 2048)) return NFFT_ERR_UNSUPPORTED;
+        G *= Nt;
+        if (G >= ((int64_t)1 << 31)) return NFFT_ERR_UNSUPPORTED;
+    }
+    if (opts) {
+        if (opts->window != NFFT_WINDOW_POLY && opts->window != NFFT_WINDOW_DIRECT) return NFFT_ERR_ARG;
+        if (opts->max_block_nodes < 0) return NFFT_ERR_ARG;
+        for (int i = 0; i < 5; ++i)
+            if (opts->reserved[i]) return NFFT_ERR_ARG;
+        for (int d = 0; d < 3; ++d)
+            if (opts->tile[d] < 0 || (d >= D && opts->tile[d] != 0)) return NFFT_ERR_ARG;
+    }
+    return NFFT_OK;
+}
+
+void release(nfft_plan_s *p) {
+    if (!p) return;
+    (void)hipFree(p->grid);
+    for (int d = 0; d < kMaxD; ++d) {
+        (void)hipFree(p->deconv[d]);
+        (void)hipFree(p->twiddle[d]);
+    }
+    (void)hipFree(p->coef);
+    (void)hipFree(p->nodes);
+    (void)hipFree(p->perm);
+    (void)hipFree(p->key_start);
+    (void)hipFree(p->subs);
+    delete p;
+}
+
+int hip_rc(hipError_t e) {
+    if (e == hipSuccess) return NFFT_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return NFFT_ERR_NOMEM;
+    return NFFT_ERR_HIP;
+}
+
+#define TRY(expr)                         \
+    do {                                  \
+        hipError_t e_ = (expr);           \
+        if (e_ != hipSuccess) {           \
+            rc = hip_rc(e_);              \
+            goto fail;                    \
+        }                                 \
+    } while (0)
+
+int lines_per_block_contig(const FftLine &fl, size_t cs) {
+    int B = std::max(1, 256 / fl.tpl);
+    while (B > 1 && (size_t)B * (fl.L + 1) * cs > kLdsBudget) --B;
+    return B;
+}
+
+int lines_per_block_strided(const FftLine &fl, size_t cs, int64_t inner) {
+    int B = 16;
+    while (B > 1 && ((size_t)B * (fl.L + 1) * cs > kLdsBudget || B * fl.tpl > 1024 || B > inner)) B /= 2;
+    return B;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nfft_strerror(int code) {
+    switch (code) {
+        case NFFT_OK: return "success";
+        case NFFT_ERR_ARG: return "invalid argument";
+        case NFFT_ERR_UNSUPPORTED: return "unsupported configuration";
+        case NFFT_ERR_NOMEM: return "device memory allocation failed";
+        case NFFT_ERR_HIP: return "HIP runtime error";
+        case NFFT_ERR_NODES: return "node coordinate is NaN or infinite";
+        default: return "unknown error";
+    }
+}
+
+int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, const void *x, int m,
+                        double sigma, nfft_dtype dtype, const nfft_options *opts, void *stream) {
+    if (!out) return NFFT_ERR_ARG;
+    int rc = validate(D, N, M, x, m, sigma, (int)dtype, opts);
+    if (rc != NFFT_OK) return rc;
+
+    nfft_plan_s *p = new nfft_plan_s();
+    p->D = D;
+    p->M = M;
+    p->m = m;
+    p->sigma = sigma;
+    p->dtype = dtype;
+    p->window = opts ? opts->window : NFFT_WINDOW_POLY;
+    p->max_block_nodes = (opts && opts->max_block_nodes) ? opts->max_block_nodes : kDefaultBlockNodes;
+    p->G = 1;
+    for (int d = 0; d < kMaxD; ++d) {
+        p->N[d] = d < D ? N[d] : 1;
+        p->Nt[d] = d < D ? oversampled(N[d], sigma) : 1;
+        if (d < D) p->G *= p->Nt[d];
+    }
+    for (int d = 0; d < D; ++d) {
+        if (!factor_line((int)p->Nt[d], p->line[d])) {
+            delete p;
+            return NFFT_ERR_UNSUPPORTED;
+        }
+    }
+
+    // ---- device work (everything above touched no HIP API) ----
+    hipStream_t s = (hipStream_t)stream;
+    const size_t cs = csize(dtype), rs = rsize(dtype);
+    const int Z = 2 * m + 1, Theta = 2 * Z;
+    int *keys = nullptr, *counts = nullptr, *cursor = nullptr, *bad = nullptr, *subcnt = nullptr,
+        *substart = nullptr;
+    double *polyscratch = nullptr;
+    int host_bad = 0, host_nsub = 0;
+    std::vector<double> qt, rr;
+    int64_t subs_cap = 0;
+
+    TRY(hipGetDevice(&p->device));
+    {
+        // tiles: prefer a 64 KiB LDS footprint, go up to the device limit if needed
+        int dev_lds = 0;
+        TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+        int Q[3] = {1, 1, 1};
+        const int *req = opts ? opts->tile : nullptr;
+        int trc = choose_tiles(D, p->Nt, m, dtype, req, kLdsBudget, Q);
+        if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds > kLdsBudget)
+            trc = choose_tiles(D, p->Nt, m, dtype, req, (size_t)dev_lds - 1024, Q);
+        if (trc != NFFT_OK) {
+            rc = trc;
+            goto fail;
+        }
+        p->geom.D = D;
+        p->geom.m = m;
+        p->geom.ntiles = 1;
+        for (int d = 0; d < kMaxD; ++d) {
+            p->geom.Nt[d] = (int)p->Nt[d];
+            p->geom.Q[d] = d < D ? Q[d] : 1;
+            p->geom.T[d] = d < D ? (int)(p->Nt[d] / Q[d]) : 1;
+            p->geom.ntiles *= p->geom.T[d];
+        }
+        p->nkeys = p->geom.ntiles << D;
+        subs_cap = p->geom.ntiles + M / p->max_block_nodes + 1;
+    }
+    TRY(hipMalloc(&p->grid, (size_t)p->G * cs));
+    for (int d = 0; d < D; ++d) {
+        TRY(hipMalloc(&p->deconv[d], (size_t)p->N[d] * rs));
+        TRY(hipMalloc(&p->twiddle[d], (size_t)p->Nt[d] * cs));
+        p->line[d].tw = p->twiddle[d];
+    }
+    TRY(hipMalloc(&p->coef, (size_t)D * 2 * m * Z * rs));
+    TRY(hipMalloc(&p->key_start, (size_t)(p->nkeys + 1) * sizeof(int)));
+    TRY(hipMalloc(&p->subs, (size_t)subs_cap * sizeof(int4)));
+    TRY(hipMalloc(&counts, (size_t)(p->nkeys + 1) * sizeof(int)));
+    TRY(hipMalloc(&bad, sizeof(int)));
+    TRY(hipMalloc(&subcnt, (size_t)(p->geom.ntiles + 1) * sizeof(int)));
+    TRY(hipMalloc(&substart, (size_t)(p->geom.ntiles + 1) * sizeof(int)));
+    if (M > 0) {
+        TRY(hipMalloc(&p->nodes, (size_t)M * node_rec_size(dtype, D)));
+        TRY(hipMalloc(&p->perm, (size_t)M * sizeof(int)));
+        TRY(hipMalloc(&keys, (size_t)M * sizeof(int)));
+        TRY(hipMalloc(&cursor, (size_t)(p->nkeys + 1) * sizeof(int)));
+    }
+
+    // FP64 precomputation: deconvolution factors, window polynomial, twiddles
+    TRY(launch_deconv_factors(*p, s));
+    vandermonde_qr(Z, Theta, qt, rr);
+    {
+        std::vector<double> host((size_t)Z * Theta + (size_t)Z * Z + kMaxD);
+        std::copy(qt.begin(), qt.end(), host.begin());
+        std::copy(rr.begin(), rr.end(), host.begin() + (size_t)Z * Theta);
+        for (int d = 0; d < kMaxD; ++d)
+            host[(size_t)Z * Theta + (size_t)Z * Z + d] =
+                d < D ? M_PI * m * (2.0 - (double)p->N[d] / (double)p->Nt[d]) : 0.0;
+        TRY(hipMalloc(&polyscratch, host.size() * sizeof(double)));
+        TRY(hipMemcpyAsync(polyscratch, host.data(), host.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+        TRY(launch_window_poly(*p, polyscratch, polyscratch + (size_t)Z * Theta, Z, Theta, s));
+        // the host vector must outlive the asynchronous copy
+        TRY(hipStreamSynchronize(s));
+    }
+    for (int d = 0; d < D; ++d) TRY(launch_twiddles(*p, d, s));
+
+    // GPU bin sort of the nodes into tiles
+    TRY(launch_fill_int(counts, p->nkeys + 1, 0, s));
+    TRY(launch_fill_int(bad, 1, 0, s));
+    TRY(launch_node_keys(*p, x, keys, counts, bad, s));
+    TRY(launch_exclusive_scan(counts, p->key_start, p->nkeys, s));
+    if (M > 0) {
+        TRY(hipMemcpyAsync(cursor, p->key_start, (size_t)(p->nkeys + 1) * sizeof(int),
+                           hipMemcpyDeviceToDevice, s));
+        TRY(launch_node_scatter(*p, x, keys, cursor, s));
+    }
+    TRY(launch_subprob_count(*p, subcnt, s));
+    TRY(launch_exclusive_scan(subcnt, substart, p->geom.ntiles, s));
+    TRY(launch_subprob_fill(*p, substart, s));
+    TRY(hipMemcpyAsync(&host_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(&host_nsub, substart + p->geom.ntiles, sizeof(int), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    p->nsub = host_nsub;
+    if (host_bad) rc = NFFT_ERR_NODES;
+
+fail:
+    (void)hipFree(keys);
+    (void)hipFree(counts);
+    (void)hipFree(cursor);
+    (void)hipFree(bad);
+    (void)hipFree(subcnt);
+    (void)hipFree(substart);
+    (void)hipFree(polyscratch);
+    if (rc != NFFT_OK) {
+        release(p);
+        return rc;
+    }
+    *out = p;
+    return NFFT_OK;
+}
+
+int nfft_plan_create(nfft_plan_t *out, int D, const int64_t *N, int64_t M, const void *x, int m,
+                     double sigma, nfft_dtype dtype, void *stream) {
+    return nfft_plan_create_ex(out, D, N, M, x, m, sigma, dtype, nullptr, stream);
+}
+
+int nfft_plan_destroy(nfft_plan_t p) {
+    if (!p) return NFFT_OK;
+    hipError_t e = hipDeviceSynchronize();
+    release(p);
+    return hip_rc(e);
+}
+
+int nfft_plan_info(nfft_plan_t p, int64_t *Ntilde, double *sigma_eff, int *tile) {
+    if (!p) return NFFT_ERR_ARG;
+    for (int d = 0; d < p->D; ++d) {
+        if (Ntilde) Ntilde[d] = p->Nt[d];
+        if (tile) tile[d] = p->geom.Q[d];
+    }
+    if (sigma_eff) *sigma_eff = (double)p->Nt[0] / (double)p->N[0];
+    return NFFT_OK;
+}
+
+int nfft_plan_grid(nfft_plan_t p, void **grid) {
+    if (!p || !grid) return NFFT_ERR_ARG;
+    *grid = p->grid;
+    return NFFT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// forward FFT with the resampling correction fused into the first (last-axis) pass
+hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
+    const int D = p.D;
+    const size_t cs = csize(p.dtype);
+    ContigPass c{};
+    c.mode = 1;
+    c.D = D;
+    c.dir = -1;
+    c.nlines = 1;
+    for (int d = 0; d < kMaxD; ++d) {
+        c.N[d] = (int)p.N[d];
+        c.Nt[d] = (int)p.Nt[d];
+    }
+    for (int d = 0; d < D - 1; ++d) {
+        c.outer_len[d] = (int)p.N[d];
+        c.outer_band[d] = 1;
+        c.nlines *= (int)p.N[d];
+    }
+    c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    hipError_t e = launch_fft_contig(p, f, p.grid, c, s);
+    if (e != hipSuccess) return e;
+    for (int a = D - 2; a >= 0; --a) {
+        AxisPass ap{};
+        ap.axis = a;
+        ap.inner = 1;
+        for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
+        ap.outer_len = 1;
+        if (a == 1) {  // D == 3: outer axis 0 holds only the band rows
+            ap.outer_len = (int)p.N[0];
+            ap.outer_band_N = (int)p.N[0];
+            ap.outer_Nt = (int)p.Nt[0];
+            ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
+        }
+        ap.in_band_N = (int)p.N[a];
+        ap.out_band_N = 0;
+        ap.dir = -1;
+        ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
+        e = launch_fft_axis(p, p.grid, ap, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// adjoint FFT with crop + resampling correction fused into the last pass
+hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s) {
+    const int D = p.D;
+    const size_t cs = csize(p.dtype);
+    for (int a = 0; a <= D - 2; ++a) {
+        AxisPass ap{};
+        ap.axis = a;
+        ap.inner = 1;
+        for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
+        ap.outer_len = 1;
+        if (a == 1) {
+            ap.outer_len = (int)p.N[0];
+            ap.outer_band_N = (int)p.N[0];
+            ap.outer_Nt = (int)p.Nt[0];
+            ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
+        }
+        ap.in_band_N = 0;
+        ap.out_band_N = (int)p.N[a];
+        ap.dir = +1;
+        ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
+        hipError_t e = launch_fft_axis(p, p.grid, ap, s);
+        if (e != hipSuccess) return e;
+    }
+    ContigPass c{};
+    c.mode = 2;
+    c.D = D;
+    c.dir = +1;
+    c.nlines = 1;
+    for (int d = 0; d < kMaxD; ++d) {
+        c.N[d] = (int)p.N[d];
+        c.Nt[d] = (int)p.Nt[d];
+    }
+    for (int d = 0; d < D - 1; ++d) {
+        c.outer_len[d] = (int)p.N[d];
+        c.outer_band[d] = 1;
+        c.nlines *= (int)p.N[d];
+    }
+    c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    return launch_fft_contig(p, p.grid, y, c, s);
+}
+
+// plain unpruned FFT of a whole grid, all axes
+hipError_t plain_fft(const nfft_plan_s &p, void *grid, int dir, hipStream_t s) {
+    const int D = p.D;
+    const size_t cs = csize(p.dtype);
+    ContigPass c{};
+    c.mode = 0;
+    c.D = D;
+    c.dir = dir;
+    c.nlines = 1;
+    for (int d = 0; d < kMaxD; ++d) {
+        c.N[d] = (int)p.N[d];
+        c.Nt[d] = (int)p.Nt[d];
+    }
+    for (int d = 0; d < D - 1; ++d) {
+        c.outer_len[d] = (int)p.Nt[d];
+        c.outer_band[d] = 0;
+        c.nlines *= (int)p.Nt[d];
+    }
+    c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    hipError_t e = launch_fft_contig(p, grid, grid, c, s);
+    if (e != hipSuccess) return e;
+    for (int a = D - 2; a >= 0; --a) {
+        AxisPass ap{};
+        ap.axis = a;
+        ap.inner = 1;
+        for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
+        ap.outer_len = 1;
+        if (a == 1) {
+            ap.outer_len = (int)p.Nt[0];
+            ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
+        }
+        ap.dir = dir;
+        ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
+        e = launch_fft_axis(p, grid, ap, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nfft_forward(nfft_plan_t p, const void *f, void *fhat, void *stream) {
+    if (!p || !f || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    if (p->M == 0) return NFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = forward_fft(*p, f, s);
+    if (e == hipSuccess) e = launch_interp(*p, p->grid, fhat, s);
+    return hip_rc(e);
+}
+
+int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream) {
+    if (!p || !y || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t n = 1;
+    for (int d = 0; d < p->D; ++d) n *= p->N[d];
+    if (p->M == 0) return hip_rc(launch_fill_zero_complex(y, n, p->dtype == NFFT_C128, s));
+    hipError_t e = launch_spread(*p, fhat, p->grid, s);
+    if (e == hipSuccess) e = adjoint_fft(*p, y, s);
+    return hip_rc(e);
+}
+
+int nfft_resample_forward(nfft_plan_t p, const void *grid, void *fhat, void *stream) {
+    if (!p || !grid || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    return hip_rc(launch_interp(*p, grid, fhat, (hipStream_t)stream));
+}
+
+int nfft_resample_adjoint(nfft_plan_t p, const void *fhat, void *grid, void *stream) {
+    if (!p || !grid || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->M == 0) return hip_rc(launch_fill_zero_complex(grid, p->G, p->dtype == NFFT_C128, s));
+    return hip_rc(launch_spread(*p, fhat, grid, s));
+}
+
+int nfft_fft_grid(nfft_plan_t p, void *grid, int direction, void *stream) {
+    if (!p || !grid || (direction != -1 && direction != 1)) return NFFT_ERR_ARG;
+    return hip_rc(plain_fft(*p, grid, direction, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,48 @@
+// Instantiation and dispatch of the resampling kernels over (type, D, 2m).
+#include "resample_impl.hpp"
+
+namespace nfft {
+
+#define NFFT_DISPATCH_M(FN, T, D, ...)                     \
+    switch (p.m) {                                         \
+        case 1: return FN<T, D, 2>(__VA_ARGS__);           \
+        case 2: return FN<T, D, 4>(__VA_ARGS__);           \
+        case 3: return FN<T, D, 6>(__VA_ARGS__);           \
+        case 4: return FN<T, D, 8>(__VA_ARGS__);           \
+        case 5: return FN<T, D, 10>(__VA_ARGS__);          \
+        case 6: return FN<T, D, 12>(__VA_ARGS__);          \
+        case 7: return FN<T, D, 14>(__VA_ARGS__);          \
+        case 8: return FN<T, D, 16>(__VA_ARGS__);          \
+        case 9: return FN<T, D, 18>(__VA_ARGS__);          \
+        case 10: return FN<T, D, 20>(__VA_ARGS__);         \
+        default: return hipErrorInvalidValue;              \
+    }
+
+template <typename T>
+static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
+    switch (p.D) {
+        case 1: NFFT_DISPATCH_M(run_interp, T, 1, p, grid, fhat, s)
+        case 2: NFFT_DISPATCH_M(run_interp, T, 2, p, grid, fhat, s)
+        default: NFFT_DISPATCH_M(run_interp, T, 3, p, grid, fhat, s)
+    }
+}
+
+template <typename T>
+static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s) {
+    switch (p.D) {
+        case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s)
+        case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s)
+        default: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s)
+    }
+}
+
+hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
+    if (p.nsub == 0) return hipSuccess;
+    return p.dtype == NFFT_C64 ? interp_t<float>(p, grid, fhat, s) : interp_t<double>(p, grid, fhat, s);
+}
+
+hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s) {
+    return p.dtype == NFFT_C64 ? spread_t<float>(p, fhat, grid, s) : spread_t<double>(p, fhat, grid, s);
+}
+
+}  // namespace nfft

@@ -1,0 +1,187 @@
+"""Thin PyTorch-facing binding of libnfft (argument marshalling only).
+
+Torch supplies device memory and the stream; every step of the transform runs
+in the library's HIP kernels.  Names follow the paper's API (section
+"Implementation", example usage): a plan built from the nodes and the size N,
+then ``forward`` (p * f) and ``adjoint`` (adjoint(p) * fhat), with optional
+output buffers (mul!), and the one-shot helpers ``nfft`` and ``nfft_adjoint``.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+_CDTYPE = {_lib.NFFT_C64: torch.complex64, _lib.NFFT_C128: torch.complex128}
+_RDTYPE = {_lib.NFFT_C64: torch.float32, _lib.NFFT_C128: torch.float64}
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """NFFT plan for nodes ``x`` (device tensor (M, D), float32 or float64) and size ``N``.
+
+    float32 nodes give a complex64 plan (FP32 arithmetic), float64 nodes a
+    complex128 plan.  ``tile``: optional per-axis tile edges; ``window``: "poly"
+    (default) or "direct"; ``max_block_nodes``: cap on nodes per interpolation
+    work item.
+    """
+
+    def __init__(self, x, N, m=4, sigma=2.0, tile=None, window="poly", max_block_nodes=0):
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+            raise TypeError("x must be a CUDA (HIP) tensor")
+        N = tuple(int(v) for v in N)
+        if x.dim() == 1 and len(N) == 1:
+            x = x.reshape(-1, 1)
+        if x.dim() != 2 or x.shape[1] != len(N):
+            raise ValueError("x must have shape (M, D) with D = len(N)")
+        if x.dtype == torch.float32:
+            self.dtype = _lib.NFFT_C64
+        elif x.dtype == torch.float64:
+            self.dtype = _lib.NFFT_C128
+        else:
+            raise TypeError("x must be float32 or float64")
+        self._lib = _lib.load()
+        self.N = N
+        self.D = len(N)
+        self.M = int(x.shape[0])
+        self.m = int(m)
+        self.sigma = float(sigma)
+        self.device = x.device
+        self.cdtype = _CDTYPE[self.dtype]
+        x = x.contiguous()
+        opts = _lib.Options()
+        if tile is not None:
+            for d, q in enumerate(tile):
+                opts.tile[d] = int(q)
+        opts.window = {"poly": _lib.NFFT_WINDOW_POLY, "direct": _lib.NFFT_WINDOW_DIRECT}[window]
+        opts.max_block_nodes = int(max_block_nodes)
+        Narr = (ctypes.c_int64 * self.D)(*N)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self._lib.nfft_plan_create_ex(ctypes.byref(handle), self.D, Narr, self.M,
+                                               ctypes.c_void_p(x.data_ptr()), self.m, self.sigma,
+                                               self.dtype, ctypes.byref(opts),
+                                               _stream_handle(self.device))
+        _lib.check(rc, "nfft_plan_create")
+        self._h = handle
+
+    # -- introspection -------------------------------------------------------
+    def info(self):
+        nt = (ctypes.c_int64 * self.D)()
+        se = ctypes.c_double()
+        tl = (ctypes.c_int * self.D)()
+        _lib.check(self._lib.nfft_plan_info(self._h, nt, ctypes.byref(se), tl), "nfft_plan_info")
+        return {"Ntilde": tuple(nt), "sigma_eff": se.value, "tile": tuple(tl)}
+
+    @property
+    def Ntilde(self):
+        return self.info()["Ntilde"]
+
+    def grid(self):
+        """Copy of the plan's oversampled grid (holds F D f after ``forward``)."""
+        ptr = ctypes.c_void_p()
+        _lib.check(self._lib.nfft_plan_grid(self._h, ctypes.byref(ptr)), "nfft_plan_grid")
+        out = torch.empty(self.Ntilde, dtype=self.cdtype, device=self.device)
+        _copy_device(out.data_ptr(), ptr.value, out.numel() * out.element_size(), self.device)
+        return out
+
+    # -- transforms ----------------------------------------------------------
+    def _check(self, t, shape, name):
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise TypeError("%s must be a tensor on %s" % (name, self.device))
+        if t.dtype != self.cdtype:
+            raise TypeError("%s must be %s" % (name, self.cdtype))
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+
+    def forward(self, f, out=None):
+        """fhat = A f (Algorithm 1); f has shape N."""
+        self._check(f, self.N, "f")
+        if out is None:
+            out = torch.empty(self.M, dtype=self.cdtype, device=self.device)
+        self._check(out, (self.M,), "out")
+        rc = self._lib.nfft_forward(self._h, ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
+        _lib.check(rc, "nfft_forward")
+        return out
+
+    def adjoint(self, fhat, out=None):
+        """y = A^H fhat (Algorithm 2); fhat has shape (M,)."""
+        self._check(fhat, (self.M,), "fhat")
+        if out is None:
+            out = torch.empty(self.N, dtype=self.cdtype, device=self.device)
+        self._check(out, self.N, "out")
+        rc = self._lib.nfft_adjoint(self._h, ctypes.c_void_p(fhat.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
+        _lib.check(rc, "nfft_adjoint")
+        return out
+
+    # -- single steps ----------------------------------------------------------
+    def resample_forward(self, grid, out=None):
+        self._check(grid, self.Ntilde, "grid")
+        if out is None:
+            out = torch.empty(self.M, dtype=self.cdtype, device=self.device)
+        self._check(out, (self.M,), "out")
+        rc = self._lib.nfft_resample_forward(self._h, ctypes.c_void_p(grid.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()),
+                                             _stream_handle(self.device))
+        _lib.check(rc, "nfft_resample_forward")
+        return out
+
+    def resample_adjoint(self, fhat, out=None):
+        self._check(fhat, (self.M,), "fhat")
+        if out is None:
+            out = torch.empty(self.Ntilde, dtype=self.cdtype, device=self.device)
+        self._check(out, self.Ntilde, "out")
+        rc = self._lib.nfft_resample_adjoint(self._h, ctypes.c_void_p(fhat.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()),
+                                             _stream_handle(self.device))
+        _lib.check(rc, "nfft_resample_adjoint")
+        return out
+
+    def fft_grid(self, grid, direction=-1):
+        """Unnormalised in-place FFT of an oversampled grid (direction -1 or +1)."""
+        self._check(grid, self.Ntilde, "grid")
+        rc = self._lib.nfft_fft_grid(self._h, ctypes.c_void_p(grid.data_ptr()), int(direction),
+                                     _stream_handle(self.device))
+        _lib.check(rc, "nfft_fft_grid")
+        return grid
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.nfft_plan_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _copy_device(dst_ptr, src_ptr, nbytes, device):
+    """Device-to-device copy of a library-owned buffer into a torch tensor."""
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_void_p]
+    hip.hipMemcpyAsync.restype = ctypes.c_int
+    rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr),
+                            ctypes.c_size_t(nbytes), 3, _stream_handle(device))
+    if rc != 0:
+        raise RuntimeError("hipMemcpyAsync failed (%d)" % rc)
+
+
+def nfft(x, f, m=4, sigma=2.0, **kw):
+    """One-shot forward NFFT: fhat_j ~= sum_n f_n exp(-2 pi i n.x_j)."""
+    return Plan(x, tuple(f.shape), m=m, sigma=sigma, **kw).forward(f)
+
+
+def nfft_adjoint(x, N, fhat, m=4, sigma=2.0, **kw):
+    """One-shot adjoint NFFT: y_n ~= sum_j fhat_j exp(+2 pi i n.x_j)."""
+    return Plan(x, tuple(N), m=m, sigma=sigma, **kw).adjoint(fhat)

@@ -1,0 +1,249 @@
+"""GPU parity: libnfft (through the C ABI) against the CPU oracle.
+
+* step parity: the oversampled FFT against numpy's FFT, the resampling steps
+  against the oracle's Algorithm 1/2 resampling on the same grid;
+* end to end: forward and adjoint against the oracle NFFT (same algorithm,
+  FP64, rounding-level tolerance) and against the direct NDFT (approximation
+  tolerance per (m, sigma, dtype));
+* the exact adjointness of the GPU pair (A ~= B F D, A^H ~= D^T F^H B^T);
+* edge cases: M = 0, one node, all nodes in one tile, grid-aligned nodes,
+  x = -1/2, a hot spot of coincident nodes, nodes outside the torus.
+
+Tolerances (derived from the arithmetic, not fitted).  Rounding errors of
+relative size u (2^-24 for c64, 2^-53 for c128) made on the oversampled grid
+(window weights, (2m)^D-term sums, log2|I_Nt| FFT stages) reach the output
+through the resampling correction, whose factors beta_d(n) grow towards the
+edge of I_N; for flat random data this amplifies a white grid error by
+kappa = prod_d sqrt(mean(beta_d^2) mean(beta_d^-2)) (about 1.5 at sigma = 2,
+about 330 for 3-D sigma = 1.25).  Gates against the FP64 oracle:
+  c64:  10 u kappa log2|I_Nt| / 8,   c128: 100 u kappa log2|I_Nt| / 8
+(the c128 constant also covers the two independent least-squares fits of the
+window polynomial).  Against the NDFT the gate is the oracle's own
+approximation gate plus the above.  The stated targets are asserted
+separately: c64 m=4 sigma=2 within 1e-5 and c128 m=6 sigma=2 within 1e-9 of
+the NDFT (relative l2).
+"""
+import numpy as np
+import pytest
+import torch
+
+import nfft_workloads as wl
+from oracle import ndft
+from oracle import nfft_alg as na
+
+pytestmark = pytest.mark.gpu
+
+C128_VS_ORACLE = 1e-11   # resampling steps alone (no resampling correction involved)
+C64_VS_ORACLE = 5e-6
+NDFT_GATE = {(4, 2.0): 1e-6, (6, 2.0): 1e-9, (8, 2.0): 1e-12, (4, 1.25): 2e-4, (3, 2.0): 3e-5}
+TARGET = {("c64", 4, 2.0): 1e-5, ("c128", 6, 2.0): 1e-9}
+
+
+def kappa(N, sigma, m):
+    Nt = na.oversampled_size(N, sigma)
+    k = 1.0
+    for d in range(len(N)):
+        b = na.deconv_factors(N[d], Nt[d], m)
+        k *= np.sqrt(np.mean(b ** 2) * np.mean(b ** -2.0))
+    return k
+
+
+def e2e_tol(N, sigma, m, dt):
+    Nt = na.oversampled_size(N, sigma)
+    lg = np.log2(np.prod(Nt))
+    return (10 * 2.0 ** -24 if dt == "c64" else 100 * 2.0 ** -53) * kappa(N, sigma, m) * lg / 8
+
+
+def rel2(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_plan(device, x, N, m, sigma, dt, **kw):
+    from paper_2208_00049_amd import Plan
+    xdt = torch.float64 if dt == "c128" else torch.float32
+    xt = torch.tensor(np.asarray(x).reshape(-1, len(N)), dtype=xdt, device=device)
+    p = Plan(xt, N, m=m, sigma=sigma, **kw)
+    return p, xt.double().cpu().numpy()
+
+
+def to_dev(a, dt, device):
+    return torch.tensor(np.asarray(a), dtype=torch.complex128 if dt == "c128" else torch.complex64,
+                        device=device)
+
+
+def run_pair(device, x, N, m, sigma, dt, f, fh, **kw):
+    p, xs = make_plan(device, x, N, m, sigma, dt, **kw)
+    fg = p.forward(to_dev(f, dt, device)).cpu().numpy()
+    yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    return p, xs, fg, yg
+
+
+# ---------------------------------------------------------------------------
+# step parity
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,sigma", [((256,), 2.0), ((32, 48), 2.0), ((64, 64), 2.0),
+                                     ((16, 16, 16), 2.0), ((16, 24, 16), 1.25), ((20,), 1.5)])
+def test_fft_grid_matches_numpy(device, dt, N, sigma):
+    p, _ = make_plan(device, np.zeros((1, len(N))), N, 2, sigma, dt)
+    Nt = p.Ntilde
+    g = wl.cn01(Nt, config=80, stream=1)
+    tol = 1e-13 if dt == "c128" else 2e-6
+    fw = p.fft_grid(to_dev(g, dt, device), -1).cpu().numpy()
+    assert rel2(fw, np.fft.fftn(g)) < tol
+    bw = p.fft_grid(to_dev(g, dt, device), +1).cpu().numpy()
+    assert rel2(bw, np.fft.ifftn(g) * g.size) < tol
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M,m,sigma", [((256,), 512, 4, 2.0), ((64, 64), 5000, 4, 2.0),
+                                         ((48, 64), 3000, 6, 2.0), ((16, 16, 16), 6000, 4, 2.0),
+                                         ((32, 32, 16), 3000, 4, 1.25), ((16, 16, 16), 3000, 4, 1.25)])
+def test_resampling_steps_match_oracle(device, dt, N, M, m, sigma):
+    D = len(N)
+    x = wl.uniform_nodes(M, D, config=81, stream=0)
+    p, xs = make_plan(device, x, N, m, sigma, dt)
+    Nt = p.Ntilde
+    ghat = wl.cn01(Nt, config=81, stream=1)
+    fh = wl.cn01((M,), config=81, stream=2)
+    tol = C128_VS_ORACLE if dt == "c128" else C64_VS_ORACLE
+    got = p.resample_forward(to_dev(ghat, dt, device)).cpu().numpy()
+    assert rel2(got, na.resample_forward(xs, ghat, N, m, Nt)) < tol
+    spread = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    assert rel2(spread, na.resample_adjoint(xs, fh, N, m, Nt)) < tol
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_forward_grid_is_F_D_f(device, dt):
+    N, M, m, sigma = (64, 48), 1000, 4, 2.0
+    x = wl.uniform_nodes(M, 2, config=82, stream=0)
+    f = wl.cn01(N, config=82, stream=1)
+    p, xs = make_plan(device, x, N, m, sigma, dt)
+    p.forward(to_dev(f, dt, device))
+    g = p.grid().cpu().numpy()
+    _, st = na.forward(xs, f, m, sigma, return_steps=True)
+    assert rel2(g, st["ghat"]) < (1e-13 if dt == "c128" else 2e-6)
+
+
+# ---------------------------------------------------------------------------
+# end to end
+
+CASES = [((256,), 512, 4, 2.0), ((256,), 512, 6, 2.0), ((64, 64), 4096, 4, 2.0),
+         ((64, 32), 3000, 6, 2.0), ((32, 32), 2048, 8, 2.0), ((64, 64), 4096, 4, 1.25),
+         ((16, 16, 16), 4096, 4, 2.0), ((16, 16, 16), 4096, 4, 1.25), ((32, 32), 1500, 3, 2.0)]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M,m,sigma", CASES)
+def test_end_to_end_against_oracle_and_ndft(device, dt, N, M, m, sigma):
+    D = len(N)
+    x = wl.uniform_nodes(M, D, config=83, stream=0)
+    f = wl.cn01(N, config=83, stream=1)
+    fh = wl.cn01((M,), config=83, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh)
+    fo = na.forward(xs, f, m, sigma)
+    yo = na.adjoint(xs, fh, N, m, sigma)
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(fg, fo) < tol and rel2(yg, yo) < tol, (rel2(fg, fo), rel2(yg, yo), tol)
+    fe = ndft.ndft_forward(xs, f)
+    ye = ndft.ndft_adjoint(xs, fh, N)
+    gate = NDFT_GATE[(m, sigma)] + tol
+    assert rel2(fg, fe) < gate and rel2(yg, ye) < gate, (rel2(fg, fe), rel2(yg, ye), gate)
+    if (dt, m, sigma) in TARGET:
+        assert max(rel2(fg, fe), rel2(yg, ye)) <= TARGET[(dt, m, sigma)]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M,m,sigma", [((128,), 300, 4, 2.0), ((64, 64), 4096, 6, 2.0),
+                                         ((16, 16, 16), 3000, 4, 1.25)])
+def test_gpu_pair_is_exactly_adjoint(device, dt, N, M, m, sigma):
+    D = len(N)
+    x = wl.uniform_nodes(M, D, config=84, stream=0)
+    f = wl.cn01(N, config=84, stream=1)
+    fh = wl.cn01((M,), config=84, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh)
+    lhs = np.vdot(fh, fg)
+    rhs = np.vdot(yg, f)
+    scale = np.linalg.norm(fh) * np.linalg.norm(fg)
+    assert abs(lhs - rhs) < e2e_tol(N, sigma, m, dt) * scale
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_direct_window_mode(device, dt):
+    N, M, m, sigma = (64, 64), 4096, 4, 2.0
+    x = wl.uniform_nodes(M, 2, config=85, stream=0)
+    f = wl.cn01(N, config=85, stream=1)
+    fh = wl.cn01((M,), config=85, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh, window="direct")
+    fo = na.forward(xs, f, m, sigma, window="direct")
+    yo = na.adjoint(xs, fh, N, m, sigma, window="direct")
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(fg, fo) < tol and rel2(yg, yo) < tol, (rel2(fg, fo), rel2(yg, yo), tol)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_empty_node_set(device, dt):
+    from paper_2208_00049_amd import Plan
+    xdt = torch.float64 if dt == "c128" else torch.float32
+    p = Plan(torch.zeros((0, 2), dtype=xdt, device=device), (32, 32))
+    y = p.adjoint(torch.zeros(0, dtype=p.cdtype, device=device),
+                  out=torch.full((32, 32), 7.0, dtype=p.cdtype, device=device))
+    assert torch.count_nonzero(y).item() == 0
+    assert p.forward(torch.ones((32, 32), dtype=p.cdtype, device=device)).numel() == 0
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("kind", ["one_tile", "grid_aligned", "hotspot", "outside", "single"])
+def test_edge_node_sets(device, dt, kind):
+    N, m, sigma = (64, 64), 4, 2.0
+    Nt = na.oversampled_size(N, sigma)
+    g = wl.rng(86, 0)
+    if kind == "one_tile":
+        x = 0.1 + g.random((3000, 2)) * (8.0 / Nt[0])
+    elif kind == "grid_aligned":
+        x = g.integers(-Nt[0] // 2, Nt[0] // 2, size=(2000, 2)) / Nt[0]
+        x[:50] = -0.5
+        x[50:100, 0] = 0.0
+    elif kind == "hotspot":
+        x = np.concatenate([np.zeros((700, 2)), wl.uniform_nodes(1000, 2, config=86, stream=0)])
+    elif kind == "outside":
+        x = wl.uniform_nodes(1500, 2, config=86, stream=0) * 7.0
+    else:
+        x = np.array([[0.25, -0.125]])
+    M = x.shape[0]
+    f = wl.cn01(N, config=86, stream=1)
+    fh = wl.cn01((M,), config=86, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh)
+    fo = na.forward(xs, f, m, sigma)
+    yo = na.adjoint(xs, fh, N, m, sigma)
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(fg, fo) < tol and rel2(yg, yo) < tol, (rel2(fg, fo), rel2(yg, yo), tol)
+
+
+def test_nan_node_is_rejected(device):
+    from paper_2208_00049_amd import NfftError, Plan
+    x = torch.zeros((10, 2), dtype=torch.float64, device=device)
+    x[3, 1] = float("nan")
+    with pytest.raises(NfftError) as e:
+        Plan(x, (32, 32))
+    assert e.value.code == -5
+
+
+def test_explicit_tiles_and_small_blocks(device):
+    """Other tilings and work-item caps give the same transform."""
+    N, M, m, sigma = (64, 64), 5000, 4, 2.0
+    x = wl.uniform_nodes(M, 2, config=87, stream=0)
+    f = wl.cn01(N, config=87, stream=1)
+    fh = wl.cn01((M,), config=87, stream=2)
+    ref = None
+    for kw in [dict(), dict(tile=(16, 64)), dict(tile=(64, 8)), dict(max_block_nodes=37)]:
+        p, xs, fg, yg = run_pair(device, x, N, m, sigma, "c128", f, fh, **kw)
+        if ref is None:
+            ref = (fg, yg)
+        else:
+            assert rel2(fg, ref[0]) < 1e-13 and rel2(yg, ref[1]) < 1e-13, kw
