@@ -1,0 +1,225 @@
+"""Benchmark of the NFFT hot path on one MI355X.
+
+One step = one forward NFFT plus one adjoint NFFT (resampling correction,
+oversampled FFT, interpolation; spreading, adjoint FFT, resampling correction)
+over the workload's synthetic node set, with inputs resident in HBM.  The
+metric is nonuniform points per second for the pair, M / (t_fwd + t_adj).
+
+Default workload: 2-D, N = 512 x 512 complex64 coefficients ~ CN(0, 1),
+M = 262144 nodes iid uniform in [-1/2, 1/2)^2, Kaiser-Bessel window m = 4,
+sigma = 2 (the paper's 2-D benchmark shape: J = |I_N| random nodes).
+
+Printed: one JSON line with the throughput, a roofline entry for the
+dominant kernel (per-kernel HIP-event durations measured in this run), the
+FP32-vs-FP64 accuracy on the same GPU and a timed CPU-oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "nonuniform pts/s, NFFT+adjoint at rel-ℓ2 ≤1e-5 (FP32) vs FP64; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "2d_n512_m262144_uniform": dict(D=2, N=(512, 512), M=262144, nodes="uniform", config=1),
+    "2d_n512_radial402x652": dict(D=2, N=(512, 512), M=402 * 652, nodes="radial", config=1),
+    "3d_n128_m2097152_uniform": dict(D=3, N=(128, 128, 128), M=2097152, nodes="uniform", config=2),
+    "1d_n256_m512_uniform": dict(D=1, N=(256,), M=512, nodes="uniform", config=0),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="2d_n512_m262144_uniform", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--m", type=int, default=4)
+    ap.add_argument("--sigma", type=float, default=2.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="plan + a few steps, no accuracy/CPU legs (for profilers)")
+    return ap.parse_args()
+
+
+def inputs(w):
+    import nfft_workloads as wl
+    if w["nodes"] == "radial":
+        x = wl.radial_nodes(402, 652)
+    else:
+        x = wl.uniform_nodes(w["M"], w["D"], config=w["config"], stream=0)
+    f = wl.cn01(w["N"], config=w["config"], stream=1)
+    fh = wl.cn01((w["M"],), config=w["config"], stream=2)
+    return x, f, fh
+
+
+def algorithmic_bytes(w, Nt, dtype):
+    """Per-launch algorithmic HBM bytes of every kernel of a step."""
+    c = 8 if dtype == "c64" else 16
+    r = c // 2
+    M, D, N = w["M"], w["D"], w["N"]
+    G = int(np.prod(Nt))
+    nodes_and_values = M * (D * r + c)
+    out = {"interp": nodes_and_values + G * c, "spread": nodes_and_values + G * c}
+    nprod = int(np.prod(N))
+    if D == 1:
+        out["fwd_deconv_fft_last"] = nprod * c + G * c
+        out["adj_fft_last_deconv"] = G * c + nprod * c
+    elif D == 2:
+        band = N[0] * Nt[1]
+        out["fwd_deconv_fft_last"] = nprod * c + band * c
+        out["fwd_fft_axis0"] = band * c + G * c
+        out["adj_fft_axis0"] = G * c + band * c
+        out["adj_fft_last_deconv"] = band * c + nprod * c
+    else:
+        lines2 = N[0] * N[1] * Nt[2]
+        plane = N[0] * Nt[1] * Nt[2]
+        out["fwd_deconv_fft_last"] = nprod * c + lines2 * c
+        out["fwd_fft_axis1"] = lines2 * c + plane * c
+        out["fwd_fft_axis0"] = plane * c + G * c
+        out["adj_fft_axis0"] = G * c + plane * c
+        out["adj_fft_axis1"] = plane * c + lines2 * c
+        out["adj_fft_last_deconv"] = lines2 * c + nprod * c
+    return out
+
+
+def cpu_baseline(x, f, fh, N, seconds):
+    """Time the FP64 NDFT oracle on a bounded sample of the same workload (host cores)."""
+    from oracle import ndft
+    M = x.shape[0]
+    nprod = int(np.prod(N))
+    g = np.random.default_rng(12345)
+    # calibrate with a small sample, then size both legs to about `seconds` in total
+    sf, sa = min(M, 256), min(nprod, 16)
+    t0 = time.perf_counter()
+    ndft.ndft_forward(x[:sf], f)
+    t1 = time.perf_counter()
+    ndft.ndft_adjoint(x, fh, N, idx=g.choice(nprod, sa, replace=False))
+    t2 = time.perf_counter()
+    per_node, per_coef = (t1 - t0) / sf, (t2 - t1) / sa
+    sf = int(min(M, max(sf, 0.5 * seconds / per_node)))
+    sa = int(min(nprod, max(sa, 0.5 * seconds / per_coef)))
+    t0 = time.perf_counter()
+    ndft.ndft_forward(x[:sf], f)
+    t1 = time.perf_counter()
+    ndft.ndft_adjoint(x, fh, N, idx=g.choice(nprod, sa, replace=False))
+    t2 = time.perf_counter()
+    t_fwd = (t1 - t0) * M / sf
+    t_adj = (t2 - t1) * nprod / sa
+    return {"value": M / (t_fwd + t_adj), "unit": "pts/s", "cores": ndft.threads(),
+            "kind": "oracle",
+            "sample": "FP64 direct NDFT: forward at %d of %d nodes (%.2f s), adjoint at %d of %d "
+                      "coefficients (%.2f s), scaled to the full transform pair"
+                      % (sf, M, t1 - t0, sa, nprod, t2 - t1)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2208_00049_amd import Plan
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    x, f, fh = inputs(w)
+    xdt = torch.float32 if args.dtype == "c64" else torch.float64
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    xt = torch.tensor(x, dtype=xdt, device=dev)
+    ft = torch.tensor(f, dtype=cdt, device=dev)
+    fht = torch.tensor(fh, dtype=cdt, device=dev)
+    fout = torch.empty(w["M"], dtype=cdt, device=dev)
+    yout = torch.empty(w["N"], dtype=cdt, device=dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    plan = Plan(xt, w["N"], m=args.m, sigma=args.sigma)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info()
+
+    def step():
+        plan.forward(ft, out=fout)
+        plan.adjoint(fht, out=yout)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_per_step = total_ms / args.steps
+    value = w["M"] * args.steps / (total_ms * 1e-3)
+
+    # per-kernel durations: a second pass of the same steps with stage events on
+    plan.set_timing(True)
+    sums = {}
+    nprof = max(5, min(args.steps, 50))
+    for _ in range(nprof):
+        step()
+        for k, v in plan.stage_times().items():
+            sums[k] = sums.get(k, 0.0) + v
+    plan.set_timing(False)
+    avg_ms = {k: v / nprof for k, v in sums.items() if v > 0}
+    algo = algorithmic_bytes(w, info["Ntilde"], args.dtype)
+    kernels = {k: {"ms": round(avg_ms[k], 5), "algorithmic_bytes": algo.get(k),
+                   "GBs": round(algo[k] / (avg_ms[k] * 1e-3) / 1e9, 1) if k in algo else None}
+               for k in avg_ms}
+    dominant = max(avg_ms, key=avg_ms.get)
+    ach = algo[dominant] / (avg_ms[dominant] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None}
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "c64" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "N": list(w["N"]), "M": w["M"], "m": args.m,
+                   "sigma": args.sigma, "nodes": w["nodes"],
+                   "complex": "complex64" if args.dtype == "c64" else "complex128",
+                   "Ntilde": list(info["Ntilde"]), "tile": list(info["tile"])},
+        "plan_ms": round(plan_ms, 2),
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    if not args.profile_only:
+        # FP32 result against FP64 on the same GPU (same FP32-rounded nodes and inputs)
+        if args.dtype == "c64":
+            p64 = Plan(xt.double(), w["N"], m=args.m, sigma=args.sigma)
+            f64 = p64.forward(ft.to(torch.complex128))
+            y64 = p64.adjoint(fht.to(torch.complex128))
+            fwd_err = (torch.linalg.norm(fout.to(torch.complex128) - f64) / torch.linalg.norm(f64)).item()
+            adj_err = (torch.linalg.norm(yout.to(torch.complex128) - y64) / torch.linalg.norm(y64)).item()
+            result["accuracy"] = {"fwd_rel_l2_fp32_vs_fp64": fwd_err, "adj_rel_l2_fp32_vs_fp64": adj_err}
+            p64.close()
+        if not args.no_cpu:
+            xs = xt.double().cpu().numpy()
+            result["cpu_baseline"] = cpu_baseline(xs, ft.cpu().numpy().astype(np.complex128),
+                                                  fht.cpu().numpy().astype(np.complex128),
+                                                  w["N"], args.cpu_seconds)
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -147,6 +147,23 @@ int nfft_plan_info(nfft_plan_t p, int64_t *Ntilde, double *sigma_eff, int *tile)
  * nfft_forward it holds ghat = F D f, after nfft_adjoint it is scratch. */
 int nfft_plan_grid(nfft_plan_t p, void **grid);
 
+/*
+ * Per-kernel timing.  With timing enabled, nfft_forward and nfft_adjoint
+ * record a pair of HIP events on `stream` around each kernel they launch.
+ * nfft_plan_timing waits for the last recorded event and returns, for the most
+ * recent forward and adjoint call, the elapsed milliseconds of each stage:
+ *   0 forward: resampling correction + zero pad + FFT along the last axis
+ *   1 forward: FFT along axis 1 (3-D only)      2 forward: FFT along axis 0
+ *   3 forward: interpolation                     4 adjoint: spreading
+ *   5 adjoint: FFT along axis 0                  6 adjoint: FFT along axis 1 (3-D)
+ *   7 adjoint: FFT along the last axis + crop + resampling correction
+ * Stages a plan does not run report 0.  ms must hold NFFT_NUM_STAGES values.
+ * Timing adds an event record per kernel; leave it off when timing whole calls.
+ */
+#define NFFT_NUM_STAGES 8
+int nfft_plan_set_timing(nfft_plan_t p, int enable);
+int nfft_plan_timing(nfft_plan_t p, double *ms);
+
 /* Static description of an error code (never NULL). */
 const char *nfft_strerror(int code);
 

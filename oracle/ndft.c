@@ -32,6 +32,20 @@
 
 #define MAXD 4
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int ndft_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* cos and sin of 2*pi*t, t in turns, with exact reduction of t to [-1/2, 1/2]. */
 static void cis_turns(double t, double *c, double *s)
 {

@@ -32,6 +32,7 @@ def _load():
         lib.ndft_adjoint_subset.argtypes = [ctypes.c_int, i64p, ctypes.c_int64, dp, dp,
                                             ctypes.c_int64, i64p, dp]
         lib.ndft_adjoint_subset.restype = ctypes.c_int
+        lib.ndft_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -85,3 +86,8 @@ def ndft_adjoint(x, fhat, N, idx=None):
     if rc != 0:
         raise ValueError("ndft_adjoint: bad arguments")
     return out.reshape(tuple(int(v) for v in Nv)) if full else out
+
+
+def threads():
+    """OpenMP threads the oracle uses."""
+    return int(_load().ndft_threads())

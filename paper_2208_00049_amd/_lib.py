@@ -23,7 +23,11 @@ NFFT_WINDOW_DIRECT = 1
 
 EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft_forward",
            "nfft_adjoint", "nfft_resample_forward", "nfft_resample_adjoint", "nfft_fft_grid",
-           "nfft_plan_info", "nfft_plan_grid", "nfft_strerror"]
+           "nfft_plan_info", "nfft_plan_grid", "nfft_plan_set_timing", "nfft_plan_timing",
+           "nfft_strerror"]
+NFFT_NUM_STAGES = 8
+STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
+          "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]
 
 
 class Options(ctypes.Structure):
@@ -65,6 +69,8 @@ def load():
     lib.nfft_plan_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int)]
     lib.nfft_plan_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.nfft_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.nfft_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nfft_strerror.argtypes = [ctypes.c_int]
     lib.nfft_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:

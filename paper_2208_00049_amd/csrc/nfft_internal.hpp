@@ -92,6 +92,11 @@ struct nfft_plan_s {
     int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}
     void *twiddle[nfft::kMaxD] = {nullptr, nullptr, nullptr};
     nfft::FftLine line[nfft::kMaxD];
+
+    // optional per-stage timing (events recorded around each kernel launch)
+    bool timing = false;
+    hipEvent_t ev[2 * NFFT_NUM_STAGES] = {};
+    bool ev_used[NFFT_NUM_STAGES] = {};
 };
 
 namespace nfft {

@@ -86,10 +86,22 @@ bool factor_line(int L, FftLine &fl) {
     return fl.tpl <= 1024;
 }
 
+// LDS of the interpolation kernel: tile + halo, plus the staged node chunk
+// (256 nodes: D origins, D fractions, a complex value, an index) and range table.
 size_t interp_lds(const int *Q, int D, int m, size_t cs) {
     size_t t = cs;
     for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + 2 * m - 1);
-    return t;
+    const size_t rs = cs / 2;
+    return t + 256 * (4 * D + rs * (D + 2) + 4) + 4 * (2 * (1 << (2 * D)) + 1);
+}
+
+// LDS of the spreading kernel: fixed-point accumulators of the tile (one int64 per
+// component for c64, two for c128) plus the staged chunk of 512 nodes.
+size_t spread_lds(const int *Q, int D, size_t cs) {
+    size_t t = (cs == 8 ? 16 : 32);
+    for (int d = 0; d < D; ++d) t *= (size_t)Q[d];
+    const size_t rs = cs / 2;
+    return t + 512 * (4 * D + rs * (D + 2)) + 8 * (1 << (2 * D)) + 16;
 }
 
 bool valid_tile(int64_t Nt, int Q, int m) {
@@ -120,7 +132,8 @@ int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req,
             if (!valid_tile(Nt[d], req[d], m)) return NFFT_ERR_ARG;
             Q[d] = req[d];
         }
-        return interp_lds(Q, D, m, cs) <= budget ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
+        return interp_lds(Q, D, m, cs) <= budget && spread_lds(Q, D, cs) <= budget
+                   ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
     }
     int want[3];
     if (D == 1) want[0] = 256;
@@ -133,8 +146,8 @@ int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req,
         Q[d] = pick_edge(Nt[d], std::max(want[d], 2 * m), m);
         if (!Q[d]) return NFFT_ERR_UNSUPPORTED;
     }
-    // shrink the largest edge until the interpolation tile (with halo) fits in LDS
-    while (interp_lds(Q, D, m, cs) > budget) {
+    // shrink the largest edge until both resampling kernels fit in LDS
+    while (interp_lds(Q, D, m, cs) > budget || spread_lds(Q, D, cs) > budget) {
         int best = -1;
         for (int d = 0; d < D; ++d) {
             const int q = pick_edge_down(Nt[d], Q[d] - 1, m);
@@ -231,6 +244,8 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
 
 void release(nfft_plan_s *p) {
     if (!p) return;
+    for (int i = 0; i < 2 * NFFT_NUM_STAGES; ++i)
+        if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
     (void)hipFree(p->grid);
     for (int d = 0; d < kMaxD; ++d) {
         (void)hipFree(p->deconv[d]);
@@ -457,6 +472,22 @@ int nfft_plan_grid(nfft_plan_t p, void **grid) {
 
 namespace {
 
+// Record the start / stop event of a stage when timing is on.
+struct StageTimer {
+    const nfft_plan_s &p;
+    int stage;
+    hipStream_t s;
+    StageTimer(const nfft_plan_s &pl, int st, hipStream_t str) : p(pl), stage(st), s(str) {
+        if (p.timing) (void)hipEventRecord(p.ev[2 * stage], s);
+    }
+    ~StageTimer() {
+        if (p.timing) {
+            (void)hipEventRecord(p.ev[2 * stage + 1], s);
+            const_cast<nfft_plan_s &>(p).ev_used[stage] = true;
+        }
+    }
+};
+
 // forward FFT with the resampling correction fused into the first (last-axis) pass
 hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
     const int D = p.D;
@@ -476,7 +507,11 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
         c.nlines *= (int)p.N[d];
     }
     c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
-    hipError_t e = launch_fft_contig(p, f, p.grid, c, s);
+    hipError_t e;
+    {
+        StageTimer t(p, 0, s);
+        e = launch_fft_contig(p, f, p.grid, c, s);
+    }
     if (e != hipSuccess) return e;
     for (int a = D - 2; a >= 0; --a) {
         AxisPass ap{};
@@ -494,7 +529,10 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
         ap.out_band_N = 0;
         ap.dir = -1;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
-        e = launch_fft_axis(p, p.grid, ap, s);
+        {
+            StageTimer t(p, a == 1 ? 1 : 2, s);
+            e = launch_fft_axis(p, p.grid, ap, s);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -520,7 +558,11 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s) {
         ap.out_band_N = (int)p.N[a];
         ap.dir = +1;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
-        hipError_t e = launch_fft_axis(p, p.grid, ap, s);
+        hipError_t e;
+        {
+            StageTimer t(p, a == 1 ? 6 : 5, s);
+            e = launch_fft_axis(p, p.grid, ap, s);
+        }
         if (e != hipSuccess) return e;
     }
     ContigPass c{};
@@ -538,6 +580,7 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s) {
         c.nlines *= (int)p.N[d];
     }
     c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    StageTimer t(p, 7, s);
     return launch_fft_contig(p, p.grid, y, c, s);
 }
 
@@ -589,7 +632,10 @@ int nfft_forward(nfft_plan_t p, const void *f, void *fhat, void *stream) {
     if (p->M == 0) return NFFT_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = forward_fft(*p, f, s);
-    if (e == hipSuccess) e = launch_interp(*p, p->grid, fhat, s);
+    if (e == hipSuccess) {
+        StageTimer t(*p, 3, s);
+        e = launch_interp(*p, p->grid, fhat, s);
+    }
     return hip_rc(e);
 }
 
@@ -599,7 +645,11 @@ int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream) {
     int64_t n = 1;
     for (int d = 0; d < p->D; ++d) n *= p->N[d];
     if (p->M == 0) return hip_rc(launch_fill_zero_complex(y, n, p->dtype == NFFT_C128, s));
-    hipError_t e = launch_spread(*p, fhat, p->grid, s);
+    hipError_t e;
+    {
+        StageTimer t(*p, 4, s);
+        e = launch_spread(*p, fhat, p->grid, s);
+    }
     if (e == hipSuccess) e = adjoint_fft(*p, y, s);
     return hip_rc(e);
 }
@@ -614,6 +664,33 @@ int nfft_resample_adjoint(nfft_plan_t p, const void *fhat, void *grid, void *str
     hipStream_t s = (hipStream_t)stream;
     if (p->M == 0) return hip_rc(launch_fill_zero_complex(grid, p->G, p->dtype == NFFT_C128, s));
     return hip_rc(launch_spread(*p, fhat, grid, s));
+}
+
+int nfft_plan_set_timing(nfft_plan_t p, int enable) {
+    if (!p) return NFFT_ERR_ARG;
+    if (enable && !p->ev[0]) {
+        for (int i = 0; i < 2 * NFFT_NUM_STAGES; ++i) {
+            hipError_t e = hipEventCreate(&p->ev[i]);
+            if (e != hipSuccess) return hip_rc(e);
+        }
+    }
+    p->timing = enable != 0;
+    for (int i = 0; i < NFFT_NUM_STAGES; ++i) p->ev_used[i] = false;
+    return NFFT_OK;
+}
+
+int nfft_plan_timing(nfft_plan_t p, double *ms) {
+    if (!p || !ms) return NFFT_ERR_ARG;
+    for (int i = 0; i < NFFT_NUM_STAGES; ++i) {
+        ms[i] = 0.0;
+        if (!p->ev_used[i]) continue;
+        hipError_t e = hipEventSynchronize(p->ev[2 * i + 1]);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, p->ev[2 * i], p->ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_rc(e);
+        ms[i] = t;
+    }
+    return NFFT_OK;
 }
 
 int nfft_fft_grid(nfft_plan_t p, void *grid, int direction, void *stream) {

@@ -88,6 +88,16 @@ class Plan:
         _copy_device(out.data_ptr(), ptr.value, out.numel() * out.element_size(), self.device)
         return out
 
+    def set_timing(self, enable=True):
+        """Record HIP events around every kernel of forward/adjoint (see stage_times)."""
+        _lib.check(self._lib.nfft_plan_set_timing(self._h, int(bool(enable))), "nfft_plan_set_timing")
+
+    def stage_times(self):
+        """Milliseconds of each stage of the latest forward and adjoint call (dict by stage name)."""
+        ms = (ctypes.c_double * _lib.NFFT_NUM_STAGES)()
+        _lib.check(self._lib.nfft_plan_timing(self._h, ms), "nfft_plan_timing")
+        return {name: ms[i] for i, name in enumerate(_lib.STAGES)}
+
     # -- transforms ----------------------------------------------------------
     def _check(self, t, shape, name):
         if not isinstance(t, torch.Tensor) or t.device != self.device:
