@@ -50,7 +50,22 @@ def parse():
                     help="target CPU time of the oracle sample")
     ap.add_argument("--profile-only", action="store_true",
                     help="plan + a few steps, no accuracy/CPU legs (for profilers)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run --steps device-to-device copies of this many bytes (a "
+                         "reference kernel for calibrating HBM traffic counters)")
     return ap.parse_args()
+
+
+def copy_reference(nbytes, steps):
+    """Plain device copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch give the
+    counters' scale for the HBM traffic of the NFFT kernels."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "steps": steps}), flush=True)
 
 
 def inputs(w):
@@ -126,6 +141,9 @@ def cpu_baseline(x, f, fh, N, seconds):
 
 def main():
     args = parse()
+    if args.copy_bytes:
+        copy_reference(args.copy_bytes, args.steps)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
