@@ -19,6 +19,16 @@
 namespace nfft {
 
 constexpr int kLinePad = 1;  // complex values of padding after each LDS line
+constexpr int kNumXcd = 8;   // MI355X: 8 accelerator dies, each with its own L2
+
+// Workgroups are dispatched round robin over the XCDs (block b runs on XCD b mod 8).
+// Renumber them so that each XCD gets a contiguous run of logical blocks: blocks
+// that share cache lines (neighbouring columns, neighbouring tiles) then share an L2.
+__device__ inline int xcd_block(int b, int nblocks) {
+    const int full = nblocks - nblocks % kNumXcd;
+    if (b >= full) return b;
+    return (b % kNumXcd) * (full / kNumXcd) + b / kNumXcd;
+}
 
 template <typename C, int R> struct Dft;
 
@@ -169,11 +179,13 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
     const int L = fl.L, LP = L + kLinePad;
     const int B = a.lines_per_block;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int o = blockIdx.y;
+    const int nchunk = (int)((a.inner + B - 1) / B);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int o = blk / nchunk;
     const long long obase =
         (long long)(a.outer_band_N ? band_pos(o, a.outer_band_N, a.outer_Nt) : o) * a.outer_stride;
     const long long inner = a.inner;
-    const long long i0 = (long long)blockIdx.x * B;
+    const long long i0 = (long long)(blk - o * nchunk) * B;
     const C zero = cmake<C>((T)0, (T)0);
 
     const int nin = a.in_band_N ? a.in_band_N : L;
@@ -284,7 +296,12 @@ static hipError_t fft_axis_t(const nfft_plan_s &p, void *grid, const AxisPass &a
     const FftLine &fl = p.line[a.axis];
     const int B = a.lines_per_block;
     const size_t shm = (size_t)B * (fl.L + kLinePad) * sizeof(cplx<T>);
-    const dim3 g((unsigned)((a.inner + B - 1) / B), (unsigned)a.outer_len);
+    const dim3 g((unsigned)(((a.inner + B - 1) / B) * a.outer_len));
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_strided<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_fft_strided<T>, g, dim3(B * fl.tpl), shm, s, (cplx<T> *)grid, fl, a);
     return hipGetLastError();
 }

@@ -4,14 +4,26 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/nfft.h"
+#include "nfft.h"
 
 namespace nfft {
 
 constexpr int kMaxD = 3;
 constexpr int kMaxRadixPasses = 16;
+constexpr int kResampleThreads = 256;  // workgroup size of the resampling kernels
 
-// Geometry of the oversampled grid and of its tiling, passed by value to kernels.
+// Nodes per staged chunk of the resampling kernels: one per thread, fewer in
+// 3-D, where the padded tile takes most of the LDS.
+constexpr int stage_chunk(int D, int rs) {
+    return D < 3 ? kResampleThreads : rs == 4 ? 128 : 64;
+}
+// Bytes of the staged chunk: D origins, D fractions, a complex value, an index.
+constexpr size_t stage_bytes(int D, int rs) {
+    return (size_t)stage_chunk(D, rs) * (4 * D + rs * (D + 2) + 4);
+}
+// LDS of the resampling kernels besides the tile: staged chunk and the scale.
+constexpr size_t resample_static_lds(int D, int rs) { return stage_bytes(D, rs) + 16; }
+
 struct Geom {
     int D;
     int m;
@@ -20,6 +32,13 @@ struct Geom {
     int T[kMaxD];    // tiles per axis = Nt / Q
     int ntiles;      // prod T
 };
+
+// Cells of a tile extended by the (2m-1)-wide trailing halo of every axis.
+inline size_t padded_cells(const Geom &g, int D) {
+    size_t c = 1;
+    for (int d = 0; d < D; ++d) c *= (size_t)(g.Q[d] + 2 * g.m - 1);
+    return c;
+}
 
 // Sorted node record: stencil origin (c - m + 1) mod Nt per axis and the
 // fractional cell offset frac = Nt*x - floor(Nt*x) in [0, 1).
@@ -79,7 +98,7 @@ struct nfft_plan_s {
     nfft::Geom geom;
     int64_t G;            // prod Nt
     int nkeys;            // ntiles << D
-    int nsub;             // interpolation work items
+    int nsub;             // resampling work items
     int device;
 
     // device buffers
@@ -89,7 +108,9 @@ struct nfft_plan_s {
     void *nodes = nullptr;         // M sorted NodeRec
     int *perm = nullptr;           // M: sorted position -> caller's node index
     int *key_start = nullptr;      // nkeys + 1
-    int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}
+    int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}, grouped by tile
+    int *tile_sub = nullptr;       // ntiles + 1: first work item of each tile
+    void *pad = nullptr;           // nsub padded tiles (spreading scratch), complex
     void *twiddle[nfft::kMaxD] = {nullptr, nullptr, nullptr};
     nfft::FftLine line[nfft::kMaxD];
 

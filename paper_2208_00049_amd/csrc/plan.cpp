@@ -86,22 +86,19 @@ bool factor_line(int L, FftLine &fl) {
     return fl.tpl <= 1024;
 }
 
-// LDS of the interpolation kernel: tile + halo, plus the staged node chunk
-// (256 nodes: D origins, D fractions, a complex value, an index) and range table.
+// LDS of the interpolation kernel: tile + halo plus the staged node chunk.
 size_t interp_lds(const int *Q, int D, int m, size_t cs) {
     size_t t = cs;
     for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + 2 * m - 1);
-    const size_t rs = cs / 2;
-    return t + 256 * (4 * D + rs * (D + 2) + 4) + 4 * (2 * (1 << (2 * D)) + 1);
+    return t + nfft::resample_static_lds(D, (int)cs / 2);
 }
 
-// LDS of the spreading kernel: fixed-point accumulators of the tile (one int64 per
-// component for c64, two for c128) plus the staged chunk of 512 nodes.
-size_t spread_lds(const int *Q, int D, size_t cs) {
+// LDS of the spreading kernel: fixed-point accumulators of the padded tile (one
+// int64 per component for c64, two for c128) plus the staged node chunk.
+size_t spread_lds(const int *Q, int D, int m, size_t cs) {
     size_t t = (cs == 8 ? 16 : 32);
-    for (int d = 0; d < D; ++d) t *= (size_t)Q[d];
-    const size_t rs = cs / 2;
-    return t + 512 * (4 * D + rs * (D + 2)) + 8 * (1 << (2 * D)) + 16;
+    for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + 2 * m - 1);
+    return t + nfft::resample_static_lds(D, (int)cs / 2);
 }
 
 bool valid_tile(int64_t Nt, int Q, int m) {
@@ -132,7 +129,7 @@ int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req,
             if (!valid_tile(Nt[d], req[d], m)) return NFFT_ERR_ARG;
             Q[d] = req[d];
         }
-        return interp_lds(Q, D, m, cs) <= budget && spread_lds(Q, D, cs) <= budget
+        return interp_lds(Q, D, m, cs) <= budget && spread_lds(Q, D, m, cs) <= budget
                    ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
     }
     int want[3];
@@ -147,7 +144,7 @@ int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req,
         if (!Q[d]) return NFFT_ERR_UNSUPPORTED;
     }
     // shrink the largest edge until both resampling kernels fit in LDS
-    while (interp_lds(Q, D, m, cs) > budget || spread_lds(Q, D, cs) > budget) {
+    while (interp_lds(Q, D, m, cs) > budget || spread_lds(Q, D, m, cs) > budget) {
         int best = -1;
         for (int d = 0; d < D; ++d) {
             const int q = pick_edge_down(Nt[d], Q[d] - 1, m);
@@ -256,6 +253,8 @@ void release(nfft_plan_s *p) {
     (void)hipFree(p->perm);
     (void)hipFree(p->key_start);
     (void)hipFree(p->subs);
+    (void)hipFree(p->tile_sub);
+    (void)hipFree(p->pad);
     delete p;
 }
 
@@ -378,7 +377,8 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     TRY(hipMalloc(&counts, (size_t)(p->nkeys + 1) * sizeof(int)));
     TRY(hipMalloc(&bad, sizeof(int)));
     TRY(hipMalloc(&subcnt, (size_t)(p->geom.ntiles + 1) * sizeof(int)));
-    TRY(hipMalloc(&substart, (size_t)(p->geom.ntiles + 1) * sizeof(int)));
+    TRY(hipMalloc(&p->tile_sub, (size_t)(p->geom.ntiles + 1) * sizeof(int)));
+    substart = p->tile_sub;
     if (M > 0) {
         TRY(hipMalloc(&p->nodes, (size_t)M * node_rec_size(dtype, D)));
         TRY(hipMalloc(&p->perm, (size_t)M * sizeof(int)));
@@ -423,6 +423,8 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     TRY(hipStreamSynchronize(s));
     p->nsub = host_nsub;
     if (host_bad) rc = NFFT_ERR_NODES;
+    if (rc == NFFT_OK && p->nsub > 0)
+        TRY(hipMalloc(&p->pad, (size_t)p->nsub * padded_cells(p->geom, D) * cs));
 
 fail:
     (void)hipFree(keys);
@@ -430,7 +432,6 @@ fail:
     (void)hipFree(cursor);
     (void)hipFree(bad);
     (void)hipFree(subcnt);
-    (void)hipFree(substart);
     (void)hipFree(polyscratch);
     if (rc != NFFT_OK) {
         release(p);

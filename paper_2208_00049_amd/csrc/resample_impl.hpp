@@ -11,24 +11,24 @@
 // over the taps of the other axes, taking their weights from the lanes that
 // computed them (DPP moves for 8-lane groups, shuffles otherwise).
 //
-// Both kernels work through their nodes in chunks of one node per thread: the
-// chunk's node data (and, for spreading, the gathered fhat values) are first
-// loaded by all threads at once into LDS, so the dependent global loads are
-// paid once per chunk instead of once per node.
+// Work items: the nodes of a tile (binned by the tile of their stencil origin)
+// are cut into items of bounded size, so that a dense tile is shared by several
+// workgroups.  Node data are staged through LDS in chunks of one node per
+// thread, so the dependent global loads are paid once per chunk.
 //
-// Interpolation (forward): the workgroup of a work item (tile, node range) copies
-// the tile plus a (2m-1)-wide trailing halo of the grid into LDS, wrapping the
-// indices at the copy (the paper's blocked Algorithm "Block-Partitioned
-// Resampling" with the copy-in of its local cache), then sums over the stencil
-// of every node and reduces the group's partial sums.
+// Interpolation (forward): the workgroup of an item copies the tile plus a
+// (2m-1)-wide trailing halo of the grid into LDS, wrapping the indices at the
+// copy (the paper's blocked Algorithm "Block-Partitioned Resampling" with the
+// copy-in of its local cache), then sums over the stencil of every node and
+// reduces the group's partial sums.
 //
-// Spreading (adjoint): the workgroup owns one tile of the output grid.  It
-// accumulates, with LDS atomics, the taps of every node whose stencil reaches
-// into the tile -- its own nodes and those of the preceding tiles whose class
-// bit says that their stencil crosses the tile border -- and writes the tile
-// once.  This replaces the locked addition into the global grid of the paper's
-// "Block-Partitioned Adjoint Resampling": each grid value has exactly one
-// writer and no global atomics are used.
+// Spreading (adjoint): the workgroup of an item accumulates its nodes' taps
+// into the padded tile (tile + trailing halo) with LDS atomics and writes the
+// padded tile to a scratch slot of its own; a merge kernel then sums, for every
+// grid point, the padded tiles that cover it.  This replaces the locked
+// addition into the global grid of the paper's "Block-Partitioned Adjoint
+// Resampling": each grid value has exactly one writer and no global atomics
+// are used.
 #pragma once
 
 #include <math.h>
@@ -37,8 +37,6 @@
 #include "nfft_internal.hpp"
 
 namespace nfft {
-
-constexpr int kResampleThreads = 256;  // workgroup size = nodes staged per chunk
 
 template <typename T> struct WinParams {
     T beta[kMaxD];
@@ -142,9 +140,24 @@ template <int G, typename T> struct BcastAll<G, G, T> {
 // ---- staged node data -------------------------------------------------------
 
 template <typename T, int D> struct Stage {
-    int l[D][kResampleThreads];   // stencil origin relative to the workgroup's tile
-    T fr[D][kResampleThreads];
-    int idx[kResampleThreads];    // caller's node index
+    static constexpr int kChunk = stage_chunk(D, (int)sizeof(T));
+    int l[D][kChunk];  // stencil origin relative to the workgroup's tile, in [0, Q)
+    T fr[D][kChunk];
+    T vr[kChunk];      // spreading: fhat value
+    T vi[kChunk];
+    int idx[kChunk];   // interpolation: caller's node index
+};
+
+// Lane li of a group computes the weight of tap li along every axis; cf holds
+// the polynomial coefficients of that tap per axis.
+template <typename T, int D, int M2> struct LaneWindow {
+    T cf[D][M2 + 1];
+    __device__ void load(const T *__restrict__ coef, int li) {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+#pragma unroll
+            for (int z = 0; z <= M2; ++z) cf[d][z] = coef[((size_t)d * M2 + li) * (M2 + 1) + z];
+    }
 };
 
 template <typename T, int D, int M2>
@@ -153,8 +166,8 @@ __global__ void __launch_bounds__(kResampleThreads)
              const int *__restrict__ perm, const int4 *__restrict__ subs,
              const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat) {
     using C = cplx<T>;
-    constexpr int Z = M2 + 1;
     constexpr int NPW = 64 / M2;
+    constexpr int CH = Stage<T, D>::kChunk;
     extern __shared__ unsigned char smem_raw[];
     __shared__ Stage<T, D> st;
     C *tile = reinterpret_cast<C *>(smem_raw);
@@ -195,23 +208,20 @@ __global__ void __launch_bounds__(kResampleThreads)
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
-    T cf[D][Z];
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-#pragma unroll
-        for (int z = 0; z < Z; ++z) cf[d][z] = coef[((size_t)d * M2 + li) * Z + z];
+    LaneWindow<T, D, M2> lw;
+    lw.load(coef, li);
 
-    for (int c0 = sp.y; c0 < sp.z; c0 += kResampleThreads) {
-        const int n = min(kResampleThreads, sp.z - c0);
-        if (threadIdx.x < n) {
-            const int node = c0 + threadIdx.x;
+    for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
+        const int n = min(CH, sp.z - c0);
+        for (int k = threadIdx.x; k < n; k += kResampleThreads) {
+            const int node = c0 + k;
             const NodeRec<T, D> rec = nodes[node];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                st.l[d][threadIdx.x] = rec.o[d] - t0[d];
-                st.fr[d][threadIdx.x] = rec.fr[d];
+                st.l[d][k] = rec.o[d] - t0[d];
+                st.fr[d][k] = rec.fr[d];
             }
-            st.idx[threadIdx.x] = perm[node];
+            st.idx[k] = perm[node];
         }
         __syncthreads();  // also completes the tile copy on the first chunk
         for (int base = wave * NPW; base < n; base += (kResampleThreads / 64) * NPW) {
@@ -223,7 +233,7 @@ __global__ void __launch_bounds__(kResampleThreads)
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 l[d] = st.l[d][ks];
-                w[d] = tap_weight<T, M2>(cf[d], st.fr[d][ks], li, window, wp.beta[d]);
+                w[d] = tap_weight<T, M2>(lw.cf[d], st.fr[d][ks], li, window, wp.beta[d]);
             }
             T ar = (T)0, ai = (T)0;
             if constexpr (D == 1) {
@@ -273,169 +283,117 @@ __global__ void __launch_bounds__(kResampleThreads)
 
 // ---- spreading accumulators --------------------------------------------------
 //
-// LDS float atomics are slow on this hardware, so the tile is accumulated in
-// fixed point with 64-bit integer LDS atomics, which also makes the sum exact
-// and independent of the order of the additions.  Each workgroup picks a
-// power-of-two scale s from the largest |Re|, |Im| of its nodes' fhat and the
-// window maximum, so that every scaled contribution c*s is below 2^30 (c64) or
-// 2^62 (c128) in magnitude.
-//   c64:  c*s is rounded to an int32 and added to one int64 per component
+// LDS float atomics are slow on this hardware (measured about 30 times slower
+// than integer ones), so the tile is accumulated in fixed point with 64-bit
+// integer LDS atomics, which also makes the sum exact and independent of the
+// order of the additions.  Each workgroup picks a power-of-two scale s from the
+// largest |Re|, |Im| of its nodes' fhat and the window maximum, so that every
+// scaled contribution c*s is below 2^30 (c64) or 2^62 (c128) in magnitude.
+//   c64:  c*s is truncated to an int32 and added to one int64 per component
 //         (resolution 2^-30 of the largest possible contribution; no
 //         overflow below 2^33 contributions per grid point).
 //   c128: c*s is split into hi = floor(c*s / 2^32) and lo = c*s - hi*2^32 in
 //         [0, 2^32), added to an int64 and a uint64 per component (96 bits).
+// The accumulators of a grid point are adjacent: [Re slots][Im slots].
 template <typename T> struct FixedPoint;
 
 template <> struct FixedPoint<float> {
     static constexpr int kSlots = 1;  // int64 slots per component
     static constexpr double kLimit = 1073741824.0;  // 2^30
-    __device__ static inline void add(unsigned long long *acc, int idx, int qtot, float c, float s) {
-        const long long v = (long long)__float2int_rn(c * s);
-        atomicAdd(acc + idx, (unsigned long long)v);
-        (void)qtot;
+    // a: the grid point's accumulators; cr, ci: scaled contributions, |c| < 2^30
+    __device__ static inline void add(unsigned long long *a, float cr, float ci) {
+        atomicAdd(a, (unsigned long long)(long long)(int)cr);
+        atomicAdd(a + 1, (unsigned long long)(long long)(int)ci);
     }
-    __device__ static inline double read(const unsigned long long *acc, int idx, int qtot) {
-        (void)qtot;
-        return (double)(long long)acc[idx];
+    __device__ static inline double read(const unsigned long long *a, int comp) {
+        return (double)(long long)a[comp];
     }
 };
 
 template <> struct FixedPoint<double> {
     static constexpr int kSlots = 2;
     static constexpr double kLimit = 4611686018427387904.0;  // 2^62
-    __device__ static inline void add(unsigned long long *acc, int idx, int qtot, double c, double s) {
-        const double v = c * s;
+    __device__ static inline void add1(unsigned long long *a, double v) {
         const int hi = __double2int_rd(v * 2.3283064365386963e-10);  // floor(v / 2^32)
         const double rest = v - (double)hi * 4294967296.0;               // in [0, 2^32)
         const unsigned lo = __double2uint_rd(rest);
-        atomicAdd(acc + idx, (unsigned long long)(long long)hi);
-        atomicAdd(acc + qtot + idx, (unsigned long long)lo);
+        atomicAdd(a, (unsigned long long)(long long)hi);
+        atomicAdd(a + 1, (unsigned long long)lo);
     }
-    __device__ static inline double read(const unsigned long long *acc, int idx, int qtot) {
-        return (double)(long long)acc[idx] * 4294967296.0 + (double)acc[qtot + idx];
+    __device__ static inline void add(unsigned long long *a, double cr, double ci) {
+        add1(a, cr);
+        add1(a + 2, ci);
+    }
+    __device__ static inline double read(const unsigned long long *a, int comp) {
+        return (double)(long long)a[2 * comp] * 4294967296.0 + (double)a[2 * comp + 1];
     }
 };
 
-template <typename T, int D> struct SpreadStage {
-    static constexpr int kChunk = 2 * kResampleThreads;
-    int l[D][kChunk];  // stencil origin relative to the workgroup's tile
-    T fr[D][kChunk];
-    T vr[kChunk];      // fhat value
-    T vi[kChunk];
-};
-
+// Spreading of one work item (a tile's node range, at most a few hundred to a
+// thousand nodes).  The workgroup accumulates the item's contributions into
+// the tile extended by the (2m-1)-wide trailing halo, in LDS, and writes that
+// padded tile to its own slot of the scratch buffer.  Every node's stencil lies
+// inside the padded tile, so the tap loops carry no bounds tests.
 template <typename T, int D, int M2>
 __global__ void __launch_bounds__(kResampleThreads)
-    k_spread(cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
-             const int *__restrict__ perm, const int *__restrict__ key_start,
+    k_spread(cplx<T> *__restrict__ pad, Geom g, const NodeRec<T, D> *__restrict__ nodes,
+             const int *__restrict__ perm, const int4 *__restrict__ subs,
              const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
              const cplx<T> *__restrict__ fhat) {
     using C = cplx<T>;
     using FP = FixedPoint<T>;
-    constexpr int Z = M2 + 1;
     constexpr int NPW = 64 / M2;
-    constexpr int NR = 1 << (2 * D);  // (shift e, class) pairs
-    constexpr int CH = SpreadStage<T, D>::kChunk;
+    constexpr int CH = Stage<T, D>::kChunk;
+    constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
     extern __shared__ unsigned char smem_raw[];
-    __shared__ SpreadStage<T, D> st;
-    __shared__ int rbeg[NR];
-    __shared__ int rpre[NR + 1];
+    __shared__ Stage<T, D> st;
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double
 
-    const int p = blockIdx.x;
-    int tc[D], t0[D];
+    const int4 sp = subs[blockIdx.x];
+    int t0[D], P[D];
     {
-        int rem = p;
+        int rem = sp.x;
 #pragma unroll
         for (int d = D - 1; d >= 0; --d) {
-            tc[d] = rem % g.T[d];
+            const int tc = rem % g.T[d];
             rem /= g.T[d];
-            t0[d] = tc[d] * g.Q[d];
+            t0[d] = tc * g.Q[d];
+            P[d] = g.Q[d] + M2 - 1;
         }
     }
-    int qtot = 1;
+    int ptot = 1;
 #pragma unroll
-    for (int d = 0; d < D; ++d) qtot *= g.Q[d];
-    // fixed-point accumulators of the owned tile: [re slots][im slots], qtot each
-    unsigned long long *acc_re = reinterpret_cast<unsigned long long *>(smem_raw);
-    unsigned long long *acc_im = acc_re + FP::kSlots * qtot;
-    for (int i = threadIdx.x; i < 2 * FP::kSlots * qtot; i += kResampleThreads) acc_re[i] = 0ull;
+    for (int d = 0; d < D; ++d) ptot *= P[d];
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
+    for (int i = threadIdx.x; i < SL * ptot; i += kResampleThreads) acc[i] = 0ull;
     if (threadIdx.x == 0) amax_bits = 0ull;
 
-    // node ranges: entry r = e << D | cls, e = set of axes along which the
-    // source tile precedes this one; a preceding tile contributes only the
-    // classes whose stencils cross into this tile (cls contains e)
-    if (threadIdx.x < NR) {
-        const int r = threadIdx.x;
-        const int e = r >> D, cls = r & ((1 << D) - 1);
-        int len = 0, b = 0;
-        if ((cls & e) == e) {
-            int q = 0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                int qd = tc[d] - ((e >> d) & 1);
-                if (qd < 0) qd += g.T[d];
-                q = q * g.T[d] + qd;
-            }
-            const int key = (q << D) | cls;
-            b = key_start[key];
-            len = key_start[key + 1] - b;
-        }
-        rbeg[r] = b;
-        rpre[r + 1] = len;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        rpre[0] = 0;
-        for (int r = 0; r < NR; ++r) rpre[r + 1] += rpre[r];
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
-    T cf[D][Z];
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-#pragma unroll
-        for (int z = 0; z < Z; ++z) cf[d][z] = coef[((size_t)d * M2 + li) * Z + z];
-    __syncthreads();
-    const int total = rpre[NR];
+    LaneWindow<T, D, M2> lw;
+    lw.load(coef, li);
 
-    // stage node v of the workgroup's list into slot s; returns max(|Re|, |Im|)
-    auto stage = [&](int v, int slot) -> T {
-        int lo = 0, hi = NR;  // largest r with rpre[r] <= v (a non-empty range)
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (rpre[mid] <= v) lo = mid;
-            else hi = mid;
-        }
-        const int e = lo >> D;
-        const int node = rbeg[lo] + (v - rpre[lo]);
+    auto stage = [&](int node, int k) -> T {
         const NodeRec<T, D> rec = nodes[node];
         const C val = fhat[perm[node]];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            int ld = rec.o[d] - t0[d];
-            if (((e >> d) & 1) && ld >= 0) ld -= g.Nt[d];
-            st.l[d][slot] = ld;
-            st.fr[d][slot] = rec.fr[d];
+            st.l[d][k] = rec.o[d] - t0[d];
+            st.fr[d][k] = rec.fr[d];
         }
-        st.vr[slot] = val.x;
-        st.vi[slot] = val.y;
+        st.vr[k] = val.x;
+        st.vi[k] = val.y;
         return fmax(fabs(val.x), fabs(val.y));
     };
 
-    // pass over all nodes for the scale; the first chunk is staged on the way
+    // pass over the item's nodes for the scale; the first chunk is staged on the way
+    __syncthreads();
     T amax = (T)0;
-    for (int v = threadIdx.x; v < total; v += kResampleThreads) {
+    for (int v = threadIdx.x; v < sp.z - sp.y; v += kResampleThreads) {
         if (v < CH) {
-            amax = fmax(amax, stage(v, v));
+            amax = fmax(amax, stage(sp.y + v, v));
         } else {
-            int lo = 0, hi = NR;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (rpre[mid] <= v) lo = mid;
-                else hi = mid;
-            }
-            const C val = fhat[perm[rbeg[lo] + (v - rpre[lo])]];
+            const C val = fhat[perm[sp.y + v]];
             amax = fmax(amax, fmax(fabs(val.x), fabs(val.y)));
         }
     }
@@ -445,9 +403,9 @@ __global__ void __launch_bounds__(kResampleThreads)
     const double bound = __longlong_as_double((long long)amax_bits) * (double)wmax_prod;
     const T scale = bound > 0.0 ? (T)exp2(floor(log2(FP::kLimit / bound))) : (T)1;
 
-    for (int c0 = 0; c0 < total; c0 += CH) {
-        const int n = min(CH, total - c0);
-        if (c0 > 0) {
+    for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
+        const int n = min(CH, sp.z - c0);
+        if (c0 > sp.y) {
             for (int k = threadIdx.x; k < n; k += kResampleThreads) stage(c0 + k, k);
             __syncthreads();
         }
@@ -460,75 +418,114 @@ __global__ void __launch_bounds__(kResampleThreads)
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 l[d] = st.l[d][ks];
-                w[d] = tap_weight<T, M2>(cf[d], st.fr[d][ks], li, window, wp.beta[d]);
+                w[d] = tap_weight<T, M2>(lw.cf[d], st.fr[d][ks], li, window, wp.beta[d]);
             }
-            const int cl = l[D - 1] + li;
-            const bool okl = valid && cl >= 0 && cl < g.Q[D - 1];
-            const T wr = st.vr[ks] * w[D - 1], wi = st.vi[ks] * w[D - 1];
+            // the lane's tap along the last axis, with the value and the scale folded in
+            const T ws = valid ? w[D - 1] * scale : (T)0;
+            const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
             if constexpr (D == 1) {
-                if (okl) {
-                    FP::add(acc_re, cl, qtot, wr, scale);
-                    FP::add(acc_im, cl, qtot, wi, scale);
-                }
+                FP::add(acc + SL * (l[0] + li), pr, pi);
             } else if constexpr (D == 2) {
                 T w0[M2];
                 BcastAll<M2, 0, T>::run(w0, w[0], gbase);
-                const int Q1 = g.Q[1];
+                unsigned long long *ap = acc + SL * (l[0] * P[1] + l[1] + li);
+                const int rs = SL * P[1];
 #pragma unroll
-                for (int a = 0; a < M2; ++a) {
-                    const int r0 = l[0] + a;
-                    if (okl && r0 >= 0 && r0 < g.Q[0]) {
-                        const int idx = r0 * Q1 + cl;
-                        FP::add(acc_re, idx, qtot, w0[a] * wr, scale);
-                        FP::add(acc_im, idx, qtot, w0[a] * wi, scale);
-                    }
-                }
+                for (int a = 0; a < M2; ++a) FP::add(ap + a * rs, w0[a] * pr, w0[a] * pi);
             } else {
                 T w0[M2], w1[M2];
                 BcastAll<M2, 0, T>::run(w0, w[0], gbase);
                 BcastAll<M2, 0, T>::run(w1, w[1], gbase);
-                const int Q1 = g.Q[1], Q2 = g.Q[2];
+                unsigned long long *ap = acc + SL * ((l[0] * P[1] + l[1]) * P[2] + l[2] + li);
+                const int rs1 = SL * P[2], rs0 = SL * P[1] * P[2];
 #pragma unroll 2
                 for (int a = 0; a < M2; ++a) {
-                    const int r0 = l[0] + a;
-                    const bool ok0 = okl && r0 >= 0 && r0 < g.Q[0];
-                    const T ar = w0[a] * wr, ai = w0[a] * wi;
+                    const T ar = w0[a] * pr, ai = w0[a] * pi;
+                    unsigned long long *rp = ap + a * rs0;
 #pragma unroll
-                    for (int b = 0; b < M2; ++b) {
-                        const int r1 = l[1] + b;
-                        if (ok0 && r1 >= 0 && r1 < Q1) {
-                            const int idx = (r0 * Q1 + r1) * Q2 + cl;
-                            FP::add(acc_re, idx, qtot, w1[b] * ar, scale);
-                            FP::add(acc_im, idx, qtot, w1[b] * ai, scale);
-                        }
-                    }
+                    for (int b = 0; b < M2; ++b) FP::add(rp + b * rs1, w1[b] * ar, w1[b] * ai);
                 }
             }
         }
         __syncthreads();
     }
 
-    // write the owned tile: every grid value has exactly this one writer
-    const double inv = 1.0 / (double)scale;
+    // the padded tile goes to the item's scratch slot, unscaled
+    const T inv = (T)(1.0 / (double)scale);
+    C *out = pad + (size_t)blockIdx.x * ptot;
+    for (int idx = threadIdx.x; idx < ptot; idx += kResampleThreads) {
+        const unsigned long long *ap = acc + SL * idx;
+        out[idx] = cmake<C>((T)FP::read(ap, 0) * inv, (T)FP::read(ap, 1) * inv);
+    }
+}
+
+// Halo merge: grid point l of tile p is the sum of the padded tiles that cover
+// it -- those of the work items of p and, within 2m-1 of p's leading edge along
+// a set e of axes, those of the tile preceding p along e (cyclically).  Each
+// grid value is written once, by one thread, in a fixed order of summation.
+template <typename T, int D>
+__global__ void __launch_bounds__(kResampleThreads)
+    k_spread_merge(cplx<T> *__restrict__ grid, Geom g, const cplx<T> *__restrict__ pad,
+                   const int *__restrict__ tile_sub, int M2) {
+    using C = cplx<T>;
+    const int p = blockIdx.x;
+    int tc[D], P[D];
+    int ptot = 1, qtot = 1;
+    {
+        int rem = p;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            tc[d] = rem % g.T[d];
+            rem /= g.T[d];
+            P[d] = g.Q[d] + M2 - 1;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ptot *= P[d];
+            qtot *= g.Q[d];
+        }
+    }
     for (int idx = threadIdx.x; idx < qtot; idx += kResampleThreads) {
-        int rem = idx;
         int a[D];
+        int rem = idx;
 #pragma unroll
         for (int d = D - 1; d >= 0; --d) {
             a[d] = rem % g.Q[d];
             rem /= g.Q[d];
         }
+        T sr = (T)0, si = (T)0;
+#pragma unroll
+        for (int e = 0; e < (1 << D); ++e) {
+            bool in = true;
+            int q = 0, off = 0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int ed = (e >> d) & 1;
+                if (ed && a[d] >= M2 - 1) in = false;
+                int qd = tc[d] - ed;
+                if (qd < 0) qd += g.T[d];
+                q = q * g.T[d] + qd;
+                off = off * P[d] + a[d] + (ed ? g.Q[d] : 0);
+            }
+            if (!in) continue;
+            for (int s = tile_sub[q]; s < tile_sub[q + 1]; ++s) {
+                const C v = pad[(size_t)s * ptot + off];
+                sr += v.x;
+                si += v.y;
+            }
+        }
         long long gi = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) gi = gi * g.Nt[d] + t0[d] + a[d];
-        grid[gi] = cmake<C>((T)(FP::read(acc_re, idx, qtot) * inv),
-                            (T)(FP::read(acc_im, idx, qtot) * inv));
+        for (int d = 0; d < D; ++d) gi = gi * g.Nt[d] + tc[d] * g.Q[d] + a[d];
+        grid[gi] = cmake<C>(sr, si);
     }
 }
 
-// Static LDS of the resampling kernels (staged node chunk and range table).
+// Static LDS of the resampling kernels (staged node chunk and the scale).
 template <typename T, int D> constexpr size_t static_lds() {
-    return sizeof(Stage<T, D>) + sizeof(SpreadStage<T, D>) + sizeof(int) * (2 * (1 << (2 * D)) + 2);
+    static_assert(sizeof(Stage<T, D>) <= stage_bytes(D, (int)sizeof(T)),
+                  "staged chunk larger than the LDS the plan reserves for it");
+    return resample_static_lds(D, (int)sizeof(T));
 }
 
 // Dynamic LDS beyond 64 KiB (static included) has to be allowed per kernel.
@@ -538,41 +535,47 @@ template <typename K> inline hipError_t allow_lds(K kernel, size_t dyn, size_t s
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
 }
 
-template <typename T, int D, int M2>
-hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
-    int tot = 1;
-    for (int d = 0; d < D; ++d) tot *= p.geom.Q[d] + M2 - 1;
-    const size_t shm = (size_t)tot * sizeof(cplx<T>);
+template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
     WinParams<T> wp;
     for (int d = 0; d < kMaxD; ++d)
-        wp.beta[d] = d < D ? (T)(M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d])) : (T)0;
+        wp.beta[d] = d < p.D ? (T)(M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d])) : (T)0;
+    return wp;
+}
+
+template <typename T, int D, int M2>
+hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
+    if (p.nsub == 0) return hipSuccess;
+    const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_interp<T, D, M2>, shm, static_lds<T, D>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_interp<T, D, M2>), dim3(p.nsub), dim3(kResampleThreads), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
-                       p.subs, (const T *)p.coef, p.window, wp, (cplx<T> *)fhat);
+                       p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat);
     return hipGetLastError();
 }
 
 template <typename T, int D, int M2>
 hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s) {
-    int tot = 1;
-    for (int d = 0; d < D; ++d) tot *= p.geom.Q[d];
-    const size_t shm = (size_t)tot * 2 * FixedPoint<T>::kSlots * sizeof(unsigned long long);
-    WinParams<T> wp;
-    double wprod = 1.0;
-    for (int d = 0; d < kMaxD; ++d) {
-        const double beta = d < D ? M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]) : 0.0;
-        wp.beta[d] = (T)beta;
-        // window maximum psi_hat_Base(0) = sinh(beta)/pi, with margin for the polynomial fit
-        if (d < D) wprod *= 1.5 * sinh(beta) / M_PI;
+    if (p.nsub > 0) {
+        const size_t shm = padded_cells(p.geom, D) * 2 * FixedPoint<T>::kSlots *
+                           sizeof(unsigned long long);
+        double wprod = 1.0;
+        for (int d = 0; d < D; ++d) {
+            const double beta = M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]);
+            // window maximum psi_hat_Base(0) = sinh(beta)/pi, with margin for the polynomial fit
+            wprod *= 1.5 * sinh(beta) / M_PI;
+        }
+        hipError_t e = allow_lds(k_spread<T, D, M2>, shm, static_lds<T, D>());
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_spread<T, D, M2>), dim3(p.nsub), dim3(kResampleThreads), shm, s,
+                           (cplx<T> *)p.pad, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
+                           p.subs, (const T *)p.coef, p.window, win_params<T>(p), (T)wprod,
+                           (const cplx<T> *)fhat);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    hipError_t e = allow_lds(k_spread<T, D, M2>, shm, static_lds<T, D>());
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_spread<T, D, M2>), dim3(p.geom.ntiles), dim3(kResampleThreads), shm, s,
-                       (cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
-                       p.key_start, (const T *)p.coef, p.window, wp, (T)wprod,
-                       (const cplx<T> *)fhat);
+    hipLaunchKernelGGL((k_spread_merge<T, D>), dim3(p.geom.ntiles), dim3(kResampleThreads), 0, s,
+                       (cplx<T> *)grid, p.geom, (const cplx<T> *)p.pad, p.tile_sub, M2);
     return hipGetLastError();
 }
 
