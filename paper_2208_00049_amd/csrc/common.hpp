@@ -39,4 +39,19 @@ __host__ __device__ inline int band_pos(int r, int N, int Nt) {
     return r < N / 2 ? Nt - N / 2 + r : r - N / 2;
 }
 
+// q = n / d and r = n % d for 0 <= n < 2^22 and d >= 1, given rcp = 1/d in
+// float: the float quotient is off by at most one, which one step corrects.
+__device__ inline int small_divmod(int n, int d, float rcp, int &r) {
+    int q = (int)((float)n * rcp);
+    r = n - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    return q;
+}
+
 }  // namespace nfft

@@ -152,9 +152,9 @@ __device__ inline void stockham_pass(C *line, bool active, int L, int p, int t, 
     __syncthreads();
 }
 
+// tw: the line's twiddle table W^j, j < L, in LDS
 template <typename C>
-__device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, int dir) {
-    const C *tw = (const C *)fl.tw;
+__device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, const C *tw, int dir) {
     int p = 1;
     for (int s = 0; s < fl.npass; ++s) {
         const int R = fl.rad[s];
@@ -177,7 +177,8 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
     extern __shared__ unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
-    const int B = a.lines_per_block;
+    const int B = a.lines_per_block;  // a power of two
+    const int lgB = __ffs(B) - 1;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nchunk = (int)((a.inner + B - 1) / B);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -188,18 +189,39 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
     const long long i0 = (long long)(blk - o * nchunk) * B;
     const C zero = cmake<C>((T)0, (T)0);
 
+    // twiddle table after the B lines (when it fits)
+    C *twl = lds + B * LP;
+    if (fl.tw_lds)
+        for (int j = tid; j < L; j += nthr) twl[j] = ((const C *)fl.tw)[j];
+    // load the band (or the whole lines): U loads per thread in flight at once
     const int nin = a.in_band_N ? a.in_band_N : L;
-    for (int idx = tid; idx < nin * B; idx += nthr) {
-        const int bb = idx % B, r = idx / B;
-        const int row = a.in_band_N ? band_pos(r, a.in_band_N, L) : r;
-        C v = zero;
-        if (i0 + bb < inner) v = grid[obase + (long long)row * inner + i0 + bb];
-        lds[bb * LP + row] = v;
+    {
+        constexpr int U = 8;
+        const int ntot = nin * B;
+        for (int base = 0; base < ntot; base += U * nthr) {
+            C v[U];
+            int dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * nthr + tid;
+                const int ic = idx < ntot ? idx : 0;
+                const int bb = ic & (B - 1), r = ic >> lgB;
+                const int row = a.in_band_N ? band_pos(r, a.in_band_N, L) : r;
+                const bool col_ok = i0 + bb < inner;
+                const long long col = col_ok ? i0 + bb : i0;  // i0 < inner always
+                v[u] = grid[obase + (long long)row * inner + col];
+                if (!col_ok) v[u] = zero;
+                dst[u] = idx < ntot ? bb * LP + row : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (dst[u] >= 0) lds[dst[u]] = v[u];
+        }
     }
     if (a.in_band_N) {
         const int nz = L - nin;
         for (int idx = tid; idx < nz * B; idx += nthr) {
-            const int bb = idx % B, r = idx / B;
+            const int bb = idx & (B - 1), r = idx >> lgB;
             lds[bb * LP + nin / 2 + r] = zero;
         }
     }
@@ -207,13 +229,152 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
 
     const int b = tid / fl.tpl, t = tid % fl.tpl;
     const bool active = b < B;
-    line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, a.dir);
+    if (fl.tw_lds) line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, twl, a.dir);
+    else line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw, a.dir);
 
     const int nout = a.out_band_N ? a.out_band_N : L;
     for (int idx = tid; idx < nout * B; idx += nthr) {
-        const int bb = idx % B, r = idx / B;
+        const int bb = idx & (B - 1), r = idx >> lgB;
         const int row = a.out_band_N ? band_pos(r, a.out_band_N, L) : r;
         if (i0 + bb < inner) grid[obase + (long long)row * inner + i0 + bb] = lds[bb * LP + row];
+    }
+}
+
+// Axis-0 pass of the adjoint (D >= 2, all Nt_0 rows in, the band of I_N out)
+// whose input is not the grid but the padded tiles of spreading: grid point
+// (c_0, c') is the sum, over the source tiles that cover it, of their work
+// items' padded-tile values (the halo merge, with the same summation order as
+// the merge kernel).  The B columns of a workgroup lie in one tile column, so
+// the item ranges of the tiles along axis 0 are read into LDS once.
+template <typename T, int D>
+__global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftLine fl, AxisPass a,
+                                                             PadSource ps) {
+    using C = cplx<T>;
+    constexpr int ER = 1 << (D - 1);  // shifts along the axes after axis 0
+    extern __shared__ unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const int L = fl.L, LP = L + kLinePad;
+    const int B = a.lines_per_block;  // a power of two dividing Q_{D-1}
+    const int lgB = __ffs(B) - 1;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const long long inner = a.inner;
+    const int i0 = blk * B;
+    const Geom &g = ps.g;
+    const int M2 = ps.M2;
+    C *twl = lds + B * LP;
+    int *rng = reinterpret_cast<int *>(twl + (fl.tw_lds ? L : 0));  // [T0][ER][2]
+
+    // tile column of the workgroup and the columns' offsets inside it
+    int tcr[D], ar[D];  // entries 1..D-1 used
+    if constexpr (D == 2) {
+        tcr[1] = i0 / g.Q[1];
+        ar[1] = i0 - tcr[1] * g.Q[1];
+    } else {
+        const int c1 = i0 / g.Nt[2], c2 = i0 - c1 * g.Nt[2];
+        tcr[1] = c1 / g.Q[1];
+        ar[1] = c1 - tcr[1] * g.Q[1];
+        tcr[2] = c2 / g.Q[2];
+        ar[2] = c2 - tcr[2] * g.Q[2];
+    }
+    int P[D], ptot = 1;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        P[d] = g.Q[d] + M2 - 1;
+        ptot *= P[d];
+    }
+    const int T0 = g.T[0];
+    for (int idx = tid; idx < T0 * ER; idx += nthr) {
+        const int tr = idx / ER, er = idx % ER;
+        int q = tr;
+#pragma unroll
+        for (int d = 1; d < D; ++d) {
+            int qd = tcr[d] - ((er >> (d - 1)) & 1);
+            if (qd < 0) qd += g.T[d];
+            q = q * g.T[d] + qd;
+        }
+        rng[2 * idx] = ps.tile_sub[q];
+        rng[2 * idx + 1] = ps.tile_sub[q + 1];
+    }
+    if (fl.tw_lds)
+        for (int j = tid; j < L; j += nthr) twl[j] = ((const C *)fl.tw)[j];
+    __syncthreads();
+
+    const C *pad = (const C *)ps.pad;
+    const float rq0 = 1.0f / (float)g.Q[0];
+    const int bb = tid & (B - 1);  // fixed per thread: nthr is a multiple of B
+    int al[D];                     // offsets of this thread's column, axes 1..D-1
+#pragma unroll
+    for (int d = 1; d < D; ++d) al[d] = ar[d];
+    al[D - 1] += bb;
+    constexpr int U = 4;
+    constexpr int NE = 2 * ER;
+    for (int base = 0; base < L * B; base += U * nthr) {
+        int off[U][NE], src[U][NE], r_of[U];
+        // per element and source tile: its first item (or -1) and the offset
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr + tid;
+            const int r = (idx < L * B ? idx : bb) >> lgB;
+            r_of[u] = idx < L * B ? r : -1;
+            int a0;
+            const int tr = small_divmod(r, g.Q[0], rq0, a0);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int e0 = e & 1, er = e >> 1;
+                bool ok = !(e0 && a0 >= M2 - 1);
+                int o = a0 + (e0 ? g.Q[0] : 0);
+#pragma unroll
+                for (int d = 1; d < D; ++d) {
+                    const int ed = (er >> (d - 1)) & 1;
+                    if (ed && al[d] >= M2 - 1) ok = false;
+                    o = o * P[d] + al[d] + (ed ? g.Q[d] : 0);
+                }
+                int trs = tr - e0;
+                if (trs < 0) trs += T0;
+                const int* rr = rng + 2 * (trs * ER + er);
+                src[u][e] = ok && rr[1] > rr[0] ? trs * ER + er : -1;
+                off[u][e] = o;
+            }
+        }
+        C v[U][NE];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+                v[u][e] = src[u][e] >= 0 ? pad[(size_t)rng[2 * src[u][e]] * ptot + off[u][e]]
+                                         : cmake<C>((T)0, (T)0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r_of[u] < 0) continue;
+            // bit d of e: the source precedes along axis d (the merge kernel's order)
+            T sr = (T)0, si = (T)0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                sr += v[u][e].x;
+                si += v[u][e].y;
+                if (src[u][e] >= 0)
+                    for (int s = rng[2 * src[u][e]] + 1; s < rng[2 * src[u][e] + 1]; ++s) {
+                        const C w = pad[(size_t)s * ptot + off[u][e]];
+                        sr += w.x;
+                        si += w.y;
+                    }
+            }
+            lds[bb * LP + r_of[u]] = cmake<C>(sr, si);
+        }
+    }
+    __syncthreads();
+
+    const int b = tid / fl.tpl, t = tid % fl.tpl;
+    const bool active = b < B;
+    if (fl.tw_lds) line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, twl, a.dir);
+    else line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw, a.dir);
+
+    const int nout = a.out_band_N ? a.out_band_N : L;
+    for (int idx = tid; idx < nout * B; idx += nthr) {
+        const int cb = idx & (B - 1), r = idx >> lgB;
+        const int row = a.out_band_N ? band_pos(r, a.out_band_N, L) : r;
+        if (i0 + cb < inner) grid[(long long)row * inner + i0 + cb] = lds[cb * LP + row];
     }
 }
 
@@ -234,6 +395,9 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     const int line_id = blockIdx.x * c.lines_per_block + b;
     const bool active = b < c.lines_per_block && line_id < c.nlines;
     C *line = lds + (b < c.lines_per_block ? b : 0) * LP;
+    C *twl = lds + c.lines_per_block * LP;  // twiddle table after the lines (when it fits)
+    if (fl.tw_lds)
+        for (int j = tid; j < L; j += blockDim.x) twl[j] = ((const C *)fl.tw)[j];
     const int D = c.D;
     const T *declast = D == 1 ? dec0 : (D == 2 ? dec1 : dec2);
 
@@ -263,39 +427,74 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     }
     const int Nl = c.N[D - 1];
 
+    // each thread owns k = t + j tpl, j < L / tpl <= 8 (the largest radix): all
+    // its loads are issued before the first LDS write
+    constexpr int KM = 8;
     if (active) {
+        C v[KM];
         if (c.mode == 1) {
-            for (int k = t; k < L; k += fl.tpl) {
-                C v = cmake<C>((T)0, (T)0);
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                const int k = t + j * fl.tpl;
                 int r = -1;
                 if (k < Nl / 2) r = k + Nl / 2;
-                else if (k >= L - Nl / 2) r = k - (L - Nl / 2);
-                if (r >= 0) v = cscale(src[frow + r], fac * declast[r]);
-                line[k] = v;
+                else if (k >= L - Nl / 2 && k < L) r = k - (L - Nl / 2);
+                const int rr = r >= 0 ? r : 0;
+                const C x = src[frow + rr];
+                const T s = fac * declast[rr];
+                v[j] = r >= 0 ? cscale(x, s) : cmake<C>((T)0, (T)0);
             }
         } else {
-            for (int k = t; k < L; k += fl.tpl) line[k] = src[grow + k];
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                const int k = t + j * fl.tpl;
+                v[j] = src[grow + (k < L ? k : 0)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+            const int k = t + j * fl.tpl;
+            if (k < L) line[k] = v[j];
         }
     }
     __syncthreads();
 
-    line_fft<C>(line, active, t, fl, c.dir);
+    if (fl.tw_lds) line_fft<C>(line, active, t, fl, twl, c.dir);
+    else line_fft<C>(line, active, t, fl, (const C *)fl.tw, c.dir);
 
     if (active) {
         if (c.mode == 2) {
-            for (int r = t; r < Nl; r += fl.tpl)
-                dst[frow + r] = cscale(line[band_pos(r, Nl, L)], fac * declast[r]);
+            T dl[KM];
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                const int r = t + j * fl.tpl;
+                dl[j] = declast[r < Nl ? r : 0];
+            }
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                const int r = t + j * fl.tpl;
+                if (r < Nl) dst[frow + r] = cscale(line[band_pos(r, Nl, L)], fac * dl[j]);
+            }
         } else {
             for (int k = t; k < L; k += fl.tpl) dst[grow + k] = line[k];
         }
     }
 }
 
+// The twiddle table goes to LDS when the pass's lines leave room for it.
+inline FftLine with_lds_table(const nfft_plan_s &p, const FftLine &fl, int B, size_t cs, size_t &shm) {
+    FftLine out = fl;
+    const size_t lines = (size_t)B * (fl.L + kLinePad) * cs;
+    out.tw_lds = lines + (size_t)fl.L * cs <= (size_t)p.lds_limit;
+    shm = lines + (out.tw_lds ? (size_t)fl.L * cs : 0);
+    return out;
+}
+
 template <typename T>
 static hipError_t fft_axis_t(const nfft_plan_s &p, void *grid, const AxisPass &a, hipStream_t s) {
-    const FftLine &fl = p.line[a.axis];
     const int B = a.lines_per_block;
-    const size_t shm = (size_t)B * (fl.L + kLinePad) * sizeof(cplx<T>);
+    size_t shm = 0;
+    const FftLine fl = with_lds_table(p, p.line[a.axis], B, sizeof(cplx<T>), shm);
     const dim3 g((unsigned)(((a.inner + B - 1) / B) * a.outer_len));
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_strided<T>),
@@ -309,10 +508,15 @@ static hipError_t fft_axis_t(const nfft_plan_s &p, void *grid, const AxisPass &a
 template <typename T>
 static hipError_t fft_contig_t(const nfft_plan_s &p, const void *src, void *dst,
                                const ContigPass &c, hipStream_t s) {
-    const FftLine &fl = p.line[p.D - 1];
     const int B = c.lines_per_block;
-    const size_t shm = (size_t)B * (fl.L + kLinePad) * sizeof(cplx<T>);
+    size_t shm = 0;
+    const FftLine fl = with_lds_table(p, p.line[p.D - 1], B, sizeof(cplx<T>), shm);
     const dim3 g((unsigned)((c.nlines + B - 1) / B));
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_contig<T>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_fft_contig<T>, g, dim3(B * fl.tpl), shm, s, (const cplx<T> *)src,
                        (cplx<T> *)dst, fl, c, (const T *)p.deconv[0], (const T *)p.deconv[1],
                        (const T *)p.deconv[2]);
@@ -322,6 +526,43 @@ static hipError_t fft_contig_t(const nfft_plan_s &p, const void *src, void *dst,
 hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, hipStream_t s) {
     if (a.outer_len == 0 || a.inner == 0) return hipSuccess;
     return p.dtype == NFFT_C64 ? fft_axis_t<float>(p, grid, a, s) : fft_axis_t<double>(p, grid, a, s);
+}
+
+hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const AxisPass &a,
+                                     hipStream_t s) {
+    const int B = a.lines_per_block;
+    const size_t cs = p.dtype == NFFT_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+    size_t shm = 0;
+    const FftLine fl = with_lds_table(p, p.line[0], B, cs, shm);
+    const int ER = 1 << (p.D - 1);
+    shm += (size_t)p.geom.T[0] * ER * 2 * sizeof(int);
+    PadSource ps{p.pad, p.tile_sub, p.geom, 2 * p.m};
+    const dim3 g((unsigned)(a.inner / B));
+    const void *k = nullptr;
+    if (p.dtype == NFFT_C64) k = p.D == 2 ? (const void *)k_fft_axis0_from_pad<float, 2>
+                                          : (const void *)k_fft_axis0_from_pad<float, 3>;
+    else k = p.D == 2 ? (const void *)k_fft_axis0_from_pad<double, 2>
+                      : (const void *)k_fft_axis0_from_pad<double, 3>;
+    if (shm > 65536) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    if (p.dtype == NFFT_C64) {
+        if (p.D == 2)
+            hipLaunchKernelGGL((k_fft_axis0_from_pad<float, 2>), g, dim3(B * fl.tpl), shm, s,
+                               (cplx<float> *)grid, fl, a, ps);
+        else
+            hipLaunchKernelGGL((k_fft_axis0_from_pad<float, 3>), g, dim3(B * fl.tpl), shm, s,
+                               (cplx<float> *)grid, fl, a, ps);
+    } else {
+        if (p.D == 2)
+            hipLaunchKernelGGL((k_fft_axis0_from_pad<double, 2>), g, dim3(B * fl.tpl), shm, s,
+                               (cplx<double> *)grid, fl, a, ps);
+        else
+            hipLaunchKernelGGL((k_fft_axis0_from_pad<double, 3>), g, dim3(B * fl.tpl), shm, s,
+                               (cplx<double> *)grid, fl, a, ps);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, const ContigPass &c,

@@ -12,10 +12,11 @@ constexpr int kMaxD = 3;
 constexpr int kMaxRadixPasses = 16;
 constexpr int kResampleThreads = 256;  // workgroup size of the resampling kernels
 
-// Nodes per staged chunk of the resampling kernels: one per thread, fewer in
-// 3-D, where the padded tile takes most of the LDS.
+// Nodes per staged chunk of the resampling kernels: two per thread in 1-D and
+// 2-D (a typical work item then needs one chunk), fewer in 3-D, where the
+// padded tile takes most of the LDS.
 constexpr int stage_chunk(int D, int rs) {
-    return D < 3 ? kResampleThreads : rs == 4 ? 128 : 64;
+    return D < 3 ? 2 * kResampleThreads : rs == 4 ? 128 : 64;
 }
 // Bytes of the staged chunk: D origins, D fractions, a complex value, an index.
 constexpr size_t stage_bytes(int D, int rs) {
@@ -54,6 +55,7 @@ struct FftLine {
     int rad[kMaxRadixPasses];
     int tpl;              // threads per line = L / largest radix
     const void *tw;       // device, L complex values of the plan's type
+    int tw_lds;           // 1: a pass copies the table into LDS (it fits beside its lines)
 };
 
 // One axis pass of the oversampled FFT over a grid viewed as [outer][L][inner].
@@ -66,11 +68,20 @@ struct AxisPass {
     long long outer_stride;  // elements between consecutive outer positions
     int in_band_N;        // 0: load the whole line; else only the band rows (others are zero)
     int out_band_N;       // 0: store the whole line; else only the band rows
-    int lines_per_block;  // B
+    int lines_per_block;  // B, a power of two
     int dir;              // -1 forward, +1 adjoint
 };
 
 // Last-axis pass with the resampling correction fused in.
+// Source of the first adjoint axis pass when it also performs the halo merge
+// of spreading: the padded tiles of the work items (see the merge kernel).
+struct PadSource {
+    const void *pad;      // nsub padded tiles, complex
+    const int *tile_sub;  // ntiles + 1: first work item of each tile
+    Geom g;
+    int M2;               // 2m
+};
+
 struct ContigPass {
     int mode;             // 0 plain grid->grid, 1 f -> grid (deconv + pad), 2 grid -> y (crop + deconv)
     int D;
@@ -100,6 +111,7 @@ struct nfft_plan_s {
     int nkeys;            // ntiles << D
     int nsub;             // resampling work items
     int device;
+    int lds_limit;        // LDS per workgroup of the device, bytes
 
     // device buffers
     void *grid = nullptr;          // G complex
@@ -141,11 +153,16 @@ hipError_t launch_subprob_fill(nfft_plan_s &p, const int *sub_start, hipStream_t
 
 // fft.hip
 hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, hipStream_t s);
+// axis-0 adjoint pass reading the merged padded tiles instead of the grid (D >= 2)
+hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const AxisPass &a,
+                                     hipStream_t s);
 hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, const ContigPass &c,
                              hipStream_t s);
 
 // resample.hip
 hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s);
-hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s);
+// merge = false: only the padded tiles are produced (the next pass merges them)
+hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                         bool merge = true);
 
 }  // namespace nfft

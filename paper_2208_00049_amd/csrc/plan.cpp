@@ -273,15 +273,18 @@ int hip_rc(hipError_t e) {
         }                                 \
     } while (0)
 
+// LDS of an FFT pass: B padded lines plus the twiddle table.
+size_t fft_lds(const FftLine &fl, size_t cs, int B) { return ((size_t)B * (fl.L + 1) + fl.L) * cs; }
+
 int lines_per_block_contig(const FftLine &fl, size_t cs) {
     int B = std::max(1, 256 / fl.tpl);
-    while (B > 1 && (size_t)B * (fl.L + 1) * cs > kLdsBudget) --B;
+    while (B > 1 && fft_lds(fl, cs, B) > kLdsBudget) --B;
     return B;
 }
 
 int lines_per_block_strided(const FftLine &fl, size_t cs, int64_t inner) {
     int B = 16;
-    while (B > 1 && ((size_t)B * (fl.L + 1) * cs > kLdsBudget || B * fl.tpl > 1024 || B > inner)) B /= 2;
+    while (B > 1 && (fft_lds(fl, cs, B) > kLdsBudget || B * fl.tpl > 1024 || B > inner)) B /= 2;
     return B;
 }
 
@@ -344,6 +347,7 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         // tiles: prefer a 64 KiB LDS footprint, go up to the device limit if needed
         int dev_lds = 0;
         TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+        p->lds_limit = dev_lds;
         int Q[3] = {1, 1, 1};
         const int *req = opts ? opts->tile : nullptr;
         int trc = choose_tiles(D, p->Nt, m, dtype, req, kLdsBudget, Q);
@@ -539,8 +543,10 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
     return hipSuccess;
 }
 
-// adjoint FFT with crop + resampling correction fused into the last pass
-hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s) {
+// adjoint FFT with crop + resampling correction fused into the last pass;
+// from_pad: the first (axis-0) pass reads and merges the padded tiles of
+// spreading instead of the grid (D >= 2)
+hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s, bool from_pad) {
     const int D = p.D;
     const size_t cs = csize(p.dtype);
     for (int a = 0; a <= D - 2; ++a) {
@@ -559,10 +565,14 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s) {
         ap.out_band_N = (int)p.N[a];
         ap.dir = +1;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
+        const bool merge_here = from_pad && a == 0;
+        if (merge_here)  // the workgroup's columns must lie in one tile column
+            while (p.geom.Q[D - 1] % ap.lines_per_block) ap.lines_per_block /= 2;
         hipError_t e;
         {
             StageTimer t(p, a == 1 ? 6 : 5, s);
-            e = launch_fft_axis(p, p.grid, ap, s);
+            e = merge_here ? launch_fft_axis0_from_pad(p, p.grid, ap, s)
+                           : launch_fft_axis(p, p.grid, ap, s);
         }
         if (e != hipSuccess) return e;
     }
@@ -646,12 +656,16 @@ int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream) {
     int64_t n = 1;
     for (int d = 0; d < p->D; ++d) n *= p->N[d];
     if (p->M == 0) return hip_rc(launch_fill_zero_complex(y, n, p->dtype == NFFT_C128, s));
+    // 2-D: the halo merge of spreading is done by the first adjoint FFT pass (in
+    // 3-D the separate merge kernel is faster: a pass's columns would span one
+    // short tile edge, and each grid value gathers from up to eight tiles)
+    const bool fuse = p->D == 2;
     hipError_t e;
     {
         StageTimer t(*p, 4, s);
-        e = launch_spread(*p, fhat, p->grid, s);
+        e = launch_spread(*p, fhat, p->grid, s, !fuse);
     }
-    if (e == hipSuccess) e = adjoint_fft(*p, y, s);
+    if (e == hipSuccess) e = adjoint_fft(*p, y, s, fuse);
     return hip_rc(e);
 }
 

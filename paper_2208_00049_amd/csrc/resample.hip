@@ -28,11 +28,12 @@ static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, h
 }
 
 template <typename T>
-static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s) {
+static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                           bool merge) {
     switch (p.D) {
-        case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s)
-        case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s)
-        default: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s)
+        case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s, merge)
+        case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s, merge)
+        default: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s, merge)
     }
 }
 
@@ -41,8 +42,10 @@ hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hip
     return p.dtype == NFFT_C64 ? interp_t<float>(p, grid, fhat, s) : interp_t<double>(p, grid, fhat, s);
 }
 
-hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s) {
-    return p.dtype == NFFT_C64 ? spread_t<float>(p, fhat, grid, s) : spread_t<double>(p, fhat, grid, s);
+hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                         bool merge) {
+    return p.dtype == NFFT_C64 ? spread_t<float>(p, fhat, grid, s, merge)
+                               : spread_t<double>(p, fhat, grid, s, merge);
 }
 
 }  // namespace nfft

@@ -137,6 +137,23 @@ template <int G, typename T> struct BcastAll<G, G, T> {
     __device__ static inline void run(T *, T, int) {}
 };
 
+// ---- box traversal ------------------------------------------------------------
+
+// Row-wise traversal of a box whose last (contiguous) axis has n cells: each
+// wavefront takes 64/lpr rows at a time, lpr lanes per row (lpr = the smallest
+// power of two >= n, at most 64), so that no index needs a division per cell.
+struct BoxRows {
+    int lpr, rpw;
+    __device__ explicit BoxRows(int n) {
+        lpr = 64;
+        while (lpr >= 2 * n && lpr > 1) lpr >>= 1;
+        rpw = 64 / lpr;
+    }
+    __device__ int first_row() const { return (threadIdx.x >> 6) * rpw + (threadIdx.x & 63) / lpr; }
+    __device__ int row_step() const { return (kResampleThreads / 64) * rpw; }
+    __device__ int first_col() const { return (threadIdx.x & 63) % lpr; }
+};
+
 // ---- staged node data -------------------------------------------------------
 
 template <typename T, int D> struct Stage {
@@ -184,26 +201,46 @@ __global__ void __launch_bounds__(kResampleThreads)
             P[d] = g.Q[d] + M2 - 1;
         }
     }
-    // copy the tile and its trailing halo into LDS, wrapping at the grid edge
-    int total = 1;
+    // copy the tile and its trailing halo into LDS, wrapping at the grid edge;
+    // eight loads per thread are in flight before the first LDS write
+    {
+        int total = 1;
 #pragma unroll
-    for (int d = 0; d < D; ++d) total *= P[d];
-    for (int idx = threadIdx.x; idx < total; idx += kResampleThreads) {
-        int rem = idx;
-        long long gi = 0;
-        int a[D];
+        for (int d = 0; d < D; ++d) total *= P[d];
+        const float rl = 1.0f / (float)P[D - 1];
+        const float r1 = D == 3 ? 1.0f / (float)P[1] : 1.0f;
+        constexpr int U = 8;
+        for (int base = 0; base < total; base += U * kResampleThreads) {
+            C v[U];
+            int dst[U];
 #pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            a[d] = rem % P[d];
-            rem /= P[d];
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + u * kResampleThreads + threadIdx.x;
+                dst[u] = idx < total ? idx : -1;
+                int col;
+                const int row = small_divmod(idx < total ? idx : 0, P[D - 1], rl, col);
+                long long gb = 0;
+                if constexpr (D >= 2) {
+                    int a1 = 0;
+                    const int a0 = D == 3 ? small_divmod(row, P[1], r1, a1) : row;
+                    int c0 = t0[0] + a0;
+                    if (c0 >= g.Nt[0]) c0 -= g.Nt[0];
+                    gb = c0;
+                    if constexpr (D == 3) {
+                        int c1 = t0[1] + a1;
+                        if (c1 >= g.Nt[1]) c1 -= g.Nt[1];
+                        gb = gb * g.Nt[1] + c1;
+                    }
+                    gb *= g.Nt[D - 1];
+                }
+                int c = t0[D - 1] + col;
+                if (c >= g.Nt[D - 1]) c -= g.Nt[D - 1];
+                v[u] = grid[gb + c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (dst[u] >= 0) tile[dst[u]] = v[u];
         }
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            int c = t0[d] + a[d];
-            if (c >= g.Nt[d]) c -= g.Nt[d];
-            gi = gi * g.Nt[d] + c;
-        }
-        tile[idx] = grid[gi];
     }
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -213,15 +250,29 @@ __global__ void __launch_bounds__(kResampleThreads)
 
     for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
         const int n = min(CH, sp.z - c0);
-        for (int k = threadIdx.x; k < n; k += kResampleThreads) {
-            const int node = c0 + k;
-            const NodeRec<T, D> rec = nodes[node];
+        {
+            // all loads first (indices clamped into the item), then the LDS writes
+            constexpr int SJ = (CH + kResampleThreads - 1) / kResampleThreads;
+            NodeRec<T, D> rec[SJ];
+            int pm[SJ];
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                st.l[d][k] = rec.o[d] - t0[d];
-                st.fr[d][k] = rec.fr[d];
+            for (int j = 0; j < SJ; ++j) {
+                const int node = c0 + min(threadIdx.x + j * kResampleThreads, n - 1);
+                rec[j] = nodes[node];
+                pm[j] = perm[node];
             }
-            st.idx[k] = perm[node];
+#pragma unroll
+            for (int j = 0; j < SJ; ++j) {
+                const int k = threadIdx.x + j * kResampleThreads;
+                if (k < n) {
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        st.l[d][k] = rec[j].o[d] - t0[d];
+                        st.fr[d][k] = rec[j].fr[d];
+                    }
+                    st.idx[k] = pm[j];
+                }
+            }
         }
         __syncthreads();  // also completes the tile copy on the first chunk
         for (int base = wave * NPW; base < n; base += (kResampleThreads / 64) * NPW) {
@@ -257,7 +308,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 BcastAll<M2, 0, T>::run(w0, w[0], gbase);
                 BcastAll<M2, 0, T>::run(w1, w[1], gbase);
                 const C *base3 = tile + (l[0] * P[1] + l[1]) * P[2] + l[2] + li;
-#pragma unroll 2
+#pragma unroll
                 for (int a = 0; a < M2; ++a) {
                     T sr = (T)0, si = (T)0;
                     const C *rowp = base3 + a * P[1] * P[2];
@@ -373,40 +424,68 @@ __global__ void __launch_bounds__(kResampleThreads)
     LaneWindow<T, D, M2> lw;
     lw.load(coef, li);
 
-    auto stage = [&](int node, int k) -> T {
-        const NodeRec<T, D> rec = nodes[node];
-        const C val = fhat[perm[node]];
+    // Stage the chunk of nodes [c0, c0 + n) into LDS: all global loads of the
+    // thread's nodes are issued before the first one is waited for (indices are
+    // clamped into the item, so the loads need no guard); returns max |Re|, |Im|.
+    constexpr int SJ = (CH + kResampleThreads - 1) / kResampleThreads;
+    auto stage_chunk_nodes = [&](int c0, int n) -> T {
+        NodeRec<T, D> rec[SJ];
+        int pm[SJ];
+        C val[SJ];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            st.l[d][k] = rec.o[d] - t0[d];
-            st.fr[d][k] = rec.fr[d];
+        for (int j = 0; j < SJ; ++j) {
+            const int node = c0 + min(threadIdx.x + j * kResampleThreads, n - 1);
+            rec[j] = nodes[node];
+            pm[j] = perm[node];
         }
-        st.vr[k] = val.x;
-        st.vi[k] = val.y;
-        return fmax(fabs(val.x), fabs(val.y));
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) val[j] = fhat[pm[j]];
+        T mx = (T)0;
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) {
+            const int k = threadIdx.x + j * kResampleThreads;
+            if (k < n) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    st.l[d][k] = rec[j].o[d] - t0[d];
+                    st.fr[d][k] = rec[j].fr[d];
+                }
+                st.vr[k] = val[j].x;
+                st.vi[k] = val[j].y;
+                mx = fmax(mx, fmax(fabs(val[j].x), fabs(val[j].y)));
+            }
+        }
+        return mx;
     };
 
     // pass over the item's nodes for the scale; the first chunk is staged on the way
-    __syncthreads();
-    T amax = (T)0;
-    for (int v = threadIdx.x; v < sp.z - sp.y; v += kResampleThreads) {
-        if (v < CH) {
-            amax = fmax(amax, stage(sp.y + v, v));
-        } else {
-            const C val = fhat[perm[sp.y + v]];
-            amax = fmax(amax, fmax(fabs(val.x), fabs(val.y)));
-        }
+    const int nitem = sp.z - sp.y;
+    T amax = stage_chunk_nodes(sp.y, min(CH, nitem));
+    for (int v = CH + threadIdx.x; v < nitem; v += kResampleThreads) {
+        const C val = fhat[perm[sp.y + v]];
+        amax = fmax(amax, fmax(fabs(val.x), fabs(val.y)));
     }
-    atomicMax(&amax_bits, (unsigned long long)__double_as_longlong((double)amax));
+    // wavefront maximum, then one LDS atomic per wavefront (non-negative values
+    // order like their bit patterns)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    __syncthreads();  // amax_bits is initialised
+    if (lane == 0) atomicMax(&amax_bits, (unsigned long long)__double_as_longlong((double)amax));
     __syncthreads();
-    // power-of-two scale: every |contribution| * scale stays below the limit
+    // power-of-two scale: every |contribution| * scale stays below the limit;
+    // with limit/bound = f 2^e, f in [0.5, 1): scale = 2^(e-1)
     const double bound = __longlong_as_double((long long)amax_bits) * (double)wmax_prod;
-    const T scale = bound > 0.0 ? (T)exp2(floor(log2(FP::kLimit / bound))) : (T)1;
+    T scale = (T)1;
+    if (bound > 0.0) {
+        int e;
+        (void)frexp(FP::kLimit / bound, &e);
+        scale = (T)ldexp(1.0, e - 1);
+    }
 
     for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
         const int n = min(CH, sp.z - c0);
         if (c0 > sp.y) {
-            for (int k = threadIdx.x; k < n; k += kResampleThreads) stage(c0 + k, k);
+            (void)stage_chunk_nodes(c0, n);
             __syncthreads();
         }
         for (int base = wave * NPW; base < n; base += (kResampleThreads / 64) * NPW) {
@@ -438,7 +517,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 BcastAll<M2, 0, T>::run(w1, w[1], gbase);
                 unsigned long long *ap = acc + SL * ((l[0] * P[1] + l[1]) * P[2] + l[2] + li);
                 const int rs1 = SL * P[2], rs0 = SL * P[1] * P[2];
-#pragma unroll 2
+#pragma unroll
                 for (int a = 0; a < M2; ++a) {
                     const T ar = w0[a] * pr, ai = w0[a] * pi;
                     unsigned long long *rp = ap + a * rs0;
@@ -470,7 +549,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     using C = cplx<T>;
     const int p = blockIdx.x;
     int tc[D], P[D];
-    int ptot = 1, qtot = 1;
+    int ptot = 1;
     {
         int rem = p;
 #pragma unroll
@@ -480,44 +559,86 @@ __global__ void __launch_bounds__(kResampleThreads)
             P[d] = g.Q[d] + M2 - 1;
         }
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            ptot *= P[d];
-            qtot *= g.Q[d];
-        }
+        for (int d = 0; d < D; ++d) ptot *= P[d];
     }
-    for (int idx = threadIdx.x; idx < qtot; idx += kResampleThreads) {
-        int a[D];
-        int rem = idx;
+    // item ranges of the 2^D source tiles: e = set of axes along which the
+    // source precedes this tile
+    __shared__ int rng[2 << D];
+    if (threadIdx.x < (1 << D)) {
+        const int e = threadIdx.x;
+        int q = 0;
 #pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            a[d] = rem % g.Q[d];
-            rem /= g.Q[d];
+        for (int d = 0; d < D; ++d) {
+            int qd = tc[d] - ((e >> d) & 1);
+            if (qd < 0) qd += g.T[d];
+            q = q * g.T[d] + qd;
         }
-        T sr = (T)0, si = (T)0;
+        rng[2 * e] = tile_sub[q];
+        rng[2 * e + 1] = tile_sub[q + 1];
+    }
+    __syncthreads();
+    int qtot = 1;
 #pragma unroll
-        for (int e = 0; e < (1 << D); ++e) {
-            bool in = true;
-            int q = 0, off = 0;
+    for (int d = 0; d < D; ++d) qtot *= g.Q[d];
+    const float rl = 1.0f / (float)g.Q[D - 1];
+    const float r1 = D == 3 ? 1.0f / (float)g.Q[1] : 1.0f;
+    constexpr int U = 4;  // cells per thread and batch
+    constexpr int NE = 1 << D;
+    for (int base = 0; base < qtot; base += U * kResampleThreads) {
+        int a[U][D], off[U][NE];
+        bool in[U][NE];
+        // cell coordinates and, per source tile, the offset in its padded tile
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const int ed = (e >> d) & 1;
-                if (ed && a[d] >= M2 - 1) in = false;
-                int qd = tc[d] - ed;
-                if (qd < 0) qd += g.T[d];
-                q = q * g.T[d] + qd;
-                off = off * P[d] + a[d] + (ed ? g.Q[d] : 0);
-            }
-            if (!in) continue;
-            for (int s = tile_sub[q]; s < tile_sub[q + 1]; ++s) {
-                const C v = pad[(size_t)s * ptot + off];
-                sr += v.x;
-                si += v.y;
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * kResampleThreads + threadIdx.x;
+            int rest;
+            const int row = small_divmod(idx < qtot ? idx : 0, g.Q[D - 1], rl, rest);
+            a[u][D - 1] = rest;
+            if constexpr (D == 2) a[u][0] = row;
+            if constexpr (D == 3) a[u][0] = small_divmod(row, g.Q[1], r1, a[u][1]);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                bool ok = idx < qtot && rng[2 * e + 1] > rng[2 * e];
+                int o = 0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int ed = (e >> d) & 1;
+                    if (ed && a[u][d] >= M2 - 1) ok = false;
+                    o = o * P[d] + a[u][d] + (ed ? g.Q[d] : 0);
+                }
+                in[u][e] = ok;
+                off[u][e] = o;
             }
         }
-        long long gi = 0;
+        // first item of every source tile: all loads independent
+        C v[U][NE];
 #pragma unroll
-        for (int d = 0; d < D; ++d) gi = gi * g.Nt[d] + tc[d] * g.Q[d] + a[d];
-        grid[gi] = cmake<C>(sr, si);
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+                v[u][e] = in[u][e] ? pad[(size_t)rng[2 * e] * ptot + off[u][e]]
+                                            : cmake<C>((T)0, (T)0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * kResampleThreads + threadIdx.x;
+            if (idx >= qtot) continue;
+            T sr = (T)0, si = (T)0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                sr += v[u][e].x;
+                si += v[u][e].y;
+                if (in[u][e])  // further items of a split tile (rare)
+                    for (int s = rng[2 * e] + 1; s < rng[2 * e + 1]; ++s) {
+                        const C w = pad[(size_t)s * ptot + off[u][e]];
+                        sr += w.x;
+                        si += w.y;
+                    }
+            }
+            long long gi = 0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) gi = gi * g.Nt[d] + tc[d] * g.Q[d] + a[u][d];
+            grid[gi] = cmake<C>(sr, si);
+        }
     }
 }
 
@@ -555,7 +676,7 @@ hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStr
 }
 
 template <typename T, int D, int M2>
-hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s) {
+hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s, bool merge) {
     if (p.nsub > 0) {
         const size_t shm = padded_cells(p.geom, D) * 2 * FixedPoint<T>::kSlots *
                            sizeof(unsigned long long);
@@ -574,6 +695,7 @@ hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStr
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (!merge) return hipSuccess;
     hipLaunchKernelGGL((k_spread_merge<T, D>), dim3(p.geom.ntiles), dim3(kResampleThreads), 0, s,
                        (cplx<T> *)grid, p.geom, (const cplx<T> *)p.pad, p.tile_sub, M2);
     return hipGetLastError();
