@@ -154,8 +154,12 @@ int nfft_plan_grid(nfft_plan_t p, void **grid);
  * recent forward and adjoint call, the elapsed milliseconds of each stage:
  *   0 forward: resampling correction + zero pad + FFT along the last axis
  *   1 forward: FFT along axis 1 (3-D only)      2 forward: FFT along axis 0
- *   3 forward: interpolation                     4 adjoint: spreading
- *   5 adjoint: FFT along axis 0                  6 adjoint: FFT along axis 1 (3-D)
+ *   3 forward: interpolation
+ *   4 adjoint: spreading into the work items' padded tiles (1-D, 3-D: and
+ *              the halo merge into the grid)
+ *   5 adjoint: FFT along axis 0 (2-D: reads the padded tiles and performs
+ *              the halo merge on the way)
+ *   6 adjoint: FFT along axis 1 (3-D)
  *   7 adjoint: FFT along the last axis + crop + resampling correction
  * Stages a plan does not run report 0.  ms must hold NFFT_NUM_STAGES values.
  * Timing adds an event record per kernel; leave it off when timing whole calls.
@@ -163,6 +167,22 @@ int nfft_plan_grid(nfft_plan_t p, void **grid);
 #define NFFT_NUM_STAGES 8
 int nfft_plan_set_timing(nfft_plan_t p, int enable);
 int nfft_plan_timing(nfft_plan_t p, double *ms);
+
+/*
+ * Back-to-back timing of one resampling stage (a measurement aid, e.g. for
+ * choosing tiles): launches the stage `reps` times on `stream` between two HIP
+ * events, synchronises the stream and stores the mean milliseconds per launch
+ * in *ms.
+ *   stage 3 (interpolation): reads the plan's grid, writes fhat (`out`, M
+ *            complex values, device).
+ *   stage 4 (spreading): reads fhat (`in`, M complex values, device) and
+ *            writes the plan's padded tiles; in 1-D and 3-D also the halo
+ *            merge into the plan's grid, as in nfft_adjoint.
+ * Errors: NFFT_ERR_ARG for another stage, reps < 1 or a missing pointer
+ * (when M > 0); NFFT_ERR_HIP for a failed launch or event.
+ */
+int nfft_plan_bench_stage(nfft_plan_t p, int stage, int reps, const void *in, void *out,
+                          void *stream, double *ms);
 
 /* Static description of an error code (never NULL). */
 const char *nfft_strerror(int code);

@@ -24,7 +24,7 @@ NFFT_WINDOW_DIRECT = 1
 EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft_forward",
            "nfft_adjoint", "nfft_resample_forward", "nfft_resample_adjoint", "nfft_fft_grid",
            "nfft_plan_info", "nfft_plan_grid", "nfft_plan_set_timing", "nfft_plan_timing",
-           "nfft_strerror"]
+           "nfft_plan_bench_stage", "nfft_strerror"]
 NFFT_NUM_STAGES = 8
 STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
           "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]

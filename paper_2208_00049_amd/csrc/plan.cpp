@@ -681,6 +681,30 @@ int nfft_resample_adjoint(nfft_plan_t p, const void *fhat, void *grid, void *str
     return hip_rc(launch_spread(*p, fhat, grid, s));
 }
 
+int nfft_plan_bench_stage(nfft_plan_t p, int stage, int reps, const void *in, void *out,
+                          void *stream, double *ms) {
+    if (!p || !ms || reps < 1 || (stage != 3 && stage != 4)) return NFFT_ERR_ARG;
+    if (p->M > 0 && ((stage == 3 && !out) || (stage == 4 && !in))) return NFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    int rc = NFFT_OK;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int i = 0; i < reps && e == hipSuccess && p->M > 0; ++i)
+        e = stage == 3 ? launch_interp(*p, p->grid, out, s)
+                       : launch_spread(*p, in, p->grid, s, p->D != 2);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (e == hipSuccess) *ms = (double)t / reps;
+    else rc = hip_rc(e);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return rc;
+}
+
 int nfft_plan_set_timing(nfft_plan_t p, int enable) {
     if (!p) return NFFT_ERR_ARG;
     if (enable && !p->ev[0]) {

@@ -98,6 +98,24 @@ class Plan:
         _lib.check(self._lib.nfft_plan_timing(self._h, ms), "nfft_plan_timing")
         return {name: ms[i] for i, name in enumerate(_lib.STAGES)}
 
+    def bench_stage(self, stage, reps, fhat=None):
+        """Mean milliseconds per launch of a resampling stage run `reps` times back to back:
+        "interp" (writes a scratch fhat) or "spread" (reads `fhat`)."""
+        idx = _lib.STAGES.index(stage)
+        if stage == "spread":
+            self._check(fhat, (self.M,), "fhat")
+            inp, out = ctypes.c_void_p(fhat.data_ptr()), None
+        elif stage == "interp":
+            buf = torch.empty(self.M, dtype=self.cdtype, device=self.device)
+            inp, out = None, ctypes.c_void_p(buf.data_ptr())
+        else:
+            raise ValueError("stage must be 'interp' or 'spread'")
+        ms = ctypes.c_double()
+        _lib.check(self._lib.nfft_plan_bench_stage(self._h, idx, int(reps), inp, out,
+                                                   _stream_handle(self.device), ctypes.byref(ms)),
+                   "nfft_plan_bench_stage")
+        return ms.value
+
     # -- transforms ----------------------------------------------------------
     def _check(self, t, shape, name):
         if not isinstance(t, torch.Tensor) or t.device != self.device:

@@ -80,5 +80,7 @@ def test_null_plan_calls(lib):
     assert lib.nfft_adjoint(None, FAKE, FAKE, None) == -1
     assert lib.nfft_plan_destroy(None) == 0
     assert lib.nfft_plan_info(None, None, None, None) == -1
+    ms = ctypes.c_double()
+    assert lib.nfft_plan_bench_stage(None, 3, 1, None, FAKE, None, ctypes.byref(ms)) == -1
     assert lib.nfft_strerror(-5).decode() == "node coordinate is NaN or infinite"
     assert lib.nfft_strerror(12345).decode() == "unknown error"
