@@ -78,7 +78,8 @@ typedef struct {
     int tile[3];          /* tile edge per axis in grid points, 0 = automatic.  Must divide
                              Ntilde_d, be >= 2m and leave >= 2 tiles per axis. */
     int window;           /* NFFT_WINDOW_POLY (default) or NFFT_WINDOW_DIRECT */
-    int max_block_nodes;  /* cap on nodes per interpolation work item, 0 = automatic */
+    int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
+                             into items of at most this many), 0 = automatic (1024) */
     int reserved[5];      /* must be zero */
 } nfft_options;
 
@@ -120,6 +121,51 @@ int nfft_forward(nfft_plan_t p, const void *f, void *fhat, void *stream);
  * y: prod(N) complex (device), overwritten.  With M == 0, y is set to zero.
  */
 int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream);
+
+/*
+ * Multi-channel transforms: K vectors through the same node set (the
+ * paper's transforms applied column by column to a K-column input).
+ * Forward: f holds K arrays of prod(N) complex values one after the other
+ * (channel-major), fhat K arrays of M.  Adjoint: fhat K x M in, y K x prod(N)
+ * out.  Every channel gives exactly what nfft_forward / nfft_adjoint give for
+ * it; the K channels share each kernel launch (second grid dimension).
+ * 1 <= K <= 65535.  The plan keeps K grids and K sets of spreading scratch:
+ * the first call with a K larger than any before allocates them (hipMalloc),
+ * later calls with K up to that allocate nothing.
+ */
+int nfft_forward_many(nfft_plan_t p, int K, const void *f, void *fhat, void *stream);
+int nfft_adjoint_many(nfft_plan_t p, int K, const void *fhat, void *y, void *stream);
+
+/*
+ * Batches of independent transforms (different plans, sizes and node sets),
+ * run as one HIP graph.  nfft_batch_create takes n distinct plans (a plan may
+ * appear once: its grid serves one transform at a time) and the number of
+ * streams (1..16) over which the transforms' kernel chains are spread inside
+ * the graph.  nfft_batch_forward / nfft_batch_adjoint take host arrays of n
+ * device pointers (in[i], out[i] as for nfft_forward / nfft_adjoint of plan i)
+ * and launch the graph on `stream`; the graph is captured on the first call
+ * and again whenever a pointer differs from the previous call's.  The plans
+ * must outlive the batch; their per-stage timing is not recorded in batch
+ * calls.  nfft_batch_destroy synchronises the device.
+ */
+typedef struct nfft_batch_s *nfft_batch_t;
+int nfft_batch_create(nfft_batch_t *out, int n, const nfft_plan_t *plans, int nstreams);
+int nfft_batch_forward(nfft_batch_t b, const void *const *f, void *const *fhat, void *stream);
+int nfft_batch_adjoint(nfft_batch_t b, const void *const *fhat, void *const *y, void *stream);
+int nfft_batch_destroy(nfft_batch_t b);
+
+/*
+ * Plan creation with tile autotuning: arguments as nfft_plan_create_ex.
+ * Unless opts fixes the tiles, plans are built for a short list of candidate
+ * tiles (then work-item caps for the best tile), forward + adjoint is timed
+ * `reps` times on `stream` for each, and the fastest plan is returned (its
+ * tiles: nfft_plan_info; its mean forward + adjoint milliseconds: *best_ms,
+ * which may be NULL).  Costs one plan creation and reps + 1 transform pairs per
+ * candidate.
+ */
+int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M, const void *x,
+                           int m, double sigma, nfft_dtype dtype, const nfft_options *opts,
+                           int reps, void *stream, double *best_ms);
 
 /*
  * The single steps, for step-wise checking and timing.  `grid` is a device

@@ -24,7 +24,9 @@ NFFT_WINDOW_DIRECT = 1
 EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft_forward",
            "nfft_adjoint", "nfft_resample_forward", "nfft_resample_adjoint", "nfft_fft_grid",
            "nfft_plan_info", "nfft_plan_grid", "nfft_plan_set_timing", "nfft_plan_timing",
-           "nfft_plan_bench_stage", "nfft_strerror"]
+           "nfft_plan_bench_stage", "nfft_forward_many", "nfft_adjoint_many",
+           "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
+           "nfft_plan_create_tuned", "nfft_strerror"]
 NFFT_NUM_STAGES = 8
 STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
           "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]
@@ -71,6 +73,21 @@ def load():
     lib.nfft_plan_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.nfft_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.nfft_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nfft_plan_bench_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.nfft_forward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.nfft_adjoint_many.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.nfft_batch_create.argtypes = [plan_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_int]
+    lib.nfft_batch_forward.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), vp]
+    lib.nfft_batch_adjoint.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), vp]
+    lib.nfft_batch_destroy.argtypes = [vp]
+    lib.nfft_plan_create_tuned.argtypes = [plan_p, ctypes.c_int, i64p, ctypes.c_int64, vp,
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(Options), ctypes.c_int, vp,
+                                           ctypes.POINTER(ctypes.c_double)]
     lib.nfft_strerror.argtypes = [ctypes.c_int]
     lib.nfft_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:

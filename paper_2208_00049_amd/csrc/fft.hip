@@ -174,6 +174,7 @@ __device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl, AxisPass a) {
     using C = cplx<T>;
+    grid += blockIdx.y * a.cstride;  // channel
     extern __shared__ unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
@@ -250,6 +251,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftLine fl, AxisPass a,
                                                              PadSource ps) {
     using C = cplx<T>;
+    grid += blockIdx.y * a.cstride;  // channel
     constexpr int ER = 1 << (D - 1);  // shifts along the axes after axis 0
     extern __shared__ unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -300,7 +302,7 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
         for (int j = tid; j < L; j += nthr) twl[j] = ((const C *)fl.tw)[j];
     __syncthreads();
 
-    const C *pad = (const C *)ps.pad;
+    const C *pad = (const C *)ps.pad + blockIdx.y * ps.cstride;
     const float rq0 = 1.0f / (float)g.Q[0];
     const int bb = tid & (B - 1);  // fixed per thread: nthr is a multiple of B
     int al[D];                     // offsets of this thread's column, axes 1..D-1
@@ -387,6 +389,8 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
                                                      ContigPass c, const T *dec0, const T *dec1,
                                                      const T *dec2) {
     using C = cplx<T>;
+    src += blockIdx.y * c.src_cstride;  // channel
+    dst += blockIdx.y * c.dst_cstride;
     extern __shared__ unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
@@ -495,7 +499,7 @@ static hipError_t fft_axis_t(const nfft_plan_s &p, void *grid, const AxisPass &a
     const int B = a.lines_per_block;
     size_t shm = 0;
     const FftLine fl = with_lds_table(p, p.line[a.axis], B, sizeof(cplx<T>), shm);
-    const dim3 g((unsigned)(((a.inner + B - 1) / B) * a.outer_len));
+    const dim3 g((unsigned)(((a.inner + B - 1) / B) * a.outer_len), (unsigned)a.K);
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_strided<T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -511,7 +515,7 @@ static hipError_t fft_contig_t(const nfft_plan_s &p, const void *src, void *dst,
     const int B = c.lines_per_block;
     size_t shm = 0;
     const FftLine fl = with_lds_table(p, p.line[p.D - 1], B, sizeof(cplx<T>), shm);
-    const dim3 g((unsigned)((c.nlines + B - 1) / B));
+    const dim3 g((unsigned)((c.nlines + B - 1) / B), (unsigned)c.K);
     if (shm > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_contig<T>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -529,15 +533,16 @@ hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, 
 }
 
 hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const AxisPass &a,
-                                     hipStream_t s) {
+                                     const void *pad, hipStream_t s) {
     const int B = a.lines_per_block;
     const size_t cs = p.dtype == NFFT_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
     size_t shm = 0;
     const FftLine fl = with_lds_table(p, p.line[0], B, cs, shm);
     const int ER = 1 << (p.D - 1);
     shm += (size_t)p.geom.T[0] * ER * 2 * sizeof(int);
-    PadSource ps{p.pad, p.tile_sub, p.geom, 2 * p.m};
-    const dim3 g((unsigned)(a.inner / B));
+    PadSource ps{pad, p.tile_sub, p.geom, 2 * p.m,
+                 (long long)p.nsub * (long long)padded_cells(p.geom, p.D)};
+    const dim3 g((unsigned)(a.inner / B), (unsigned)a.K);
     const void *k = nullptr;
     if (p.dtype == NFFT_C64) k = p.D == 2 ? (const void *)k_fft_axis0_from_pad<float, 2>
                                           : (const void *)k_fft_axis0_from_pad<float, 3>;

@@ -70,6 +70,8 @@ struct AxisPass {
     int out_band_N;       // 0: store the whole line; else only the band rows
     int lines_per_block;  // B, a power of two
     int dir;              // -1 forward, +1 adjoint
+    int K;                // channels (grid blockIdx.y), each a whole grid
+    long long cstride;    // elements between the channels' grids
 };
 
 // Last-axis pass with the resampling correction fused in.
@@ -80,6 +82,7 @@ struct PadSource {
     const int *tile_sub;  // ntiles + 1: first work item of each tile
     Geom g;
     int M2;               // 2m
+    long long cstride;    // elements between the channels' sets of padded tiles
 };
 
 struct ContigPass {
@@ -92,6 +95,9 @@ struct ContigPass {
     int Nt[kMaxD];
     int lines_per_block;
     int dir;
+    int K;                  // channels (grid blockIdx.y)
+    long long src_cstride;  // elements between channels of src
+    long long dst_cstride;  // elements between channels of dst
 };
 
 }  // namespace nfft
@@ -108,6 +114,7 @@ struct nfft_plan_s {
     int max_block_nodes;
     nfft::Geom geom;
     int64_t G;            // prod Nt
+    int64_t NN;           // prod N
     int nkeys;            // ntiles << D
     int nsub;             // resampling work items
     int device;
@@ -123,6 +130,10 @@ struct nfft_plan_s {
     int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}, grouped by tile
     int *tile_sub = nullptr;       // ntiles + 1: first work item of each tile
     void *pad = nullptr;           // nsub padded tiles (spreading scratch), complex
+    // multi-channel calls: K grids and K sets of padded tiles, grown on demand
+    void *grid_many = nullptr;
+    void *pad_many = nullptr;
+    int many_cap = 0;              // channels the two buffers hold
     void *twiddle[nfft::kMaxD] = {nullptr, nullptr, nullptr};
     nfft::FftLine line[nfft::kMaxD];
 
@@ -133,6 +144,10 @@ struct nfft_plan_s {
 };
 
 namespace nfft {
+
+// plan.cpp: the argument checks of plan creation (no HIP call)
+int validate_plan_args(int D, const int64_t *N, int64_t M, const void *x, int m, double sigma,
+                       int dtype, const nfft_options *opts);
 
 // precompute.hip
 hipError_t launch_deconv_factors(const nfft_plan_s &p, hipStream_t s);
@@ -155,14 +170,16 @@ hipError_t launch_subprob_fill(nfft_plan_s &p, const int *sub_start, hipStream_t
 hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, hipStream_t s);
 // axis-0 adjoint pass reading the merged padded tiles instead of the grid (D >= 2)
 hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const AxisPass &a,
-                                     hipStream_t s);
+                                     const void *pad, hipStream_t s);
 hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, const ContigPass &c,
                              hipStream_t s);
 
 // resample.hip
-hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s);
+// K channels: grids at stride G, fhat at stride M, padded tiles at stride pad_elems()
+hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                         int K = 1);
 // merge = false: only the padded tiles are produced (the next pass merges them)
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
-                         bool merge = true);
+                         bool merge = true, int K = 1, void *pad = nullptr);
 
 }  // namespace nfft

@@ -21,6 +21,7 @@ namespace {
 constexpr int kMaxM = 10;
 constexpr size_t kLdsBudget = 65536;
 constexpr int kDefaultBlockNodes = 1024;
+constexpr int kMaxChannels = 65535;  // channels of one multi-channel call (grid y dimension)
 
 bool is_235_smooth(int64_t v) {
     for (int p : {2, 3, 5})
@@ -255,6 +256,8 @@ void release(nfft_plan_s *p) {
     (void)hipFree(p->subs);
     (void)hipFree(p->tile_sub);
     (void)hipFree(p->pad);
+    (void)hipFree(p->grid_many);
+    (void)hipFree(p->pad_many);
     delete p;
 }
 
@@ -290,6 +293,13 @@ int lines_per_block_strided(const FftLine &fl, size_t cs, int64_t inner) {
 
 }  // namespace
 
+namespace nfft {
+int validate_plan_args(int D, const int64_t *N, int64_t M, const void *x, int m, double sigma,
+                       int dtype, const nfft_options *opts) {
+    return validate(D, N, M, x, m, sigma, dtype, opts);
+}
+}  // namespace nfft
+
 extern "C" {
 
 const char *nfft_strerror(int code) {
@@ -319,10 +329,12 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     p->window = opts ? opts->window : NFFT_WINDOW_POLY;
     p->max_block_nodes = (opts && opts->max_block_nodes) ? opts->max_block_nodes : kDefaultBlockNodes;
     p->G = 1;
+    p->NN = 1;
     for (int d = 0; d < kMaxD; ++d) {
         p->N[d] = d < D ? N[d] : 1;
         p->Nt[d] = d < D ? oversampled(N[d], sigma) : 1;
         if (d < D) p->G *= p->Nt[d];
+        if (d < D) p->NN *= p->N[d];
     }
     for (int d = 0; d < D; ++d) {
         if (!factor_line((int)p->Nt[d], p->line[d])) {
@@ -493,11 +505,15 @@ struct StageTimer {
     }
 };
 
-// forward FFT with the resampling correction fused into the first (last-axis) pass
-hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
+// forward FFT with the resampling correction fused into the first (last-axis)
+// pass; K channels: f at stride prod(N), grids at stride G
+hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, hipStream_t s) {
     const int D = p.D;
     const size_t cs = csize(p.dtype);
     ContigPass c{};
+    c.K = K;
+    c.src_cstride = p.NN;
+    c.dst_cstride = p.G;
     c.mode = 1;
     c.D = D;
     c.dir = -1;
@@ -515,7 +531,7 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
     hipError_t e;
     {
         StageTimer t(p, 0, s);
-        e = launch_fft_contig(p, f, p.grid, c, s);
+        e = launch_fft_contig(p, f, grid, c, s);
     }
     if (e != hipSuccess) return e;
     for (int a = D - 2; a >= 0; --a) {
@@ -533,10 +549,12 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
         ap.in_band_N = (int)p.N[a];
         ap.out_band_N = 0;
         ap.dir = -1;
+        ap.K = K;
+        ap.cstride = p.G;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
         {
             StageTimer t(p, a == 1 ? 1 : 2, s);
-            e = launch_fft_axis(p, p.grid, ap, s);
+            e = launch_fft_axis(p, grid, ap, s);
         }
         if (e != hipSuccess) return e;
     }
@@ -546,7 +564,8 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, hipStream_t s) {
 // adjoint FFT with crop + resampling correction fused into the last pass;
 // from_pad: the first (axis-0) pass reads and merges the padded tiles of
 // spreading instead of the grid (D >= 2)
-hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s, bool from_pad) {
+hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pad, int K,
+                       hipStream_t s, bool from_pad) {
     const int D = p.D;
     const size_t cs = csize(p.dtype);
     for (int a = 0; a <= D - 2; ++a) {
@@ -564,6 +583,8 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s, bool from_p
         ap.in_band_N = 0;
         ap.out_band_N = (int)p.N[a];
         ap.dir = +1;
+        ap.K = K;
+        ap.cstride = p.G;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
         const bool merge_here = from_pad && a == 0;
         if (merge_here)  // the workgroup's columns must lie in one tile column
@@ -571,12 +592,15 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s, bool from_p
         hipError_t e;
         {
             StageTimer t(p, a == 1 ? 6 : 5, s);
-            e = merge_here ? launch_fft_axis0_from_pad(p, p.grid, ap, s)
-                           : launch_fft_axis(p, p.grid, ap, s);
+            e = merge_here ? launch_fft_axis0_from_pad(p, grid, ap, pad, s)
+                           : launch_fft_axis(p, grid, ap, s);
         }
         if (e != hipSuccess) return e;
     }
     ContigPass c{};
+    c.K = K;
+    c.src_cstride = p.G;
+    c.dst_cstride = p.NN;
     c.mode = 2;
     c.D = D;
     c.dir = +1;
@@ -592,7 +616,7 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, hipStream_t s, bool from_p
     }
     c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
     StageTimer t(p, 7, s);
-    return launch_fft_contig(p, p.grid, y, c, s);
+    return launch_fft_contig(p, grid, y, c, s);
 }
 
 // plain unpruned FFT of a whole grid, all axes
@@ -600,6 +624,7 @@ hipError_t plain_fft(const nfft_plan_s &p, void *grid, int dir, hipStream_t s) {
     const int D = p.D;
     const size_t cs = csize(p.dtype);
     ContigPass c{};
+    c.K = 1;
     c.mode = 0;
     c.D = D;
     c.dir = dir;
@@ -627,11 +652,52 @@ hipError_t plain_fft(const nfft_plan_s &p, void *grid, int dir, hipStream_t s) {
             ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
         }
         ap.dir = dir;
+        ap.K = 1;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
         e = launch_fft_axis(p, grid, ap, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Make room for K channels' grids and padded tiles (multi-channel calls).
+hipError_t ensure_channels(nfft_plan_s &p, int K) {
+    if (K <= p.many_cap) return hipSuccess;
+    (void)hipFree(p.grid_many);
+    (void)hipFree(p.pad_many);
+    p.grid_many = p.pad_many = nullptr;
+    p.many_cap = 0;
+    const size_t cs = csize(p.dtype);
+    hipError_t e = hipMalloc(&p.grid_many, (size_t)K * p.G * cs);
+    if (e == hipSuccess && p.nsub > 0)
+        e = hipMalloc(&p.pad_many, (size_t)K * p.nsub * padded_cells(p.geom, p.D) * cs);
+    if (e == hipSuccess) p.many_cap = K;
+    return e;
+}
+
+hipError_t run_forward(const nfft_plan_s &p, const void *f, void *fhat, int K, void *grid,
+                       hipStream_t s) {
+    hipError_t e = forward_fft(p, f, grid, K, s);
+    if (e == hipSuccess) {
+        StageTimer t(p, 3, s);
+        e = launch_interp(p, grid, fhat, s, K);
+    }
+    return e;
+}
+
+hipError_t run_adjoint(const nfft_plan_s &p, const void *fhat, void *y, int K, void *grid,
+                       void *pad, hipStream_t s) {
+    // 2-D: the halo merge of spreading is done by the first adjoint FFT pass (in
+    // 3-D the separate merge kernel is faster: a pass's columns would span one
+    // short tile edge, and each grid value gathers from up to eight tiles)
+    const bool fuse = p.D == 2;
+    hipError_t e;
+    {
+        StageTimer t(p, 4, s);
+        e = launch_spread(p, fhat, grid, s, !fuse, K, pad);
+    }
+    if (e == hipSuccess) e = adjoint_fft(p, y, grid, pad, K, s, fuse);
+    return e;
 }
 
 }  // namespace
@@ -641,31 +707,31 @@ extern "C" {
 int nfft_forward(nfft_plan_t p, const void *f, void *fhat, void *stream) {
     if (!p || !f || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
     if (p->M == 0) return NFFT_OK;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = forward_fft(*p, f, s);
-    if (e == hipSuccess) {
-        StageTimer t(*p, 3, s);
-        e = launch_interp(*p, p->grid, fhat, s);
-    }
-    return hip_rc(e);
+    return hip_rc(run_forward(*p, f, fhat, 1, p->grid, (hipStream_t)stream));
 }
 
 int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream) {
     if (!p || !y || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
-    int64_t n = 1;
-    for (int d = 0; d < p->D; ++d) n *= p->N[d];
-    if (p->M == 0) return hip_rc(launch_fill_zero_complex(y, n, p->dtype == NFFT_C128, s));
-    // 2-D: the halo merge of spreading is done by the first adjoint FFT pass (in
-    // 3-D the separate merge kernel is faster: a pass's columns would span one
-    // short tile edge, and each grid value gathers from up to eight tiles)
-    const bool fuse = p->D == 2;
-    hipError_t e;
-    {
-        StageTimer t(*p, 4, s);
-        e = launch_spread(*p, fhat, p->grid, s, !fuse);
-    }
-    if (e == hipSuccess) e = adjoint_fft(*p, y, s, fuse);
+    if (p->M == 0) return hip_rc(launch_fill_zero_complex(y, p->NN, p->dtype == NFFT_C128, s));
+    return hip_rc(run_adjoint(*p, fhat, y, 1, p->grid, p->pad, s));
+}
+
+int nfft_forward_many(nfft_plan_t p, int K, const void *f, void *fhat, void *stream) {
+    if (!p || K < 1 || K > kMaxChannels || !f || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    if (p->M == 0) return NFFT_OK;
+    hipError_t e = ensure_channels(*p, K);
+    if (e == hipSuccess) e = run_forward(*p, f, fhat, K, p->grid_many, (hipStream_t)stream);
+    return hip_rc(e);
+}
+
+int nfft_adjoint_many(nfft_plan_t p, int K, const void *fhat, void *y, void *stream) {
+    if (!p || K < 1 || K > kMaxChannels || !y || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->M == 0)
+        return hip_rc(launch_fill_zero_complex(y, (int64_t)K * p->NN, p->dtype == NFFT_C128, s));
+    hipError_t e = ensure_channels(*p, K);
+    if (e == hipSuccess) e = run_adjoint(*p, fhat, y, K, p->grid_many, p->pad_many, s);
     return hip_rc(e);
 }
 

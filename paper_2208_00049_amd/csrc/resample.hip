@@ -19,33 +19,36 @@ namespace nfft {
     }
 
 template <typename T>
-static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
+static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                           int K) {
     switch (p.D) {
-        case 1: NFFT_DISPATCH_M(run_interp, T, 1, p, grid, fhat, s)
-        case 2: NFFT_DISPATCH_M(run_interp, T, 2, p, grid, fhat, s)
-        default: NFFT_DISPATCH_M(run_interp, T, 3, p, grid, fhat, s)
+        case 1: NFFT_DISPATCH_M(run_interp, T, 1, p, grid, fhat, s, K)
+        case 2: NFFT_DISPATCH_M(run_interp, T, 2, p, grid, fhat, s, K)
+        default: NFFT_DISPATCH_M(run_interp, T, 3, p, grid, fhat, s, K)
     }
 }
 
 template <typename T>
 static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
-                           bool merge) {
+                           bool merge, int K, void *pad) {
     switch (p.D) {
-        case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s, merge)
-        case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s, merge)
-        default: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s, merge)
+        case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s, merge, K, pad)
+        case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s, merge, K, pad)
+        default: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s, merge, K, pad)
     }
 }
 
-hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
+hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
-    return p.dtype == NFFT_C64 ? interp_t<float>(p, grid, fhat, s) : interp_t<double>(p, grid, fhat, s);
+    return p.dtype == NFFT_C64 ? interp_t<float>(p, grid, fhat, s, K)
+                               : interp_t<double>(p, grid, fhat, s, K);
 }
 
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
-                         bool merge) {
-    return p.dtype == NFFT_C64 ? spread_t<float>(p, fhat, grid, s, merge)
-                               : spread_t<double>(p, fhat, grid, s, merge);
+                         bool merge, int K, void *pad) {
+    if (!pad) pad = p.pad;
+    return p.dtype == NFFT_C64 ? spread_t<float>(p, fhat, grid, s, merge, K, pad)
+                               : spread_t<double>(p, fhat, grid, s, merge, K, pad);
 }
 
 }  // namespace nfft

@@ -181,8 +181,11 @@ template <typename T, int D, int M2>
 __global__ void __launch_bounds__(kResampleThreads)
     k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
-             const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat) {
+             const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat,
+             long long gstride, long long fstride) {
     using C = cplx<T>;
+    grid += blockIdx.y * gstride;  // channel
+    fhat += blockIdx.y * fstride;
     constexpr int NPW = 64 / M2;
     constexpr int CH = Stage<T, D>::kChunk;
     extern __shared__ unsigned char smem_raw[];
@@ -390,8 +393,10 @@ __global__ void __launch_bounds__(kResampleThreads)
     k_spread(cplx<T> *__restrict__ pad, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
              const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
-             const cplx<T> *__restrict__ fhat) {
+             const cplx<T> *__restrict__ fhat, long long pstride, long long fstride) {
     using C = cplx<T>;
+    pad += blockIdx.y * pstride;  // channel
+    fhat += blockIdx.y * fstride;
     using FP = FixedPoint<T>;
     constexpr int NPW = 64 / M2;
     constexpr int CH = Stage<T, D>::kChunk;
@@ -545,8 +550,10 @@ __global__ void __launch_bounds__(kResampleThreads)
 template <typename T, int D>
 __global__ void __launch_bounds__(kResampleThreads)
     k_spread_merge(cplx<T> *__restrict__ grid, Geom g, const cplx<T> *__restrict__ pad,
-                   const int *__restrict__ tile_sub, int M2) {
+                   const int *__restrict__ tile_sub, int M2, long long gstride, long long pstride) {
     using C = cplx<T>;
+    grid += blockIdx.y * gstride;  // channel
+    pad += blockIdx.y * pstride;
     const int p = blockIdx.x;
     int tc[D], P[D];
     int ptot = 1;
@@ -664,19 +671,22 @@ template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
 }
 
 template <typename T, int D, int M2>
-hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s) {
+hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
     const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
     hipError_t e = allow_lds(k_interp<T, D, M2>, shm, static_lds<T, D>());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_interp<T, D, M2>), dim3(p.nsub), dim3(kResampleThreads), shm, s,
+    hipLaunchKernelGGL((k_interp<T, D, M2>), dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
-                       p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat);
+                       p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
+                       (long long)p.G, (long long)p.M);
     return hipGetLastError();
 }
 
 template <typename T, int D, int M2>
-hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s, bool merge) {
+hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s, bool merge,
+                      int K, void *pad) {
+    const long long pstride = (long long)p.nsub * (long long)padded_cells(p.geom, D);
     if (p.nsub > 0) {
         const size_t shm = padded_cells(p.geom, D) * 2 * FixedPoint<T>::kSlots *
                            sizeof(unsigned long long);
@@ -688,16 +698,17 @@ hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStr
         }
         hipError_t e = allow_lds(k_spread<T, D, M2>, shm, static_lds<T, D>());
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_spread<T, D, M2>), dim3(p.nsub), dim3(kResampleThreads), shm, s,
-                           (cplx<T> *)p.pad, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
+        hipLaunchKernelGGL((k_spread<T, D, M2>), dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
+                           (cplx<T> *)pad, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                            p.subs, (const T *)p.coef, p.window, win_params<T>(p), (T)wprod,
-                           (const cplx<T> *)fhat);
+                           (const cplx<T> *)fhat, pstride, (long long)p.M);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (!merge) return hipSuccess;
-    hipLaunchKernelGGL((k_spread_merge<T, D>), dim3(p.geom.ntiles), dim3(kResampleThreads), 0, s,
-                       (cplx<T> *)grid, p.geom, (const cplx<T> *)p.pad, p.tile_sub, M2);
+    hipLaunchKernelGGL((k_spread_merge<T, D>), dim3(p.geom.ntiles, K), dim3(kResampleThreads), 0, s,
+                       (cplx<T> *)grid, p.geom, (const cplx<T> *)pad, p.tile_sub, M2, (long long)p.G,
+                       pstride);
     return hipGetLastError();
 }
 

@@ -25,11 +25,13 @@ class Plan:
 
     float32 nodes give a complex64 plan (FP32 arithmetic), float64 nodes a
     complex128 plan.  ``tile``: optional per-axis tile edges; ``window``: "poly"
-    (default) or "direct"; ``max_block_nodes``: cap on nodes per interpolation
-    work item.
+    (default) or "direct"; ``max_block_nodes``: cap on nodes per resampling
+    work item; ``tune``: if > 0 (and no tile is given), the library's autotuner
+    picks the tiles, timing each candidate ``tune`` times (``tuned_ms`` then
+    holds the chosen plan's forward + adjoint milliseconds).
     """
 
-    def __init__(self, x, N, m=4, sigma=2.0, tile=None, window="poly", max_block_nodes=0):
+    def __init__(self, x, N, m=4, sigma=2.0, tile=None, window="poly", max_block_nodes=0, tune=0):
         if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
             raise TypeError("x must be a CUDA (HIP) tensor")
         N = tuple(int(v) for v in N)
@@ -60,11 +62,21 @@ class Plan:
         opts.max_block_nodes = int(max_block_nodes)
         Narr = (ctypes.c_int64 * self.D)(*N)
         handle = ctypes.c_void_p()
+        self.tuned_ms = None
         with torch.cuda.device(self.device):
-            rc = self._lib.nfft_plan_create_ex(ctypes.byref(handle), self.D, Narr, self.M,
-                                               ctypes.c_void_p(x.data_ptr()), self.m, self.sigma,
-                                               self.dtype, ctypes.byref(opts),
-                                               _stream_handle(self.device))
+            if tune and tile is None:
+                ms = ctypes.c_double()
+                rc = self._lib.nfft_plan_create_tuned(
+                    ctypes.byref(handle), self.D, Narr, self.M, ctypes.c_void_p(x.data_ptr()),
+                    self.m, self.sigma, self.dtype, ctypes.byref(opts), int(tune),
+                    _stream_handle(self.device), ctypes.byref(ms))
+                if rc == _lib.NFFT_OK:
+                    self.tuned_ms = ms.value
+            else:
+                rc = self._lib.nfft_plan_create_ex(ctypes.byref(handle), self.D, Narr, self.M,
+                                                   ctypes.c_void_p(x.data_ptr()), self.m,
+                                                   self.sigma, self.dtype, ctypes.byref(opts),
+                                                   _stream_handle(self.device))
         _lib.check(rc, "nfft_plan_create")
         self._h = handle
 
@@ -149,6 +161,31 @@ class Plan:
         _lib.check(rc, "nfft_adjoint")
         return out
 
+    # -- multi-channel ---------------------------------------------------------
+    def forward_many(self, f, out=None):
+        """K channels at once: f has shape (K, *N), the result (K, M)."""
+        K = int(f.shape[0]) if f.dim() == self.D + 1 else -1
+        self._check(f, (K,) + self.N, "f")
+        if out is None:
+            out = torch.empty((K, self.M), dtype=self.cdtype, device=self.device)
+        self._check(out, (K, self.M), "out")
+        rc = self._lib.nfft_forward_many(self._h, K, ctypes.c_void_p(f.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
+        _lib.check(rc, "nfft_forward_many")
+        return out
+
+    def adjoint_many(self, fhat, out=None):
+        """K channels at once: fhat has shape (K, M), the result (K, *N)."""
+        K = int(fhat.shape[0]) if fhat.dim() == 2 else -1
+        self._check(fhat, (K, self.M), "fhat")
+        if out is None:
+            out = torch.empty((K,) + self.N, dtype=self.cdtype, device=self.device)
+        self._check(out, (K,) + self.N, "out")
+        rc = self._lib.nfft_adjoint_many(self._h, K, ctypes.c_void_p(fhat.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
+        _lib.check(rc, "nfft_adjoint_many")
+        return out
+
     # -- single steps ----------------------------------------------------------
     def resample_forward(self, grid, out=None):
         self._check(grid, self.Ntilde, "grid")
@@ -184,6 +221,57 @@ class Plan:
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._lib.nfft_plan_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent transforms of several plans run as one HIP graph (see nfft_batch_create).
+
+    ``forward(fs, outs)`` / ``adjoint(fhats, outs)`` take lists of tensors, one per plan, in
+    the plans' order; the graph is captured on the first call and again whenever a tensor
+    differs from the previous call's (keep the same tensors to replay it).
+    """
+
+    def __init__(self, plans, nstreams=4):
+        self.plans = list(plans)
+        self._lib = _lib.load()
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        handle = ctypes.c_void_p()
+        _lib.check(self._lib.nfft_batch_create(ctypes.byref(handle), len(self.plans), arr,
+                                               int(nstreams)), "nfft_batch_create")
+        self._h = handle
+        self.device = self.plans[0].device
+
+    def _run(self, fn, ins, outs, in_shape, out_shape, name):
+        n = len(self.plans)
+        if len(ins) != n or len(outs) != n:
+            raise ValueError("need one input and one output per plan")
+        for p, a, b in zip(self.plans, ins, outs):
+            p._check(a, in_shape(p), name + " input")
+            p._check(b, out_shape(p), name + " output")
+        inp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ins])
+        out = (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs])
+        _lib.check(fn(self._h, inp, out, _stream_handle(self.device)), name)
+        return outs
+
+    def forward(self, fs, outs):
+        return self._run(self._lib.nfft_batch_forward, fs, outs, lambda p: p.N, lambda p: (p.M,),
+                         "nfft_batch_forward")
+
+    def adjoint(self, fhats, outs):
+        return self._run(self._lib.nfft_batch_adjoint, fhats, outs, lambda p: (p.M,),
+                         lambda p: p.N, "nfft_batch_adjoint")
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.nfft_batch_destroy(h)
             self._h = None
 
     def __del__(self):

@@ -82,5 +82,28 @@ def test_null_plan_calls(lib):
     assert lib.nfft_plan_info(None, None, None, None) == -1
     ms = ctypes.c_double()
     assert lib.nfft_plan_bench_stage(None, 3, 1, None, FAKE, None, ctypes.byref(ms)) == -1
+    assert lib.nfft_forward_many(None, 2, FAKE, FAKE, None) == -1
+    assert lib.nfft_adjoint_many(None, 2, FAKE, FAKE, None) == -1
+    assert lib.nfft_batch_forward(None, None, None, None) == -1
+    assert lib.nfft_batch_destroy(None) == 0
+
+
+def test_batch_and_tuner_argument_errors(lib):
+    """Rejected before any HIP call: empty batch, null plan, stream count, bad plan arguments."""
+    out = ctypes.c_void_p()
+    plans = (ctypes.c_void_p * 2)(None, None)
+    assert lib.nfft_batch_create(ctypes.byref(out), 0, plans, 1) == -1
+    assert lib.nfft_batch_create(ctypes.byref(out), 2, plans, 1) == -1
+    assert lib.nfft_batch_create(ctypes.byref(out), 2, plans, 0) == -1
+    N = (ctypes.c_int64 * 2)(64, 64)
+    ms = ctypes.c_double()
+    # sigma <= 1, odd N, reps < 1
+    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(1.0), 0,
+                                      None, 2, None, ctypes.byref(ms)) == -1
+    Nodd = (ctypes.c_int64 * 2)(63, 64)
+    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, Nodd, 0, None, 4, ctypes.c_double(2.0),
+                                      0, None, 2, None, ctypes.byref(ms)) == -2
+    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(2.0), 0,
+                                      None, 0, None, ctypes.byref(ms)) == -1
     assert lib.nfft_strerror(-5).decode() == "node coordinate is NaN or infinite"
     assert lib.nfft_strerror(12345).decode() == "unknown error"
