@@ -34,6 +34,11 @@ WORKLOADS = {
     "2d_n512_radial402x652": dict(D=2, N=(512, 512), M=402 * 652, nodes="radial", config=1),
     "3d_n128_m2097152_uniform": dict(D=3, N=(128, 128, 128), M=2097152, nodes="uniform", config=2),
     "1d_n256_m512_uniform": dict(D=1, N=(256,), M=512, nodes="uniform", config=0),
+    # the runtime around the plans: K channels through one node set, and a batch of 64
+    # independent transforms of random sizes run as one HIP graph
+    "2d_n256_radial256x256_k32": dict(D=2, N=(256, 256), M=65536, nodes="radial256", config=3,
+                                      K=32),
+    "2d_batch64": dict(D=2, nodes="batch", config=3, count=64),
 }
 
 
@@ -112,6 +117,8 @@ def inputs(w):
     import nfft_workloads as wl
     if w["nodes"] == "radial":
         x = wl.radial_nodes(402, 652)
+    elif w["nodes"] == "radial256":
+        x = wl.radial_nodes(256, 256)
     else:
         x = wl.uniform_nodes(w["M"], w["D"], config=w["config"], stream=0)
     f = wl.cn01(w["N"], config=w["config"], stream=1)
@@ -179,6 +186,122 @@ def cpu_baseline(x, f, fh, N, seconds):
                       % (sf, M, t1 - t0, sa, nprod, t2 - t1)}
 
 
+def timed(fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` calls after `warmup` calls (HIP events)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_multichannel(args, w):
+    """K channels through one radial node set: forward_many + adjoint_many per step."""
+    import torch
+    import nfft_workloads as wl
+    from paper_2208_00049_amd import Plan
+    dev = torch.device("cuda:0")
+    K, M, N = w["K"], w["M"], w["N"]
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    x = torch.tensor(wl.radial_nodes(256, 256), dtype=torch.float32 if args.dtype == "c64"
+                     else torch.float64, device=dev)
+    f = torch.tensor(np.stack([wl.cn01(N, config=3, stream=700 + k) for k in range(K)]),
+                     dtype=cdt, device=dev)
+    fh = torch.tensor(np.stack([wl.cn01((M,), config=3, stream=900 + k) for k in range(K)]),
+                      dtype=cdt, device=dev)
+    plan = Plan(x, N, m=args.m, sigma=args.sigma)
+    fo = torch.empty((K, M), dtype=cdt, device=dev)
+    yo = torch.empty((K,) + tuple(N), dtype=cdt, device=dev)
+    ms = timed(lambda: (plan.forward_many(f, out=fo), plan.adjoint_many(fh, out=yo)),
+               args.steps, args.warmup)
+    # the same work as K single-channel calls, for comparison
+    f1 = [f[k] for k in range(K)]
+    fh1 = [fh[k] for k in range(K)]
+    fo1 = torch.empty(M, dtype=cdt, device=dev)
+    yo1 = torch.empty(tuple(N), dtype=cdt, device=dev)
+
+    def single():
+        for k in range(K):
+            plan.forward(f1[k], out=fo1)
+            plan.adjoint(fh1[k], out=yo1)
+    ms_single = timed(single, max(2, args.steps // 10), 2)
+    # per-stage times of one multi-channel step
+    plan.set_timing(True)
+    plan.forward_many(f, out=fo)
+    plan.adjoint_many(fh, out=yo)
+    st = {k: v for k, v in plan.stage_times().items() if v > 0}
+    plan.set_timing(False)
+    info = plan.info()
+    algo = algorithmic_bytes(dict(w, nodes="radial"), info["Ntilde"], args.dtype)
+    dominant = max(st, key=st.get)
+    ach = K * algo[dominant] / (st[dominant] * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(K * M / (ms * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "c64" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "N": list(N), "M": M, "K": K, "m": args.m,
+                   "sigma": args.sigma, "nodes": "radial 256 spokes x 256 samples",
+                   "Ntilde": list(info["Ntilde"]), "tile": list(info["tile"])},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes": K * algo[dominant],
+                     "launch_ms": round(st[dominant], 5)},
+        "stages_ms": {k: round(v, 5) for k, v in st.items()},
+        "single_channel_calls_ms_per_step": round(ms_single, 5),
+        "speedup_vs_single_channel_calls": round(ms_single / ms, 2),
+        "cpu_baseline": None,
+    }
+
+
+def bench_batch(args, w):
+    """64 independent 2-D transforms of random sizes: one graph launch for all forwards and
+    one for all adjoints per step, against the same calls issued one after another."""
+    import torch
+    import nfft_workloads as wl
+    from paper_2208_00049_amd import Batch, Plan
+    dev = torch.device("cuda:0")
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    xdt = torch.float32 if args.dtype == "c64" else torch.float64
+    specs = wl.batched_specs(w["count"], config=w["config"])
+    plans, fs, fhs, fos, yos = [], [], [], [], []
+    for b, (N, M) in enumerate(specs):
+        x = torch.tensor(wl.uniform_nodes(M, 2, config=3, stream=100 + b), dtype=xdt, device=dev)
+        plans.append(Plan(x, N, m=args.m, sigma=args.sigma))
+        fs.append(torch.tensor(wl.cn01(N, config=3, stream=300 + b), dtype=cdt, device=dev))
+        fhs.append(torch.tensor(wl.cn01((M,), config=3, stream=500 + b), dtype=cdt, device=dev))
+        fos.append(torch.empty(M, dtype=cdt, device=dev))
+        yos.append(torch.empty(N, dtype=cdt, device=dev))
+    batch = Batch(plans, nstreams=8)
+    ms = timed(lambda: (batch.forward(fs, fos), batch.adjoint(fhs, yos)), args.steps, args.warmup)
+
+    def eager():
+        for p, f, fh, fo, yo in zip(plans, fs, fhs, fos, yos):
+            p.forward(f, out=fo)
+            p.adjoint(fh, out=yo)
+    ms_eager = timed(eager, max(2, args.steps // 5), 2)
+    total = sum(M for _, M in specs)
+    return {
+        "metric": METRIC, "value": round(total / (ms * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "c64" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "transforms": len(specs), "total_M": total,
+                   "N_choices": [64, 128, 256, 512], "m": args.m, "sigma": args.sigma,
+                   "nodes": "uniform", "graph_streams": 8},
+        "roofline": None,
+        "eager_calls_ms_per_step": round(ms_eager, 5),
+        "speedup_vs_eager_calls": round(ms_eager / ms, 2),
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.copy_bytes:
@@ -192,6 +315,10 @@ def main():
     from paper_2208_00049_amd import Plan
 
     w = WORKLOADS[args.workload]
+    if w["nodes"] in ("radial256", "batch"):
+        res = bench_multichannel(args, w) if w["nodes"] == "radial256" else bench_batch(args, w)
+        print(json.dumps(res), flush=True)
+        return
     dev = torch.device("cuda:0")
     x, f, fh = inputs(w)
     xdt = torch.float32 if args.dtype == "c64" else torch.float64

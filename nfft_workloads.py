@@ -12,7 +12,13 @@ section "Materials and Methods"; no public dataset is involved):
 * uniform nodes: ``rng.random((M, D)) - 0.5`` in FP64 (rounded to FP32 for the
   single-precision path by the caller);
 * radial nodes: S spokes x T samples, theta_s = pi s / S, r_t = (t - T/2) / T,
-  x = (r cos theta, r sin theta), which lies in [-1/2, 1/2)^2.
+  x = (r cos theta, r sin theta), which lies in [-1/2, 1/2)^2;
+* batched transforms (config 3): transform b draws its size N_b uniformly from
+  {64^2, 128^2, 256^2, 512^2} and M_b uniformly from the integers in
+  [10^4, 5 10^5] (stream 0), then its nodes from stream 100 + b, its f from
+  stream 300 + b and its fhat from stream 500 + b;
+* multi-channel (config 3): K coefficient vectors through one node set,
+  channel k from stream 700 + k (f) and 900 + k (fhat).
 """
 import numpy as np
 
@@ -70,6 +76,15 @@ def cn01(shape, config: int = 0, stream: int = 1) -> np.ndarray:
     return (re + 1j * im) / np.sqrt(2.0)
 
 
+def batched_specs(count: int = 64, config: int = 3):
+    """Sizes of a batch of independent 2-D transforms: a list of (N, M) pairs."""
+    g = rng(config, 0)
+    edges = np.array([64, 128, 256, 512])
+    ns = g.choice(edges, size=count)
+    ms = g.integers(10_000, 500_000, size=count, endpoint=True)
+    return [((int(n), int(n)), int(mm)) for n, mm in zip(ns, ms)]
+
+
 # Workload shapes of the hot path (plain NFFT, forward + adjoint).
 WORKLOADS = {
     "1d_n256_m512": dict(config=0, D=1, N=(256,), M=512, nodes="uniform"),
@@ -77,6 +92,10 @@ WORKLOADS = {
     "2d_n512_radial402x652": dict(config=1, D=2, N=(512, 512), M=402 * 652, nodes="radial",
                                   spokes=402, samples=652),
     "3d_n128_m2097152": dict(config=2, D=3, N=(128, 128, 128), M=2097152, nodes="uniform"),
+    # batched / multi-channel (the runtime around the plans)
+    "2d_n256_radial256x256_k32": dict(config=3, D=2, N=(256, 256), M=256 * 256, nodes="radial",
+                                      spokes=256, samples=256, K=32),
+    "2d_batch64": dict(config=3, D=2, count=64, nodes="uniform"),
 }
 
 
