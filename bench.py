@@ -39,6 +39,8 @@ WORKLOADS = {
     "2d_n256_radial256x256_k32": dict(D=2, N=(256, 256), M=65536, nodes="radial256", config=3,
                                       K=32),
     "2d_batch64": dict(D=2, nodes="batch", config=3, count=64),
+    # differentiable: loss ||A(x) f - y||^2, gradients with respect to f and the nodes
+    "2d_n256_grad_radial256x256": dict(D=2, N=(256, 256), M=65536, nodes="grad", config=4),
 }
 
 
@@ -260,6 +262,55 @@ def bench_multichannel(args, w):
     }
 
 
+def bench_grad(args, w):
+    """One optimisation step's transforms: loss = ||A(x) f - y||^2 forward, then the
+    gradients with respect to f and the nodes (jittered radial nodes, y from perturbed
+    nodes); the plan for the current nodes is built outside the timed step (plan_ms)."""
+    import torch
+    import nfft_workloads as wl
+    from paper_2208_00049_amd import Plan
+    from paper_2208_00049_amd.autograd import nfft as nfft_ad
+    dev = torch.device("cuda:0")
+    N, M = w["N"], w["M"]
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    xdt = torch.float32 if args.dtype == "c64" else torch.float64
+    Nt = int(round(args.sigma * N[0]))
+    x = wl.jittered_radial_nodes(256, 256, Nt, config=4, stream=0)
+    xp = x + wl.rng(4, 3).uniform(-0.25 / N[0], 0.25 / N[0], size=x.shape)
+    xp = xp - np.floor(xp + 0.5)
+    xt = torch.tensor(x, dtype=xdt, device=dev)
+    f = torch.tensor(wl.cn01(N, config=4, stream=1), dtype=cdt, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = Plan(xt, N, m=args.m, sigma=args.sigma)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    py = Plan(torch.tensor(xp, dtype=xdt, device=dev), N, m=args.m, sigma=args.sigma)
+    y = py.forward(f)
+    py.close()
+    xr = xt.clone().requires_grad_(True)
+    fr = f.clone().requires_grad_(True)
+
+    def step():
+        xr.grad = None
+        fr.grad = None
+        loss = (nfft_ad(xr, fr, plan=plan) - y).abs().pow(2).sum()
+        loss.backward()
+    ms = timed(step, args.steps, args.warmup)
+    return {
+        "metric": METRIC, "value": round(M / (ms * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "c64" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "N": list(N), "M": M, "m": args.m,
+                   "sigma": args.sigma, "nodes": "radial 256 x 256, radial jitter U(+-0.5/Ntilde)",
+                   "step": "forward, loss, backward (grad f, grad x)"},
+        "plan_ms": round(plan_ms, 2),
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def bench_batch(args, w):
     """64 independent 2-D transforms of random sizes: one graph launch for all forwards and
     one for all adjoints per step, against the same calls issued one after another."""
@@ -315,8 +366,9 @@ def main():
     from paper_2208_00049_amd import Plan
 
     w = WORKLOADS[args.workload]
-    if w["nodes"] in ("radial256", "batch"):
-        res = bench_multichannel(args, w) if w["nodes"] == "radial256" else bench_batch(args, w)
+    if w["nodes"] in ("radial256", "batch", "grad"):
+        res = {"radial256": bench_multichannel, "batch": bench_batch,
+               "grad": bench_grad}[w["nodes"]](args, w)
         print(json.dumps(res), flush=True)
         return
     dev = torch.device("cuda:0")

@@ -137,6 +137,25 @@ int nfft_forward_many(nfft_plan_t p, int K, const void *f, void *fhat, void *str
 int nfft_adjoint_many(nfft_plan_t p, int K, const void *fhat, void *y, void *stream);
 
 /*
+ * Derivatives with respect to the nodes (for differentiable use).
+ *   nfft_forward_deriv: dfhat[d][j] ~= sum_{n in I_N} (-2 pi i n_d) f_n exp(-2 pi i n.x_j),
+ *     the partial derivative of the forward transform's output j along axis d,
+ *     computed as D forward NFFTs of the coefficients -2 pi i n_d f_n (one
+ *     multi-channel call that reads f once; the factor is applied in the
+ *     resampling-correction pass).  f: prod(N) complex; dfhat: D x M complex
+ *     (axis-major), device.  Uses the plan's multi-channel buffers (K = D).
+ *   nfft_node_grad: grad_x[j*D + d] = Re(conj(a_j) dfhat[d][j]) for j < M, d < D
+ *     (a: M complex; grad_x: M x D reals of the plan's real type, node-major like
+ *     the nodes).  With a = the gradient of a real loss with respect to the
+ *     forward output (the conjugate-Wirtinger convention: 2 dL/d conj(fhat)),
+ *     grad_x is dL/dx for the forward transform.  For the adjoint transform
+ *     y = A^H fhat, dL/dx[j, d] = Re(conj(fhat_j) w[d][j]) with w =
+ *     nfft_forward_deriv of the gradient with respect to y.
+ */
+int nfft_forward_deriv(nfft_plan_t p, const void *f, void *dfhat, void *stream);
+int nfft_node_grad(nfft_plan_t p, const void *a, const void *dfhat, void *grad_x, void *stream);
+
+/*
  * Batches of independent transforms (different plans, sizes and node sets),
  * run as one HIP graph.  nfft_batch_create takes n distinct plans (a plan may
  * appear once: its grid serves one transform at a time) and the number of

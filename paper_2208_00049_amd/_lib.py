@@ -26,7 +26,7 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
            "nfft_plan_info", "nfft_plan_grid", "nfft_plan_set_timing", "nfft_plan_timing",
            "nfft_plan_bench_stage", "nfft_forward_many", "nfft_adjoint_many",
            "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
-           "nfft_plan_create_tuned", "nfft_strerror"]
+           "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror"]
 NFFT_NUM_STAGES = 8
 STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
           "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]
@@ -88,6 +88,8 @@ def load():
                                            ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(Options), ctypes.c_int, vp,
                                            ctypes.POINTER(ctypes.c_double)]
+    lib.nfft_forward_deriv.argtypes = [vp, vp, vp, vp]
+    lib.nfft_node_grad.argtypes = [vp, vp, vp, vp, vp]
     lib.nfft_strerror.argtypes = [ctypes.c_int]
     lib.nfft_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:

@@ -429,6 +429,12 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
             if (D == 3) fac *= dec1[i1];
         }
     }
+    // derivative channels (mode 1): channel d multiplies f by -2 pi i n_d
+    const T twopi = (T)6.283185307179586476925;
+    if (c.deriv && (int)blockIdx.y < D - 1) {
+        const int nd = blockIdx.y == 0 ? i0 - c.N[0] / 2 : i1 - c.N[1] / 2;
+        fac *= (T)nd * twopi;
+    }
     const int Nl = c.N[D - 1];
 
     // each thread owns k = t + j tpl, j < L / tpl <= 8 (the largest radix): all
@@ -445,8 +451,11 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
                 else if (k >= L - Nl / 2 && k < L) r = k - (L - Nl / 2);
                 const int rr = r >= 0 ? r : 0;
                 const C x = src[frow + rr];
-                const T s = fac * declast[rr];
-                v[j] = r >= 0 ? cscale(x, s) : cmake<C>((T)0, (T)0);
+                T s = fac * declast[rr];
+                if (c.deriv && blockIdx.y == D - 1) s *= (T)(rr - Nl / 2) * twopi;
+                C y = cscale(x, s);
+                if (c.deriv) y = cmake<C>(y.y, -y.x);  // times -i
+                v[j] = r >= 0 ? y : cmake<C>((T)0, (T)0);
             }
         } else {
 #pragma unroll

@@ -98,6 +98,7 @@ struct ContigPass {
     int K;                  // channels (grid blockIdx.y)
     long long src_cstride;  // elements between channels of src
     long long dst_cstride;  // elements between channels of dst
+    int deriv;              // mode 1, K = D: channel d takes -2 pi i n_d f (one shared f)
 };
 
 }  // namespace nfft
@@ -175,6 +176,10 @@ hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, c
                              hipStream_t s);
 
 // resample.hip
+// out[j*D + d] = Re(conj(a_j) v[d*M + j]) for the plan's M nodes
+hipError_t launch_node_grad(const nfft_plan_s &p, const void *a, const void *v, void *out,
+                            hipStream_t s);
+
 // K channels: grids at stride G, fhat at stride M, padded tiles at stride pad_elems()
 hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
                          int K = 1);

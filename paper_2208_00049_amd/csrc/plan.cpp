@@ -507,12 +507,15 @@ struct StageTimer {
 
 // forward FFT with the resampling correction fused into the first (last-axis)
 // pass; K channels: f at stride prod(N), grids at stride G
-hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, hipStream_t s) {
+// deriv: K = D channels from one f, channel d with coefficients -2 pi i n_d f_n
+hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, hipStream_t s,
+                       bool deriv = false) {
     const int D = p.D;
     const size_t cs = csize(p.dtype);
     ContigPass c{};
     c.K = K;
-    c.src_cstride = p.NN;
+    c.deriv = deriv ? 1 : 0;
+    c.src_cstride = deriv ? 0 : p.NN;
     c.dst_cstride = p.G;
     c.mode = 1;
     c.D = D;
@@ -723,6 +726,21 @@ int nfft_forward_many(nfft_plan_t p, int K, const void *f, void *fhat, void *str
     hipError_t e = ensure_channels(*p, K);
     if (e == hipSuccess) e = run_forward(*p, f, fhat, K, p->grid_many, (hipStream_t)stream);
     return hip_rc(e);
+}
+
+int nfft_forward_deriv(nfft_plan_t p, const void *f, void *dfhat, void *stream) {
+    if (!p || !f || (p->M > 0 && !dfhat)) return NFFT_ERR_ARG;
+    if (p->M == 0) return NFFT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = ensure_channels(*p, p->D);
+    if (e == hipSuccess) e = forward_fft(*p, f, p->grid_many, p->D, s, true);
+    if (e == hipSuccess) e = launch_interp(*p, p->grid_many, dfhat, s, p->D);
+    return hip_rc(e);
+}
+
+int nfft_node_grad(nfft_plan_t p, const void *a, const void *dfhat, void *grad_x, void *stream) {
+    if (!p || (p->M > 0 && (!a || !dfhat || !grad_x))) return NFFT_ERR_ARG;
+    return hip_rc(launch_node_grad(*p, a, dfhat, grad_x, (hipStream_t)stream));
 }
 
 int nfft_adjoint_many(nfft_plan_t p, int K, const void *fhat, void *y, void *stream) {

@@ -51,4 +51,30 @@ hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hip
                                : spread_t<double>(p, fhat, grid, s, merge, K, pad);
 }
 
+// Node gradient: out[j*D + d] = Re(conj(a_j) v[d*M + j]) = a.x v.x + a.y v.y.
+template <typename T>
+__global__ void k_node_grad(const cplx<T> *__restrict__ a, const cplx<T> *__restrict__ v,
+                            T *__restrict__ out, long long M, int D) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * D) return;
+    const long long j = i / D;
+    const int d = (int)(i - j * D);
+    const cplx<T> x = a[j], y = v[(long long)d * M + j];
+    out[i] = x.x * y.x + x.y * y.y;
+}
+
+hipError_t launch_node_grad(const nfft_plan_s &p, const void *a, const void *v, void *out,
+                            hipStream_t s) {
+    const long long n = (long long)p.M * p.D;
+    if (n == 0) return hipSuccess;
+    const dim3 g((unsigned)((n + 255) / 256));
+    if (p.dtype == NFFT_C64)
+        hipLaunchKernelGGL(k_node_grad<float>, g, dim3(256), 0, s, (const cplx<float> *)a,
+                           (const cplx<float> *)v, (float *)out, (long long)p.M, p.D);
+    else
+        hipLaunchKernelGGL(k_node_grad<double>, g, dim3(256), 0, s, (const cplx<double> *)a,
+                           (const cplx<double> *)v, (double *)out, (long long)p.M, p.D);
+    return hipGetLastError();
+}
+
 }  // namespace nfft

@@ -186,6 +186,30 @@ class Plan:
         _lib.check(rc, "nfft_adjoint_many")
         return out
 
+    # -- derivatives with respect to the nodes -----------------------------------
+    def forward_deriv(self, f, out=None):
+        """(D, M): entry [d, j] ~= sum_n (-2 pi i n_d) f_n exp(-2 pi i n.x_j)."""
+        self._check(f, self.N, "f")
+        if out is None:
+            out = torch.empty((self.D, self.M), dtype=self.cdtype, device=self.device)
+        self._check(out, (self.D, self.M), "out")
+        rc = self._lib.nfft_forward_deriv(self._h, ctypes.c_void_p(f.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
+        _lib.check(rc, "nfft_forward_deriv")
+        return out
+
+    def node_grad(self, a, dfhat, out=None):
+        """(M, D) reals: Re(conj(a_j) dfhat[d, j])."""
+        self._check(a, (self.M,), "a")
+        self._check(dfhat, (self.D, self.M), "dfhat")
+        if out is None:
+            out = torch.empty((self.M, self.D), dtype=_RDTYPE[self.dtype], device=self.device)
+        rc = self._lib.nfft_node_grad(self._h, ctypes.c_void_p(a.data_ptr()),
+                                      ctypes.c_void_p(dfhat.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
+        _lib.check(rc, "nfft_node_grad")
+        return out
+
     # -- single steps ----------------------------------------------------------
     def resample_forward(self, grid, out=None):
         self._check(grid, self.Ntilde, "grid")
