@@ -116,8 +116,45 @@ def poly_coeffs(m, beta, Z=None, Theta=None):
     return mu
 
 
+# Exponents of the linear-interpolation table sizes for the Kaiser-Bessel window, m = 1..8
+# (LINEAR item of subsection "Window precomputation": S = m 2^{c_min(m,8)} + 2).
+LINEAR_C = (3, 7, 9, 14, 17, 20, 23, 24)
+
+
+def linear_table_size(m):
+    """S = m 2^{c_min(m,8)} + 2 table entries."""
+    return m * 2 ** LINEAR_C[min(m, 8) - 1] + 2
+
+
+def linear_table(m, beta):
+    """Lookup table psi_s = psi_hat_Base(s / (S - 2)), s = 0..S-1.  Entry S-2 (|u| = 1) is
+    the sinh form's limit beta/pi, the value the half-open support gives at u = -1 (the only
+    tap with |u| = 1); entry S-1 lies outside the support and is 0."""
+    S = linear_table_size(m)
+    u = np.arange(S) / (S - 2.0)
+    s = np.sqrt(np.clip(1.0 - u * u, 0.0, None))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        val = np.where(s > 0, np.sinh(beta * s) / (np.pi * np.where(s > 0, s, 1.0)), beta / np.pi)
+    val[S - 1] = 0.0
+    return val
+
+
+def linear_lookup(u, table):
+    """psi_hat_Base(u) by linear interpolation in the table: kappa = |u| (S - 2),
+    s = floor(kappa), alpha = kappa - s, value psi_s + alpha (psi_{s+1} - psi_s)."""
+    S = table.shape[0]
+    kappa = np.abs(np.asarray(u, dtype=np.float64)) * (S - 2)
+    s = np.floor(kappa).astype(np.int64)
+    alpha = kappa - s
+    return table[s] + alpha * (table[s + 1] - table[s])
+
+
 def tap_weights(frac, m, beta, window="poly"):
-    """Window weights for the 2m taps of nodes with fractional offset ``frac``; shape (..., 2m)."""
+    """Window weights for the 2m taps of nodes with fractional offset ``frac``; shape (..., 2m).
+
+    window: "poly" (POLYNOMIAL), "direct" (no precomputation) or "linear" (LINEAR table
+    lookup); the paper's TENSOR and FULL modes store "poly" weights and so compute the same.
+    """
     frac = np.asarray(frac, dtype=np.float64)
     t = np.arange(2 * m)
     if window == "direct":
@@ -127,7 +164,9 @@ def tap_weights(frac, m, beta, window="poly"):
         zeta = frac - 0.5
         powers = zeta[..., None] ** np.arange(mu.shape[1])
         return powers @ mu.T
-    raise ValueError("window must be 'poly' or 'direct'")
+    if window == "linear":
+        return linear_lookup((frac[..., None] + m - 1 - t) / m, linear_table(m, beta))
+    raise ValueError("window must be 'poly', 'direct' or 'linear'")
 
 
 # ---------------------------------------------------------------------------

@@ -150,3 +150,17 @@ def test_planted_axis_transpose_is_caught(monkeypatch):
     N, x, f, fh, ef, _ = _case(2)
     bad = orig(x, f.T.copy(), 4, 2.0)
     assert _rel2(bad, ef) > GATE[(4, 2.0)]
+
+
+@pytest.mark.parametrize("m,sigma,gate", [(2, 2.0, 3e-3), (4, 2.0, 2e-6)])
+def test_linear_window_nfft_against_ndft(m, sigma, gate):
+    """The LINEAR table sizes keep the window error below the NFFT error (2-D)."""
+    N = (24, 32)
+    x = wl.uniform_nodes(700, 2, config=70, stream=0)
+    f = wl.cn01(N, config=70, stream=1)
+    fh = wl.cn01((700,), config=70, stream=2)
+    e_f = _rel2(na.forward(x, f, m, sigma, window="linear"), ndft.ndft_forward(x, f))
+    e_a = _rel2(na.adjoint(x, fh, N, m, sigma, window="linear"), ndft.ndft_adjoint(x, fh, N))
+    e_p = _rel2(na.forward(x, f, m, sigma, window="poly"), ndft.ndft_forward(x, f))
+    assert e_f < gate and e_a < gate
+    assert e_f < 2 * e_p + 1e-12

@@ -104,3 +104,42 @@ def test_tap_arguments_cover_the_support_once():
                                           ((30,), 1.3, (40,))])
 def test_oversampled_size_rule(N, sigma, want):
     assert na.oversampled_size(N, sigma) == want
+
+
+# ---------------------------------------------------------------------------
+# LINEAR precomputation (lookup table with linear interpolation)
+
+def test_linear_table_size_matches_printed_example():
+    """The paper prints S = 134217730 table entries for m = 8 (Kaiser-Bessel)."""
+    assert na.linear_table_size(8) == 134217730
+    assert [na.linear_table_size(m) for m in (1, 2, 4)] == [1 * 2 ** 3 + 2, 2 * 2 ** 7 + 2,
+                                                            4 * 2 ** 14 + 2]
+
+
+@pytest.mark.parametrize("m,sigma", [(2, 2.0), (4, 2.0), (4, 1.25)])
+def test_linear_lookup_exact_at_samples_and_within_bound(m, sigma):
+    beta = na.kb_beta(m, sigma)
+    table = na.linear_table(m, beta)
+    S = table.shape[0]
+    # at the sample points the lookup is the window itself (alpha = 0)
+    s = np.array([0, 1, 7, S // 3, S - 3])
+    u = s / (S - 2.0)
+    assert np.array_equal(na.linear_lookup(u, table), na.window_hat(u, beta))
+    assert na.linear_lookup(np.array([-1.0]), table)[0] == beta / np.pi
+    # between samples: |error| <= h^2/8 max|psi''| on the cell (h = 1/(S-2)); psi'' from
+    # central differences of the exact window on a finer grid
+    g = np.random.default_rng(3)
+    uu = g.uniform(-0.999, 0.999, 4000)
+    h = 1.0 / (S - 2)
+    d = h / 4
+
+    def psi2(v):
+        return np.abs(na.window_hat(v + d, beta) - 2 * na.window_hat(v, beta)
+                      + na.window_hat(v - d, beta)) / d ** 2
+    # max |psi''| over the cell, sampled at the cell's ends and the point
+    lo = np.floor(np.abs(uu) / h) * h
+    second = np.maximum(np.maximum(psi2(lo), psi2(lo + h)), psi2(np.abs(uu)))
+    err = np.abs(na.linear_lookup(uu, table) - na.window_hat(uu, beta))
+    assert np.all(err <= 1.5 * h * h / 8 * second + 1e-14 * na.window_hat(0.0, beta))
+    # symmetric in u
+    assert np.array_equal(na.linear_lookup(uu, table), na.linear_lookup(-uu, table))
