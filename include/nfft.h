@@ -70,14 +70,22 @@ enum {
     NFFT_WINDOW_POLY = 0,   /* piecewise polynomial of degree 2m per tap, least-squares fit
                                to the Kaiser-Bessel window in FP64 (the paper's POLYNOMIAL
                                precomputation, subsection "Window precomputation") */
-    NFFT_WINDOW_DIRECT = 1  /* evaluate sinh(beta sqrt(1-u^2)) / (pi sqrt(1-u^2)) per tap
+    NFFT_WINDOW_DIRECT = 1, /* evaluate sinh(beta sqrt(1-u^2)) / (pi sqrt(1-u^2)) per tap
                                (the paper's "no precomputation" option) */
+    NFFT_WINDOW_TENSOR = 2, /* the paper's TENSOR precomputation: the plan stores, per node
+                               and axis, the 2m polynomial-window weights (2m D M values) */
+    NFFT_WINDOW_LINEAR = 3, /* the paper's LINEAR precomputation: a table of
+                               S = m 2^c + 2 window samples per axis (c = 3, 7, 9, 14, 17,
+                               20, 23, 24 for m = 1..8, 24 above), linear interpolation */
+    NFFT_WINDOW_FULL = 4    /* the paper's FULL precomputation: per node all (2m)^D weight
+                               products (the nonzeros of the sparse matrix B); D <= 2,
+                               D = 3 returns NFFT_ERR_UNSUPPORTED */
 };
 
 typedef struct {
     int tile[3];          /* tile edge per axis in grid points, 0 = automatic.  Must divide
                              Ntilde_d, be >= 2m and leave >= 2 tiles per axis. */
-    int window;           /* NFFT_WINDOW_POLY (default) or NFFT_WINDOW_DIRECT */
+    int window;           /* NFFT_WINDOW_POLY (default), _DIRECT, _TENSOR, _LINEAR or _FULL */
     int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
                              into items of at most this many), 0 = automatic (1024) */
     int reserved[5];      /* must be zero */

@@ -20,6 +20,11 @@ NFFT_C64 = 0
 NFFT_C128 = 1
 NFFT_WINDOW_POLY = 0
 NFFT_WINDOW_DIRECT = 1
+NFFT_WINDOW_TENSOR = 2
+NFFT_WINDOW_LINEAR = 3
+NFFT_WINDOW_FULL = 4
+WINDOWS = {"poly": NFFT_WINDOW_POLY, "direct": NFFT_WINDOW_DIRECT, "tensor": NFFT_WINDOW_TENSOR,
+           "linear": NFFT_WINDOW_LINEAR, "full": NFFT_WINDOW_FULL}
 
 EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft_forward",
            "nfft_adjoint", "nfft_resample_forward", "nfft_resample_adjoint", "nfft_fft_grid",

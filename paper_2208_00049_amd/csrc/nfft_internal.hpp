@@ -131,6 +131,8 @@ struct nfft_plan_s {
     int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}, grouped by tile
     int *tile_sub = nullptr;       // ntiles + 1: first work item of each tile
     void *pad = nullptr;           // nsub padded tiles (spreading scratch), complex
+    void *wtab = nullptr;          // window tables: TENSOR / FULL per sorted node, LINEAR per axis
+    long long lin_S = 0;           // LINEAR: entries per axis
     // multi-channel calls: K grids and K sets of padded tiles, grown on demand
     void *grid_many = nullptr;
     void *pad_many = nullptr;
@@ -155,6 +157,8 @@ hipError_t launch_deconv_factors(const nfft_plan_s &p, hipStream_t s);
 hipError_t launch_window_poly(const nfft_plan_s &p, const double *qt, const double *r, int Z,
                               int Theta, hipStream_t s);
 hipError_t launch_twiddles(const nfft_plan_s &p, int axis, hipStream_t s);
+// TENSOR / FULL weights of the sorted nodes, or the LINEAR tables (plan's window mode)
+hipError_t launch_window_tables(const nfft_plan_s &p, hipStream_t s);
 
 // binsort.hip
 hipError_t launch_fill_int(int *a, int64_t n, int v, hipStream_t s);

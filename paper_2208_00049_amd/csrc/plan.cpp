@@ -230,7 +230,8 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
         if (G >= ((int64_t)1 << 31)) return NFFT_ERR_UNSUPPORTED;
     }
     if (opts) {
-        if (opts->window != NFFT_WINDOW_POLY && opts->window != NFFT_WINDOW_DIRECT) return NFFT_ERR_ARG;
+        if (opts->window < NFFT_WINDOW_POLY || opts->window > NFFT_WINDOW_FULL) return NFFT_ERR_ARG;
+        if (opts->window == NFFT_WINDOW_FULL && D == 3) return NFFT_ERR_UNSUPPORTED;
         if (opts->max_block_nodes < 0) return NFFT_ERR_ARG;
         for (int i = 0; i < 5; ++i)
             if (opts->reserved[i]) return NFFT_ERR_ARG;
@@ -258,6 +259,7 @@ void release(nfft_plan_s *p) {
     (void)hipFree(p->pad);
     (void)hipFree(p->grid_many);
     (void)hipFree(p->pad_many);
+    (void)hipFree(p->wtab);
     delete p;
 }
 
@@ -441,6 +443,24 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     if (host_bad) rc = NFFT_ERR_NODES;
     if (rc == NFFT_OK && p->nsub > 0)
         TRY(hipMalloc(&p->pad, (size_t)p->nsub * padded_cells(p->geom, D) * cs));
+    if (rc == NFFT_OK && p->window != NFFT_WINDOW_POLY && p->window != NFFT_WINDOW_DIRECT) {
+        // window tables of the precomputation modes (FP64 evaluation, plan type storage)
+        size_t n = 0;
+        if (p->window == NFFT_WINDOW_LINEAR) {
+            static const int kLinearC[8] = {3, 7, 9, 14, 17, 20, 23, 24};
+            p->lin_S = (long long)m * (1LL << kLinearC[std::min(m, 8) - 1]) + 2;
+            n = (size_t)D * p->lin_S;
+        } else if (p->window == NFFT_WINDOW_TENSOR) {
+            n = (size_t)M * D * 2 * m;
+        } else {
+            n = (size_t)M * (D == 1 ? 2 * m : 4 * m * m);
+        }
+        if (n > 0) {
+            TRY(hipMalloc(&p->wtab, n * rs));
+            TRY(launch_window_tables(*p, s));
+            TRY(hipStreamSynchronize(s));
+        }
+    }
 
 fail:
     (void)hipFree(keys);

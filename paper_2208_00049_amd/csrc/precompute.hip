@@ -79,6 +79,55 @@ __global__ void k_window_poly(int m, int Z, int Theta, const double *betas, cons
     }
 }
 
+// LINEAR window table (paper, LINEAR item of subsection "Window
+// precomputation"): psi_s = psi_hat_Base(s / (S - 2)) for s <= S - 2 (the sinh
+// form, whose value at |u| = 1 is the limit beta/pi, the half-open support's
+// value at u = -1) and psi_{S-1} = 0, outside the support.  FP64, stored in T.
+template <typename T>
+__global__ void k_window_linear(long long S, double beta, T *table) {
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    table[s] = s == S - 1 ? (T)0 : (T)window_hat_fp64((double)s / (double)(S - 2), beta);
+}
+
+// Polynomial window weight of tap t at offset frac, evaluated like the
+// resampling kernels do (Horner in T on zeta = frac - 1/2).
+template <typename T>
+__device__ inline T poly_weight(const T *mu, int Z, T frac) {
+    const T z = frac - (T)0.5;
+    T acc = mu[Z - 1];
+    for (int k = Z - 2; k >= 0; --k) acc = fma(acc, z, mu[k]);
+    return acc;
+}
+
+// TENSOR precomputation: per sorted node k, axis d, tap t, the window weight
+// (polynomial window, as the paper combines TENSOR with it):
+// out[(k D + d) 2m + t].  FULL (D <= 2): per sorted node the (2m)^D products
+// out[k (2m)^D + a 2m + b] = w_0[a] w_1[b] (1-D: the 2m weights).
+template <typename T, int D>
+__global__ void k_window_nodes(const NodeRec<T, D> *nodes, long long M, int m, const T *mu,
+                               int full, T *out) {
+    const int M2 = 2 * m, Z = 2 * m + 1;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!full) {
+        if (i >= M * D * M2) return;
+        const long long k = i / (D * M2);
+        const int r = (int)(i - k * D * M2), d = r / M2, t = r - d * M2;
+        out[i] = poly_weight(mu + ((size_t)d * M2 + t) * Z, Z, nodes[k].fr[d]);
+    } else if (D == 1) {
+        if (i >= M * M2) return;
+        const long long k = i / M2;
+        const int t = (int)(i - k * M2);
+        out[i] = poly_weight(mu + (size_t)t * Z, Z, nodes[k].fr[0]);
+    } else {
+        if (i >= M * M2 * M2) return;
+        const long long k = i / (M2 * M2);
+        const int r = (int)(i - k * M2 * M2), a = r / M2, b = r - a * M2;
+        out[i] = poly_weight(mu + (size_t)a * Z, Z, nodes[k].fr[0]) *
+                 poly_weight(mu + ((size_t)M2 + b) * Z, Z, nodes[k].fr[D - 1]);
+    }
+}
+
 // Twiddle table exp(-2 pi i t / L), t = 0..L-1, evaluated in FP64.
 template <typename T>
 __global__ void k_twiddles(int L, cplx<T> *tw) {
@@ -119,6 +168,45 @@ hipError_t launch_window_poly(const nfft_plan_s &p, const double *qt, const doub
     else
         hipLaunchKernelGGL(k_window_poly<double>, dim3(p.D), dim3(64), 0, s, p.m, Z, Theta, betas,
                            qt, r, (double *)p.coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_tables(const nfft_plan_s &p, hipStream_t s) {
+    if (p.window == NFFT_WINDOW_LINEAR) {
+        // one table per axis: beta depends on sigma_d
+        for (int d = 0; d < p.D; ++d) {
+            const unsigned blocks = (unsigned)((p.lin_S + 255) / 256);
+            if (p.dtype == NFFT_C64)
+                hipLaunchKernelGGL(k_window_linear<float>, dim3(blocks), dim3(256), 0, s, p.lin_S,
+                                   kb_beta(p, d), (float *)p.wtab + (size_t)d * p.lin_S);
+            else
+                hipLaunchKernelGGL(k_window_linear<double>, dim3(blocks), dim3(256), 0, s, p.lin_S,
+                                   kb_beta(p, d), (double *)p.wtab + (size_t)d * p.lin_S);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    if (p.window != NFFT_WINDOW_TENSOR && p.window != NFFT_WINDOW_FULL) return hipSuccess;
+    if (p.M == 0) return hipSuccess;
+    const int full = p.window == NFFT_WINDOW_FULL;
+    const long long per = full ? (p.D == 1 ? 2 * p.m : 4LL * p.m * p.m) : (long long)p.D * 2 * p.m;
+    const long long n = p.M * per;
+    const dim3 g((unsigned)((n + 255) / 256));
+#define NFFT_WT(T, DD)                                                                            \
+    hipLaunchKernelGGL((k_window_nodes<T, DD>), g, dim3(256), 0, s,                               \
+                       (const NodeRec<T, DD> *)p.nodes, (long long)p.M, p.m, (const T *)p.coef,  \
+                       full, (T *)p.wtab)
+    if (p.dtype == NFFT_C64) {
+        if (p.D == 1) NFFT_WT(float, 1);
+        else if (p.D == 2) NFFT_WT(float, 2);
+        else NFFT_WT(float, 3);
+    } else {
+        if (p.D == 1) NFFT_WT(double, 1);
+        else if (p.D == 2) NFFT_WT(double, 2);
+        else NFFT_WT(double, 3);
+    }
+#undef NFFT_WT
     return hipGetLastError();
 }
 

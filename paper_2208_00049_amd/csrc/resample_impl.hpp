@@ -40,11 +40,15 @@ namespace nfft {
 
 template <typename T> struct WinParams {
     T beta[kMaxD];
+    const T *tab;  // TENSOR / FULL: weights per sorted node; LINEAR: S samples per axis
+    long long S;   // LINEAR table entries per axis
 };
 
-// Window value of tap t for a node with offset frac (lane-owned coefficients cf).
+// Window value of tap t for a node with offset frac (lane-owned coefficients cf;
+// lin: the axis's LINEAR table of S entries).
 template <typename T, int M2>
-__device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta) {
+__device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, const T *lin,
+                               long long S) {
     if (window == NFFT_WINDOW_POLY) {
         const T z = frac - (T)0.5;
         T acc = cf[M2];
@@ -53,6 +57,16 @@ __device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta) {
         return acc;
     }
     constexpr int m = M2 / 2;
+    if (window == NFFT_WINDOW_LINEAR) {
+        // kappa = |u| (S - 2), s = floor(kappa), alpha = kappa - s; |u| <= 1, so s + 1 < S
+        const double u = ((double)frac + (double)(m - 1 - t)) / (double)m;
+        const double kappa = fabs(u) * (double)(S - 2);
+        long long i = (long long)kappa;
+        if (i > S - 2) i = S - 2;
+        const T alpha = (T)(kappa - (double)i);
+        const T a = lin[i], b = lin[i + 1];
+        return a + alpha * (b - a);
+    }
     const T u = (frac + (T)(m - 1 - t)) / (T)m;
     const T s2 = (T)1 - u * u;
     const T s = s2 > (T)0 ? sqrt(s2) : (T)0;
@@ -177,6 +191,40 @@ template <typename T, int D, int M2> struct LaneWindow {
     }
 };
 
+// Weights of this lane's tap li along every axis for the node at sorted
+// position gk (TENSOR and FULL read the plan's per-node tables; FULL keeps the
+// last axis's factor at 1 because its row weights are whole products).
+template <typename T, int D, int M2>
+__device__ inline void node_weights(T *w, const LaneWindow<T, D, M2> &lw, const T *fr, long long gk,
+                                    int li, int window, const WinParams<T> &wp) {
+    if (window == NFFT_WINDOW_TENSOR) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) w[d] = wp.tab[(gk * D + d) * M2 + li];
+    } else if (window == NFFT_WINDOW_FULL) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) w[d] = (T)1;
+        if (D == 1) w[0] = wp.tab[gk * M2 + li];
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, window, wp.beta[d], wp.tab + d * wp.S,
+                                     wp.S);
+    }
+}
+
+// Row weights of a 2-D node: the weights of axis 0 broadcast from the group's
+// lanes, or, with FULL, the lane's own column of the node's (2m)^2 products.
+template <typename T, int M2>
+__device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, int gbase, int window,
+                                      const WinParams<T> &wp) {
+    if (window == NFFT_WINDOW_FULL) {
+#pragma unroll
+        for (int a = 0; a < M2; ++a) w0[a] = wp.tab[(gk * M2 + a) * M2 + li];
+    } else {
+        BcastAll<M2, 0, T>::run(w0, w_axis0, gbase);
+    }
+}
+
 template <typename T, int D, int M2>
 __global__ void __launch_bounds__(kResampleThreads)
     k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
@@ -282,13 +330,15 @@ __global__ void __launch_bounds__(kResampleThreads)
             const int k = base + grp;
             const bool valid = grp < NPW && k < n;
             const int ks = valid ? k : 0;
-            T w[D];
+            T w[D], fr[D];
             int l[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 l[d] = st.l[d][ks];
-                w[d] = tap_weight<T, M2>(lw.cf[d], st.fr[d][ks], li, window, wp.beta[d]);
+                fr[d] = st.fr[d][ks];
             }
+            const long long gk = c0 + ks;  // sorted position of the node
+            node_weights<T, D, M2>(w, lw, fr, gk, li, window, wp);
             T ar = (T)0, ai = (T)0;
             if constexpr (D == 1) {
                 const C v = tile[l[0] + li];
@@ -296,7 +346,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 ai = w[0] * v.y;
             } else if constexpr (D == 2) {
                 T w0[M2];
-                BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                row_weights_2d<T, M2>(w0, w[0], gk, li, gbase, window, wp);
                 const C *row = tile + l[0] * P[1] + l[1] + li;
 #pragma unroll
                 for (int a = 0; a < M2; ++a) {
@@ -497,13 +547,15 @@ __global__ void __launch_bounds__(kResampleThreads)
             const int k = base + grp;
             const bool valid = grp < NPW && k < n;
             const int ks = valid ? k : 0;
-            T w[D];
+            T w[D], fr[D];
             int l[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 l[d] = st.l[d][ks];
-                w[d] = tap_weight<T, M2>(lw.cf[d], st.fr[d][ks], li, window, wp.beta[d]);
+                fr[d] = st.fr[d][ks];
             }
+            const long long gk = c0 + ks;  // sorted position of the node
+            node_weights<T, D, M2>(w, lw, fr, gk, li, window, wp);
             // the lane's tap along the last axis, with the value and the scale folded in
             const T ws = valid ? w[D - 1] * scale : (T)0;
             const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
@@ -511,7 +563,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 FP::add(acc + SL * (l[0] + li), pr, pi);
             } else if constexpr (D == 2) {
                 T w0[M2];
-                BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                row_weights_2d<T, M2>(w0, w[0], gk, li, gbase, window, wp);
                 unsigned long long *ap = acc + SL * (l[0] * P[1] + l[1] + li);
                 const int rs = SL * P[1];
 #pragma unroll
@@ -667,6 +719,8 @@ template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
     WinParams<T> wp;
     for (int d = 0; d < kMaxD; ++d)
         wp.beta[d] = d < p.D ? (T)(M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d])) : (T)0;
+    wp.tab = (const T *)p.wtab;
+    wp.S = p.lin_S;
     return wp;
 }
 

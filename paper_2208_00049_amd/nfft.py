@@ -24,8 +24,9 @@ class Plan:
     """NFFT plan for nodes ``x`` (device tensor (M, D), float32 or float64) and size ``N``.
 
     float32 nodes give a complex64 plan (FP32 arithmetic), float64 nodes a
-    complex128 plan.  ``tile``: optional per-axis tile edges; ``window``: "poly"
-    (default) or "direct"; ``max_block_nodes``: cap on nodes per resampling
+    complex128 plan.  ``tile``: optional per-axis tile edges; ``window``: the window
+    evaluation, "poly" (default), "direct", "tensor", "linear" or "full" (the paper's
+    precomputation options); ``max_block_nodes``: cap on nodes per resampling
     work item; ``tune``: if > 0 (and no tile is given), the library's autotuner
     picks the tiles, timing each candidate ``tune`` times (``tuned_ms`` then
     holds the chosen plan's forward + adjoint milliseconds).
@@ -58,7 +59,7 @@ class Plan:
         if tile is not None:
             for d, q in enumerate(tile):
                 opts.tile[d] = int(q)
-        opts.window = {"poly": _lib.NFFT_WINDOW_POLY, "direct": _lib.NFFT_WINDOW_DIRECT}[window]
+        opts.window = _lib.WINDOWS[window]
         opts.max_block_nodes = int(max_block_nodes)
         Narr = (ctypes.c_int64 * self.D)(*N)
         handle = ctypes.c_void_p()

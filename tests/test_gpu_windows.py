@@ -1,0 +1,68 @@
+"""GPU tests of the window-evaluation modes (the paper's precomputation options).
+
+* TENSOR stores the polynomial-window weights per node: results are bit for bit
+  those of POLYNOMIAL (same Horner evaluation, done at plan time).
+* FULL stores the (2m)^D weight products per node (D <= 2): the oracle with the
+  polynomial window, within the rounding tolerance; D = 3 is rejected.
+* LINEAR looks the window up in a table of m 2^c + 2 samples with linear
+  interpolation: the oracle with the same lookup, within the rounding tolerance,
+  and the NDFT within the approximation gate.
+"""
+import numpy as np
+import pytest
+import torch
+
+import nfft_workloads as wl
+from oracle import ndft
+from oracle import nfft_alg as na
+from test_gpu_nfft import NDFT_GATE, e2e_tol, make_plan, rel2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((256,), 512, 4, 2.0, "c128"), ((64, 64), 5000, 4, 2.0, "c64"),
+         ((48, 64), 3000, 6, 2.0, "c128"), ((32, 32), 2000, 2, 2.0, "c64"),
+         ((16, 16, 16), 3000, 4, 2.0, "c64"), ((16, 24, 16), 2000, 4, 1.25, "c128")]
+
+
+def run(device, N, M, m, sigma, dt, window, config):
+    x = wl.uniform_nodes(M, len(N), config=config, stream=0)
+    f = wl.cn01(N, config=config, stream=1)
+    fh = wl.cn01((M,), config=config, stream=2)
+    p, xs = make_plan(device, x, N, m, sigma, dt, window=window)
+    return p.forward(to_dev(f, dt, device)), p.adjoint(to_dev(fh, dt, device)), xs, f, fh
+
+
+@pytest.mark.parametrize("N,M,m,sigma,dt", CASES)
+def test_tensor_is_bitwise_poly(device, N, M, m, sigma, dt):
+    ft, yt, *_ = run(device, N, M, m, sigma, dt, "tensor", 60)
+    fp, yp, *_ = run(device, N, M, m, sigma, dt, "poly", 60)
+    assert torch.equal(ft, fp) and torch.equal(yt, yp)
+
+
+@pytest.mark.parametrize("N,M,m,sigma,dt", [c for c in CASES if len(c[0]) <= 2])
+def test_full_matches_oracle(device, N, M, m, sigma, dt):
+    fg, yg, xs, f, fh = run(device, N, M, m, sigma, dt, "full", 61)
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(fg.cpu().numpy(), na.forward(xs, f, m, sigma)) < tol
+    assert rel2(yg.cpu().numpy(), na.adjoint(xs, fh, N, m, sigma)) < tol
+
+
+def test_full_rejects_3d(device):
+    from paper_2208_00049_amd import NfftError
+    with pytest.raises(NfftError):
+        make_plan(device, np.zeros((10, 3)), (16, 16, 16), 4, 2.0, "c64", window="full")
+
+
+@pytest.mark.parametrize("N,M,m,sigma,dt", CASES)
+def test_linear_matches_oracle(device, N, M, m, sigma, dt):
+    fg, yg, xs, f, fh = run(device, N, M, m, sigma, dt, "linear", 62)
+    print("linear", N, m, sigma, dt, flush=True)
+    # the table lookup's interpolation weight is computed from the FP32 fraction on the GPU
+    # (FP64 in the oracle): same order as the rounding of the polynomial path
+    tol = e2e_tol(N, sigma, m, dt)
+    fo = na.forward(xs, f, m, sigma, window="linear")
+    yo = na.adjoint(xs, fh, N, m, sigma, window="linear")
+    assert rel2(fg.cpu().numpy(), fo) < tol and rel2(yg.cpu().numpy(), yo) < tol
+    if (m, sigma) in NDFT_GATE:
+        gate = NDFT_GATE[(m, sigma)] + tol
+        assert rel2(fg.cpu().numpy(), ndft.ndft_forward(xs, f)) < 2 * gate
