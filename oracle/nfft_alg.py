@@ -75,6 +75,19 @@ def window_hat(u, beta):
     return np.where(inside, val, 0.0)
 
 
+def window_hat_full(u, beta):
+    """phi_hat_Base(u): the Fourier transform of phi_Base on the whole line -- the sinh form
+    for |u| < 1, beta/pi at |u| = 1, its continuation sin(beta sqrt(u^2-1)) / (pi sqrt(u^2-1))
+    for |u| > 1.  The (2m+2)-tap stencil samples it beyond the truncation interval."""
+    u = np.asarray(u, dtype=np.float64)
+    q = 1.0 - u * u
+    r = np.sqrt(np.abs(q))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        inner = np.sinh(beta * r) / (np.pi * np.where(r > 0, r, 1.0))
+        outer = np.sin(beta * r) / (np.pi * np.where(r > 0, r, 1.0))
+    return np.where(r == 0, beta / np.pi, np.where(q > 0, inner, outer))
+
+
 def window_phi(xi, beta):
     """phi_Base(xi) = I0(sqrt(beta^2 - 4 pi^2 xi^2)) for |2 pi xi| <= beta."""
     xi = np.asarray(xi, dtype=np.float64)
@@ -94,24 +107,30 @@ def deconv_factors(N_d, Nt_d, m):
     return 1.0 / (m * window_phi(m * n / Nt_d, beta))
 
 
-def poly_coeffs(m, beta, Z=None, Theta=None):
+def poly_coeffs(m, beta, Z=None, Theta=None, wide=False):
     """Piecewise-polynomial window approximation (POLYNOMIAL precomputation).
 
     For each tap t = 0..2m-1 a polynomial P_t of degree Z-1 (default 2m) in
     zeta = frac - 1/2 in [-1/2, 1/2] is fitted by least squares to Theta = 2Z
     equispaced samples of psi_hat_Base((zeta + m - 1/2 - t)/m); returns
     mu[t, z] so that P_t(zeta) = sum_z mu[t, z] zeta^z.  The continuous sinh form
-    is sampled (its value at |u| = 1 is the limit beta/pi).
+    is sampled (its value at |u| = 1 is the limit beta/pi).  wide: the 2m+2 taps
+    t = 0..2m+1 of the (2m+2)-point stencil, samples of phi_hat_Base((zeta + m +
+    1/2 - t)/m) (beyond |u| = 1 the sin continuation).
     """
     Z = 2 * m + 1 if Z is None else Z
     Theta = 2 * Z if Theta is None else Theta
     zeta = -0.5 + np.arange(Theta) / (Theta - 1.0)
     V = zeta[:, None] ** np.arange(Z)[None, :]
-    mu = np.zeros((2 * m, Z))
-    for t in range(2 * m):
-        u = (zeta + m - 0.5 - t) / m
-        s = np.sqrt(np.clip(1.0 - u * u, 0.0, None))
-        b = np.where(s > 0, np.sinh(beta * s) / (np.pi * np.where(s > 0, s, 1.0)), beta / np.pi)
+    taps, lo = (2 * m + 2, m) if wide else (2 * m, m - 1)
+    mu = np.zeros((taps, Z))
+    for t in range(taps):
+        u = (zeta + lo + 0.5 - t) / m
+        if wide:
+            b = window_hat_full(u, beta)
+        else:
+            s = np.sqrt(np.clip(1.0 - u * u, 0.0, None))
+            b = np.where(s > 0, np.sinh(beta * s) / (np.pi * np.where(s > 0, s, 1.0)), beta / np.pi)
         mu[t] = np.linalg.lstsq(V, b, rcond=None)[0]
     return mu
 
@@ -149,24 +168,28 @@ def linear_lookup(u, table):
     return table[s] + alpha * (table[s + 1] - table[s])
 
 
-def tap_weights(frac, m, beta, window="poly"):
+def tap_weights(frac, m, beta, window="poly", wide=False):
     """Window weights for the 2m taps of nodes with fractional offset ``frac``; shape (..., 2m).
 
     window: "poly" (POLYNOMIAL), "direct" (no precomputation) or "linear" (LINEAR table
     lookup); the paper's TENSOR and FULL modes store "poly" weights and so compute the same.
+    wide: the 2m+2 taps of the (2m+2)-point stencil, tap t at u = (frac + m - t)/m, with
+    the untruncated window phi_hat_Base ("Window Size Considerations").
     """
     frac = np.asarray(frac, dtype=np.float64)
-    t = np.arange(2 * m)
+    taps, lo = (2 * m + 2, m) if wide else (2 * m, m - 1)
+    t = np.arange(taps)
+    u = (frac[..., None] + lo - t) / m
     if window == "direct":
-        return window_hat((frac[..., None] + m - 1 - t) / m, beta)
+        return window_hat_full(u, beta) if wide else window_hat(u, beta)
     if window == "poly":
-        mu = poly_coeffs(m, beta)
+        mu = poly_coeffs(m, beta, wide=wide)
         zeta = frac - 0.5
         powers = zeta[..., None] ** np.arange(mu.shape[1])
         return powers @ mu.T
-    if window == "linear":
-        return linear_lookup((frac[..., None] + m - 1 - t) / m, linear_table(m, beta))
-    raise ValueError("window must be 'poly', 'direct' or 'linear'")
+    if window == "linear" and not wide:
+        return linear_lookup(u, linear_table(m, beta))
+    raise ValueError("window must be 'poly', 'direct' or 'linear' (not wide)")
 
 
 # ---------------------------------------------------------------------------
@@ -178,11 +201,11 @@ def _wrap(x):
     return x - np.floor(x + 0.5)
 
 
-def _stencil(x, Nt, m):
-    """Per node and axis: stencil origin c - m + 1 (unwrapped) and frac."""
+def _stencil(x, Nt, m, wide=False):
+    """Per node and axis: stencil origin c - m + 1 (wide: c - m; unwrapped) and frac."""
     y = _wrap(x) * np.asarray(Nt, dtype=np.float64)[None, :]
     c = np.floor(y)
-    return (c - m + 1).astype(np.int64), y - c
+    return (c - (m if wide else m - 1)).astype(np.int64), y - c
 
 
 def _band_index(N_d, Nt_d):
@@ -191,17 +214,18 @@ def _band_index(N_d, Nt_d):
     return np.mod(n, Nt_d)
 
 
-def _weights_per_axis(x, N, Nt, m, window):
-    origin, frac = _stencil(x, Nt, m)
+def _weights_per_axis(x, N, Nt, m, window, wide=False):
+    origin, frac = _stencil(x, Nt, m, wide)
     ws = []
     for d in range(len(N)):
         beta = kb_beta(m, Nt[d] / N[d])
-        ws.append(tap_weights(frac[:, d], m, beta, window))
+        ws.append(tap_weights(frac[:, d], m, beta, window, wide))
     return origin, ws
 
 
-def forward(x, f, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False):
-    """Direct NFFT, Algorithm 1 (resampling correction, FFT, resampling)."""
+def forward(x, f, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False, wide=False):
+    """Direct NFFT, Algorithm 1 (resampling correction, FFT, resampling); wide: the
+    (2m+2)-point stencil."""
     f = np.asarray(f, dtype=np.complex128)
     N = f.shape
     D = len(N)
@@ -221,14 +245,15 @@ def forward(x, f, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False):
     ghat = np.fft.fftn(g)
 
     # step 3: fhat_j = sum over the (2m)^D stencil of prod_d w_d * ghat[l mod Nt]
-    fhat = resample_forward(x, ghat, N, m, Nt, window)
+    fhat = resample_forward(x, ghat, N, m, Nt, window, wide)
     if return_steps:
         return fhat, {"g": g, "ghat": ghat, "Nt": Nt}
     return fhat
 
 
-def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False):
-    """Adjoint NFFT, Algorithm 2 (adjoint resampling, adjoint FFT, resampling correction)."""
+def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=False, wide=False):
+    """Adjoint NFFT, Algorithm 2 (adjoint resampling, adjoint FFT, resampling correction);
+    wide: the (2m+2)-point stencil."""
     N = tuple(int(v) for v in N)
     D = len(N)
     Nt = oversampled_size(N, sigma) if Nt is None else tuple(Nt)
@@ -237,7 +262,7 @@ def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=Fal
     G = int(np.prod(Nt))
 
     # step 1: ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt)
-    ghat = resample_adjoint(x, fhat, N, m, Nt, window)
+    ghat = resample_adjoint(x, fhat, N, m, Nt, window, wide)
 
     # step 2: g_n = sum_l ghat_l exp(+2 pi i n.l/Nt)  (unnormalised)
     g = np.fft.ifftn(ghat) * G
@@ -253,7 +278,7 @@ def adjoint(x, fhat, N, m=4, sigma=2.0, Nt=None, window="poly", return_steps=Fal
     return y
 
 
-def resample_forward(x, ghat, N, m, Nt, window="poly"):
+def resample_forward(x, ghat, N, m, Nt, window="poly", wide=False):
     """Resampling of Algorithm 1 (step 3): fhat_j = sum_l ghat_l psi_tilde(x_j - l/Nt).
 
     ``ghat`` is the oversampled grid in storage order (index l mod Nt).
@@ -262,11 +287,11 @@ def resample_forward(x, ghat, N, m, Nt, window="poly"):
     D = len(N)
     Nt = tuple(int(v) for v in Nt)
     x = np.asarray(x, dtype=np.float64).reshape(-1, D)
-    origin, ws = _weights_per_axis(x, N, Nt, m, window)
+    origin, ws = _weights_per_axis(x, N, Nt, m, window, wide)
     J = x.shape[0]
     flat_g = np.asarray(ghat, dtype=np.complex128).reshape(-1)
     fhat = np.zeros(J, dtype=np.complex128)
-    for taps in np.ndindex(*([2 * m] * D)):
+    for taps in np.ndindex(*([ws[0].shape[1]] * D)):
         w = np.ones(J)
         flat = np.zeros(J, dtype=np.int64)
         for d in range(D):
@@ -276,19 +301,19 @@ def resample_forward(x, ghat, N, m, Nt, window="poly"):
     return fhat
 
 
-def resample_adjoint(x, fhat, N, m, Nt, window="poly"):
+def resample_adjoint(x, fhat, N, m, Nt, window="poly", wide=False):
     """Adjoint resampling of Algorithm 2 (step 1): ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt)."""
     N = tuple(int(v) for v in N)
     D = len(N)
     Nt = tuple(int(v) for v in Nt)
     x = np.asarray(x, dtype=np.float64).reshape(-1, D)
     fhat = np.asarray(fhat, dtype=np.complex128).reshape(-1)
-    origin, ws = _weights_per_axis(x, N, Nt, m, window)
+    origin, ws = _weights_per_axis(x, N, Nt, m, window, wide)
     J = x.shape[0]
     G = int(np.prod(Nt))
     acc_re = np.zeros(G)
     acc_im = np.zeros(G)
-    for taps in np.ndindex(*([2 * m] * D)):
+    for taps in np.ndindex(*([ws[0].shape[1]] * D)):
         w = np.ones(J)
         flat = np.zeros(J, dtype=np.int64)
         for d in range(D):

@@ -123,7 +123,8 @@ def test_planted_fft_sign_is_caught(monkeypatch):
 def test_planted_stencil_offset_is_caught(monkeypatch):
     orig = na._stencil
     assert _fails_pin(monkeypatch, (na, "_stencil"),
-                      lambda x, Nt, m: (orig(x, Nt, m)[0] - 1, orig(x, Nt, m)[1]))
+                      lambda x, Nt, m, wide=False: (orig(x, Nt, m, wide)[0] - 1,
+                                                    orig(x, Nt, m, wide)[1]))
 
 
 def test_planted_deconv_scale_is_caught(monkeypatch):
@@ -135,7 +136,8 @@ def test_planted_deconv_scale_is_caught(monkeypatch):
 def test_planted_reversed_taps_are_caught(monkeypatch):
     orig = na.tap_weights
     assert _fails_pin(monkeypatch, (na, "tap_weights"),
-                      lambda frac, m, beta, window="poly": orig(frac, m, beta, window)[..., ::-1])
+                      lambda frac, m, beta, window="poly", wide=False:
+                      orig(frac, m, beta, window, wide)[..., ::-1])
 
 
 def test_planted_window_phi_frequency_is_caught(monkeypatch):
@@ -164,3 +166,36 @@ def test_linear_window_nfft_against_ndft(m, sigma, gate):
     e_p = _rel2(na.forward(x, f, m, sigma, window="poly"), ndft.ndft_forward(x, f))
     assert e_f < gate and e_a < gate
     assert e_f < 2 * e_p + 1e-12
+
+
+@pytest.mark.parametrize("m", [3, 4])
+def test_wide_stencil_accuracy_ordering(m):
+    """Window Size Considerations / Accuracy Analysis: 2m+2 taps with the untruncated window
+    are more accurate than 2m taps at the same m, and less accurate than 2(m+1) taps
+    (m increased by one)."""
+    N = (24, 32)
+    x = wl.uniform_nodes(600, 2, config=71, stream=0)
+    f = wl.cn01(N, config=71, stream=1)
+    fh = wl.cn01((600,), config=71, stream=2)
+    ref_f, ref_a = ndft.ndft_forward(x, f), ndft.ndft_adjoint(x, fh, N)
+    e = {}
+    for key, mm, wide in [("2m", m, False), ("2m+2", m, True), ("2(m+1)", m + 1, False)]:
+        e[key] = (_rel2(na.forward(x, f, mm, 2.0, wide=wide), ref_f),
+                  _rel2(na.adjoint(x, fh, N, mm, 2.0, wide=wide), ref_a))
+    for i in range(2):
+        assert e["2(m+1)"][i] < e["2m+2"][i] < e["2m"][i], e
+
+
+def test_wide_stencil_is_a_plain_sum_on_tiny_input():
+    """Brute force: one node, the (2m+2)^D-term resampling sum written out by hand."""
+    m, N, Nt = 2, (8,), (16,)
+    x = np.array([[0.1234]])
+    g = wl.cn01(Nt, config=72, stream=1)
+    beta = na.kb_beta(m, 2.0)
+    y = 16 * 0.1234
+    c = np.floor(y)
+    want = 0.0
+    for l in range(int(c) - m, int(c) + m + 2):
+        want += na.window_hat_full((y - l) / m, beta) * g[l % 16]
+    got = na.resample_forward(x, g, N, m, Nt, window="direct", wide=True)[0]
+    assert abs(got - want) < 1e-12 * abs(want)

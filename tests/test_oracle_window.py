@@ -143,3 +143,20 @@ def test_linear_lookup_exact_at_samples_and_within_bound(m, sigma):
     assert np.all(err <= 1.5 * h * h / 8 * second + 1e-14 * na.window_hat(0.0, beta))
     # symmetric in u
     assert np.array_equal(na.linear_lookup(uu, table), na.linear_lookup(-uu, table))
+
+
+@pytest.mark.parametrize("m,sigma", [(4, 2.0), (3, 2.0)])
+def test_kb_fourier_pair_beyond_the_support(m, sigma):
+    """phi_hat_Base for |u| > 1 (sampled by the (2m+2)-tap stencil) is the same Fourier
+    integral of phi_Base: the sin continuation of the sinh form."""
+    beta = na.kb_beta(m, sigma)
+    bmp = mp.mpf(beta)
+    lim = bmp / (2 * mp.pi)
+    peak = na.window_hat_full(0.0, beta)
+    for u in [1.05, -1.2, 1.3, 0.5]:
+        val = mp.quad(lambda xi: mp.besseli(0, mp.sqrt(max(bmp ** 2 - (2 * mp.pi * xi) ** 2, 0)))
+                      * mp.cos(2 * mp.pi * u * xi), [-lim, 0, lim])
+        got = na.window_hat_full(u, beta)
+        # relative to the window's peak: the tail values are ~1/sinh(beta) of it
+        assert abs(got - float(val)) <= 1e-13 * peak, (m, sigma, u)
+    assert na.window_hat_full(1.0, beta) == beta / np.pi
