@@ -1,8 +1,9 @@
 // Plan-time node preparation and GPU bin sort of the nodes into grid tiles.
 //
 // Per node and axis (in FP64): wrap x into [-1/2, 1/2), y = Nt*x, c = floor(y),
-// frac = y - c, stencil origin o = (c - m + 1) mod Nt.  The stencil of the node
-// covers grid points o .. o+2m-1 (mod Nt) on that axis.  The node is binned by
+// frac = y - c, stencil origin o = (c - lo) mod Nt with lo = m - 1 (2m points)
+// or m (the wide stencil of 2m + 2 points).  The stencil of the node covers grid
+// points o .. o+taps-1 (mod Nt) on that axis.  The node is binned by
 // the tile that holds its origin, and by a class bit per axis that says whether
 // its stencil runs past the end of that tile into the next one.  Sort key =
 // tile << D | class; counting sort = histogram, exclusive scan, scatter.
@@ -33,11 +34,11 @@ struct Cell {
     double frac;  // fractional offset in [0, 1)
 };
 
-__device__ inline Cell node_cell(double xv, int Nt, int m) {
+__device__ inline Cell node_cell(double xv, int Nt, int lo) {
     const double xw = xv - floor(xv + 0.5);
     const double y = xw * (double)Nt;
     const double c = floor(y);
-    long long o = (long long)c - m + 1;
+    long long o = (long long)c - lo;
     o %= Nt;
     if (o < 0) o += Nt;
     Cell cell;
@@ -59,11 +60,11 @@ __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, i
             ok = false;
             continue;
         }
-        const Cell c = node_cell(xv, g.Nt[d], g.m);
+        const Cell c = node_cell(xv, g.Nt[d], g.lo);
         const int p = c.o / g.Q[d];
         const int loc = c.o - p * g.Q[d];
         tile = tile * g.T[d] + p;
-        cls |= (loc >= g.Q[d] - (2 * g.m - 1)) ? (1 << d) : 0;
+        cls |= (loc >= g.Q[d] - (g.taps - 1)) ? (1 << d) : 0;
     }
     if (!ok) {
         *bad = 1;
@@ -86,7 +87,7 @@ __global__ void k_node_scatter(const T *x, int M, Geom g, const int *keys, int *
     for (int d = 0; d < D; ++d) {
         double xv = (double)x[(size_t)j * D + d];
         if (!isfinite(xv)) xv = 0.0;  // the plan is rejected; keep the record in range
-        const Cell c = node_cell(xv, g.Nt[d], g.m);
+        const Cell c = node_cell(xv, g.Nt[d], g.lo);
         rec.o[d] = c.o;
         rec.fr[d] = (T)c.frac;
     }

@@ -549,7 +549,7 @@ hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const Axi
     const FftLine fl = with_lds_table(p, p.line[0], B, cs, shm);
     const int ER = 1 << (p.D - 1);
     shm += (size_t)p.geom.T[0] * ER * 2 * sizeof(int);
-    PadSource ps{pad, p.tile_sub, p.geom, 2 * p.m,
+    PadSource ps{pad, p.tile_sub, p.geom, p.geom.taps,
                  (long long)p.nsub * (long long)padded_cells(p.geom, p.D)};
     const dim3 g((unsigned)(a.inner / B), (unsigned)a.K);
     const void *k = nullptr;

@@ -32,12 +32,14 @@ struct Geom {
     int Q[kMaxD];    // tile edge per axis (divides Nt)
     int T[kMaxD];    // tiles per axis = Nt / Q
     int ntiles;      // prod T
+    int taps;        // stencil points per axis: 2m, or 2m + 2 with the wide stencil
+    int lo;          // stencil points before the node's cell: taps/2 - 1
 };
 
 // Cells of a tile extended by the (2m-1)-wide trailing halo of every axis.
 inline size_t padded_cells(const Geom &g, int D) {
     size_t c = 1;
-    for (int d = 0; d < D; ++d) c *= (size_t)(g.Q[d] + 2 * g.m - 1);
+    for (int d = 0; d < D; ++d) c *= (size_t)(g.Q[d] + g.taps - 1);
     return c;
 }
 
@@ -112,6 +114,7 @@ struct nfft_plan_s {
     double sigma;
     nfft_dtype dtype;
     int window;
+    int wide;             // (2m+2)-point stencil
     int max_block_nodes;
     nfft::Geom geom;
     int64_t G;            // prod Nt

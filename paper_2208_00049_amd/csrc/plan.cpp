@@ -88,49 +88,49 @@ bool factor_line(int L, FftLine &fl) {
 }
 
 // LDS of the interpolation kernel: tile + halo plus the staged node chunk.
-size_t interp_lds(const int *Q, int D, int m, size_t cs) {
+size_t interp_lds(const int *Q, int D, int taps, size_t cs) {
     size_t t = cs;
-    for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + 2 * m - 1);
+    for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + taps - 1);
     return t + nfft::resample_static_lds(D, (int)cs / 2);
 }
 
 // LDS of the spreading kernel: fixed-point accumulators of the padded tile (one
 // int64 per component for c64, two for c128) plus the staged node chunk.
-size_t spread_lds(const int *Q, int D, int m, size_t cs) {
+size_t spread_lds(const int *Q, int D, int taps, size_t cs) {
     size_t t = (cs == 8 ? 16 : 32);
-    for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + 2 * m - 1);
+    for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + taps - 1);
     return t + nfft::resample_static_lds(D, (int)cs / 2);
 }
 
-bool valid_tile(int64_t Nt, int Q, int m) {
-    return Q >= 2 * m && Q > 0 && Nt % Q == 0 && Nt / Q >= 2;
+bool valid_tile(int64_t Nt, int Q, int taps) {
+    return Q >= taps && Q > 0 && Nt % Q == 0 && Nt / Q >= 2;
 }
 
-// Largest valid tile edge <= want (a divisor of Nt, >= 2m, >= 2 tiles).
-int pick_edge_down(int64_t Nt, int want, int m) {
-    for (int q = std::min<int64_t>(want, Nt / 2); q >= 2 * m; --q)
-        if (valid_tile(Nt, q, m)) return q;
+// Largest valid tile edge <= want (a divisor of Nt, >= taps, >= 2 tiles).
+int pick_edge_down(int64_t Nt, int want, int taps) {
+    for (int q = std::min<int64_t>(want, Nt / 2); q >= taps; --q)
+        if (valid_tile(Nt, q, taps)) return q;
     return 0;
 }
 
 // Valid tile edge closest to want: the largest one <= want, else the smallest one above.
-int pick_edge(int64_t Nt, int want, int m) {
-    const int q = pick_edge_down(Nt, want, m);
+int pick_edge(int64_t Nt, int want, int taps) {
+    const int q = pick_edge_down(Nt, want, taps);
     if (q) return q;
-    for (int v = std::max(want, 2 * m); v <= Nt / 2; ++v)
-        if (valid_tile(Nt, v, m)) return v;
+    for (int v = std::max(want, taps); v <= Nt / 2; ++v)
+        if (valid_tile(Nt, v, taps)) return v;
     return 0;
 }
 
-int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req, size_t budget,
+int choose_tiles(int D, const int64_t *Nt, int taps, nfft_dtype dt, const int *req, size_t budget,
                  int *Q) {
     const size_t cs = csize(dt);
     if (req && (req[0] || req[1] || req[2])) {
         for (int d = 0; d < D; ++d) {
-            if (!valid_tile(Nt[d], req[d], m)) return NFFT_ERR_ARG;
+            if (!valid_tile(Nt[d], req[d], taps)) return NFFT_ERR_ARG;
             Q[d] = req[d];
         }
-        return interp_lds(Q, D, m, cs) <= budget && spread_lds(Q, D, m, cs) <= budget
+        return interp_lds(Q, D, taps, cs) <= budget && spread_lds(Q, D, taps, cs) <= budget
                    ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
     }
     int want[3];
@@ -141,18 +141,18 @@ int choose_tiles(int D, const int64_t *Nt, int m, nfft_dtype dt, const int *req,
         want[1] = want[2] = 16;
     }
     for (int d = 0; d < D; ++d) {
-        Q[d] = pick_edge(Nt[d], std::max(want[d], 2 * m), m);
+        Q[d] = pick_edge(Nt[d], std::max(want[d], taps), taps);
         if (!Q[d]) return NFFT_ERR_UNSUPPORTED;
     }
     // shrink the largest edge until both resampling kernels fit in LDS
-    while (interp_lds(Q, D, m, cs) > budget || spread_lds(Q, D, m, cs) > budget) {
+    while (interp_lds(Q, D, taps, cs) > budget || spread_lds(Q, D, taps, cs) > budget) {
         int best = -1;
         for (int d = 0; d < D; ++d) {
-            const int q = pick_edge_down(Nt[d], Q[d] - 1, m);
+            const int q = pick_edge_down(Nt[d], Q[d] - 1, taps);
             if (q && (best < 0 || Q[d] > Q[best])) best = d;
         }
         if (best < 0) return NFFT_ERR_UNSUPPORTED;
-        Q[best] = pick_edge_down(Nt[best], Q[best] - 1, m);
+        Q[best] = pick_edge_down(Nt[best], Q[best] - 1, taps);
     }
     return NFFT_OK;
 }
@@ -224,7 +224,7 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
         if (N[d] < 2) return NFFT_ERR_ARG;
         if (N[d] % 2) return NFFT_ERR_UNSUPPORTED;
         const int64_t Nt = oversampled(N[d], sigma);
-        if (Nt < 4 * m) return NFFT_ERR_ARG;
+        if (Nt < 2 * (2 * m + (opts && opts->wide ? 2 : 0))) return NFFT_ERR_ARG;
         if (Nt > (dtype == NFFT_C64 ? 4096 : 2048)) return NFFT_ERR_UNSUPPORTED;
         G *= Nt;
         if (G >= ((int64_t)1 << 31)) return NFFT_ERR_UNSUPPORTED;
@@ -232,8 +232,10 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
     if (opts) {
         if (opts->window < NFFT_WINDOW_POLY || opts->window > NFFT_WINDOW_FULL) return NFFT_ERR_ARG;
         if (opts->window == NFFT_WINDOW_FULL && D == 3) return NFFT_ERR_UNSUPPORTED;
+        if (opts->wide != 0 && opts->wide != 1) return NFFT_ERR_ARG;
+        if (opts->wide && opts->window == NFFT_WINDOW_LINEAR) return NFFT_ERR_UNSUPPORTED;
         if (opts->max_block_nodes < 0) return NFFT_ERR_ARG;
-        for (int i = 0; i < 5; ++i)
+        for (int i = 0; i < 4; ++i)
             if (opts->reserved[i]) return NFFT_ERR_ARG;
         for (int d = 0; d < 3; ++d)
             if (opts->tile[d] < 0 || (d >= D && opts->tile[d] != 0)) return NFFT_ERR_ARG;
@@ -329,6 +331,8 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     p->sigma = sigma;
     p->dtype = dtype;
     p->window = opts ? opts->window : NFFT_WINDOW_POLY;
+    p->wide = opts ? opts->wide : 0;
+    const int taps = 2 * m + (p->wide ? 2 : 0);
     p->max_block_nodes = (opts && opts->max_block_nodes) ? opts->max_block_nodes : kDefaultBlockNodes;
     p->G = 1;
     p->NN = 1;
@@ -364,15 +368,17 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         p->lds_limit = dev_lds;
         int Q[3] = {1, 1, 1};
         const int *req = opts ? opts->tile : nullptr;
-        int trc = choose_tiles(D, p->Nt, m, dtype, req, kLdsBudget, Q);
+        int trc = choose_tiles(D, p->Nt, taps, dtype, req, kLdsBudget, Q);
         if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds > kLdsBudget)
-            trc = choose_tiles(D, p->Nt, m, dtype, req, (size_t)dev_lds - 1024, Q);
+            trc = choose_tiles(D, p->Nt, taps, dtype, req, (size_t)dev_lds - 1024, Q);
         if (trc != NFFT_OK) {
             rc = trc;
             goto fail;
         }
         p->geom.D = D;
         p->geom.m = m;
+        p->geom.taps = taps;
+        p->geom.lo = taps / 2 - 1;
         p->geom.ntiles = 1;
         for (int d = 0; d < kMaxD; ++d) {
             p->geom.Nt[d] = (int)p->Nt[d];
@@ -389,7 +395,7 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         TRY(hipMalloc(&p->twiddle[d], (size_t)p->Nt[d] * cs));
         p->line[d].tw = p->twiddle[d];
     }
-    TRY(hipMalloc(&p->coef, (size_t)D * 2 * m * Z * rs));
+    TRY(hipMalloc(&p->coef, (size_t)D * taps * Z * rs));
     TRY(hipMalloc(&p->key_start, (size_t)(p->nkeys + 1) * sizeof(int)));
     TRY(hipMalloc(&p->subs, (size_t)subs_cap * sizeof(int4)));
     TRY(hipMalloc(&counts, (size_t)(p->nkeys + 1) * sizeof(int)));
@@ -451,9 +457,9 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
             p->lin_S = (long long)m * (1LL << kLinearC[std::min(m, 8) - 1]) + 2;
             n = (size_t)D * p->lin_S;
         } else if (p->window == NFFT_WINDOW_TENSOR) {
-            n = (size_t)M * D * 2 * m;
+            n = (size_t)M * D * taps;
         } else {
-            n = (size_t)M * (D == 1 ? 2 * m : 4 * m * m);
+            n = (size_t)M * (D == 1 ? taps : taps * taps);
         }
         if (n > 0) {
             TRY(hipMalloc(&p->wtab, n * rs));

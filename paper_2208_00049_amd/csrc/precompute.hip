@@ -31,6 +31,15 @@ __device__ double window_hat_fp64(double u, double beta) {
     return s > 0.0 ? sinh(beta * s) / (M_PI * s) : beta / M_PI;
 }
 
+// The same Fourier transform on the whole line: for |u| > 1 its continuation
+// sin(beta sqrt(u^2-1)) / (pi sqrt(u^2-1)), sampled by the wide stencil.
+__device__ double window_hat_full_fp64(double u, double beta) {
+    const double q = 1.0 - u * u;
+    const double r = sqrt(fabs(q));
+    if (r == 0.0) return beta / M_PI;
+    return q > 0.0 ? sinh(beta * r) / (M_PI * r) : sin(beta * r) / (M_PI * r);
+}
+
 // Resampling-correction factors of one axis (paper, subsection "Resampling
 // Correction"): beta_tensor[n] = 1 / (m phi_Base(m n / Nt)), n in I_N, with
 // phi_Base(xi) = I0(sqrt(beta^2 - (2 pi xi)^2)).  Computed in FP64, stored in T.
@@ -51,19 +60,23 @@ __global__ void k_deconv_factors(int N, int Nt, int m, double beta, T *out) {
 // 1/2 - t)/m) by least squares.  The fit is done in the variable s = 2 zeta in
 // [-1, 1] with the thin QR factors of its Vandermonde matrix (qt = Q^T, Z x
 // Theta; r = R, Z x Z upper), then rescaled exactly by 2^z.  One thread per
-// (axis, tap); FP64 throughout, stored in T.
+// (axis, tap); FP64 throughout, stored in T.  With the wide stencil (taps =
+// 2m + 2, lo = m) tap t samples the untruncated window at (zeta + m + 1/2 - t)/m.
 template <typename T>
-__global__ void k_window_poly(int m, int Z, int Theta, const double *betas, const double *qt,
-                              const double *r, T *mu) {
+__global__ void k_window_poly(int m, int taps, int Z, int Theta, const double *betas,
+                              const double *qt, const double *r, T *mu) {
     const int t = threadIdx.x;
     const int axis = blockIdx.x;
-    if (t >= 2 * m) return;
+    if (t >= taps) return;
+    const int lo = taps / 2 - 1;
+    const bool wide = taps > 2 * m;
     const double beta = betas[axis];
     double c[32];
     for (int z = 0; z < Z; ++z) c[z] = 0.0;
     for (int v = 0; v < Theta; ++v) {
         const double zeta = -0.5 + (double)v / (double)(Theta - 1);
-        const double b = window_hat_fp64((zeta + (double)m - 0.5 - (double)t) / (double)m, beta);
+        const double u = (zeta + (double)lo + 0.5 - (double)t) / (double)m;
+        const double b = wide ? window_hat_full_fp64(u, beta) : window_hat_fp64(u, beta);
         for (int z = 0; z < Z; ++z) c[z] += qt[z * Theta + v] * b;
     }
     double sol[32];
@@ -74,7 +87,7 @@ __global__ void k_window_poly(int m, int Z, int Theta, const double *betas, cons
     }
     double scale = 1.0;
     for (int z = 0; z < Z; ++z) {
-        mu[((size_t)axis * 2 * m + t) * Z + z] = (T)(sol[z] * scale);
+        mu[((size_t)axis * taps + t) * Z + z] = (T)(sol[z] * scale);
         scale *= 2.0;
     }
 }
@@ -105,9 +118,9 @@ __device__ inline T poly_weight(const T *mu, int Z, T frac) {
 // out[(k D + d) 2m + t].  FULL (D <= 2): per sorted node the (2m)^D products
 // out[k (2m)^D + a 2m + b] = w_0[a] w_1[b] (1-D: the 2m weights).
 template <typename T, int D>
-__global__ void k_window_nodes(const NodeRec<T, D> *nodes, long long M, int m, const T *mu,
-                               int full, T *out) {
-    const int M2 = 2 * m, Z = 2 * m + 1;
+__global__ void k_window_nodes(const NodeRec<T, D> *nodes, long long M, int m, int taps,
+                               const T *mu, int full, T *out) {
+    const int M2 = taps, Z = 2 * m + 1;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (!full) {
         if (i >= M * D * M2) return;
@@ -163,11 +176,11 @@ hipError_t launch_window_poly(const nfft_plan_s &p, const double *qt, const doub
     // betas, qt and r live in one device scratch allocation owned by the caller
     const double *betas = r + Z * Z;
     if (p.dtype == NFFT_C64)
-        hipLaunchKernelGGL(k_window_poly<float>, dim3(p.D), dim3(64), 0, s, p.m, Z, Theta, betas,
-                           qt, r, (float *)p.coef);
+        hipLaunchKernelGGL(k_window_poly<float>, dim3(p.D), dim3(64), 0, s, p.m, p.geom.taps, Z,
+                           Theta, betas, qt, r, (float *)p.coef);
     else
-        hipLaunchKernelGGL(k_window_poly<double>, dim3(p.D), dim3(64), 0, s, p.m, Z, Theta, betas,
-                           qt, r, (double *)p.coef);
+        hipLaunchKernelGGL(k_window_poly<double>, dim3(p.D), dim3(64), 0, s, p.m, p.geom.taps, Z,
+                           Theta, betas, qt, r, (double *)p.coef);
     return hipGetLastError();
 }
 
@@ -190,12 +203,14 @@ hipError_t launch_window_tables(const nfft_plan_s &p, hipStream_t s) {
     if (p.window != NFFT_WINDOW_TENSOR && p.window != NFFT_WINDOW_FULL) return hipSuccess;
     if (p.M == 0) return hipSuccess;
     const int full = p.window == NFFT_WINDOW_FULL;
-    const long long per = full ? (p.D == 1 ? 2 * p.m : 4LL * p.m * p.m) : (long long)p.D * 2 * p.m;
+    const long long tp = p.geom.taps;
+    const long long per = full ? (p.D == 1 ? tp : tp * tp) : (long long)p.D * tp;
     const long long n = p.M * per;
     const dim3 g((unsigned)((n + 255) / 256));
 #define NFFT_WT(T, DD)                                                                            \
     hipLaunchKernelGGL((k_window_nodes<T, DD>), g, dim3(256), 0, s,                               \
-                       (const NodeRec<T, DD> *)p.nodes, (long long)p.M, p.m, (const T *)p.coef,  \
+                       (const NodeRec<T, DD> *)p.nodes, (long long)p.M, p.m, p.geom.taps,       \
+                       (const T *)p.coef,                                                         \
                        full, (T *)p.wtab)
     if (p.dtype == NFFT_C64) {
         if (p.D == 1) NFFT_WT(float, 1);

@@ -3,8 +3,9 @@
 
 namespace nfft {
 
+// over the stencil points per axis (2m, or 2m + 2 with the wide stencil)
 #define NFFT_DISPATCH_M(FN, T, D, ...)                     \
-    switch (p.m) {                                         \
+    switch (p.geom.taps / 2) {                             \
         case 1: return FN<T, D, 2>(__VA_ARGS__);           \
         case 2: return FN<T, D, 4>(__VA_ARGS__);           \
         case 3: return FN<T, D, 6>(__VA_ARGS__);           \
@@ -15,6 +16,7 @@ namespace nfft {
         case 8: return FN<T, D, 16>(__VA_ARGS__);          \
         case 9: return FN<T, D, 18>(__VA_ARGS__);          \
         case 10: return FN<T, D, 20>(__VA_ARGS__);         \
+        case 11: return FN<T, D, 22>(__VA_ARGS__);         \
         default: return hipErrorInvalidValue;              \
     }
 

@@ -42,24 +42,29 @@ template <typename T> struct WinParams {
     T beta[kMaxD];
     const T *tab;  // TENSOR / FULL: weights per sorted node; LINEAR: S samples per axis
     long long S;   // LINEAR table entries per axis
+    int m;         // window half-width (M2 = 2m, or 2m + 2 with the wide stencil)
 };
 
 // Window value of tap t for a node with offset frac (lane-owned coefficients cf;
-// lin: the axis's LINEAR table of S entries).
+// lin: the axis's LINEAR table of S entries).  Tap t sits at u = (frac + M2/2 -
+// 1 - t) / m; with the wide stencil (M2 = 2m + 2) the outer taps lie beyond
+// |u| = 1, where the untruncated window continues as sin(beta sqrt(u^2-1)) /
+// (pi sqrt(u^2-1)).
 template <typename T, int M2>
 __device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, const T *lin,
-                               long long S) {
+                               long long S, int m) {
     if (window == NFFT_WINDOW_POLY) {
+        // degree 2m; coefficients above it are zero (wide stencil: M2 = 2m + 2)
         const T z = frac - (T)0.5;
         T acc = cf[M2];
 #pragma unroll
         for (int k = M2 - 1; k >= 0; --k) acc = fma(acc, z, cf[k]);
         return acc;
     }
-    constexpr int m = M2 / 2;
+    constexpr int lo = M2 / 2 - 1;
     if (window == NFFT_WINDOW_LINEAR) {
         // kappa = |u| (S - 2), s = floor(kappa), alpha = kappa - s; |u| <= 1, so s + 1 < S
-        const double u = ((double)frac + (double)(m - 1 - t)) / (double)m;
+        const double u = ((double)frac + (double)(lo - t)) / (double)m;
         const double kappa = fabs(u) * (double)(S - 2);
         long long i = (long long)kappa;
         if (i > S - 2) i = S - 2;
@@ -67,8 +72,12 @@ __device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, c
         const T a = lin[i], b = lin[i + 1];
         return a + alpha * (b - a);
     }
-    const T u = (frac + (T)(m - 1 - t)) / (T)m;
+    const T u = (frac + (T)(lo - t)) / (T)m;
     const T s2 = (T)1 - u * u;
+    if (s2 < (T)0) {  // wide stencil only: beyond the truncation interval
+        const T r = sqrt(-s2);
+        return sin(beta * r) / ((T)M_PI * r);
+    }
     const T s = s2 > (T)0 ? sqrt(s2) : (T)0;
     return s > (T)0 ? sinh(beta * s) / ((T)M_PI * s) : beta / (T)M_PI;
 }
@@ -183,20 +192,33 @@ template <typename T, int D> struct Stage {
 // the polynomial coefficients of that tap per axis.
 template <typename T, int D, int M2> struct LaneWindow {
     T cf[D][M2 + 1];
-    __device__ void load(const T *__restrict__ coef, int li) {
+    // m: window half-width; the table holds 2m + 1 coefficients per (axis, tap)
+    __device__ void load(const T *__restrict__ coef, int li, int m) {
+        const int Z = 2 * m + 1;
 #pragma unroll
         for (int d = 0; d < D; ++d)
 #pragma unroll
-            for (int z = 0; z <= M2; ++z) cf[d][z] = coef[((size_t)d * M2 + li) * (M2 + 1) + z];
+            for (int z = 0; z <= M2; ++z)
+                cf[d][z] = z < Z ? coef[((size_t)d * M2 + li) * Z + z] : (T)0;
     }
 };
 
 // Weights of this lane's tap li along every axis for the node at sorted
 // position gk (TENSOR and FULL read the plan's per-node tables; FULL keeps the
 // last axis's factor at 1 because its row weights are whole products).
-template <typename T, int D, int M2>
+//
+// GW = false instantiates the polynomial window alone (the default mode, kept
+// free of the other modes' branches and registers); GW = true handles all modes.
+template <bool GW, typename T, int D, int M2>
 __device__ inline void node_weights(T *w, const LaneWindow<T, D, M2> &lw, const T *fr, long long gk,
                                     int li, int window, const WinParams<T> &wp) {
+    if constexpr (!GW) {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, NFFT_WINDOW_POLY, wp.beta[d], nullptr, 0,
+                                     wp.m);
+        return;
+    }
     if (window == NFFT_WINDOW_TENSOR) {
 #pragma unroll
         for (int d = 0; d < D; ++d) w[d] = wp.tab[(gk * D + d) * M2 + li];
@@ -208,16 +230,16 @@ __device__ inline void node_weights(T *w, const LaneWindow<T, D, M2> &lw, const 
 #pragma unroll
         for (int d = 0; d < D; ++d)
             w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, window, wp.beta[d], wp.tab + d * wp.S,
-                                     wp.S);
+                                     wp.S, wp.m);
     }
 }
 
 // Row weights of a 2-D node: the weights of axis 0 broadcast from the group's
 // lanes, or, with FULL, the lane's own column of the node's (2m)^2 products.
-template <typename T, int M2>
+template <bool GW, typename T, int M2>
 __device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, int gbase, int window,
                                       const WinParams<T> &wp) {
-    if (window == NFFT_WINDOW_FULL) {
+    if (GW && window == NFFT_WINDOW_FULL) {
 #pragma unroll
         for (int a = 0; a < M2; ++a) w0[a] = wp.tab[(gk * M2 + a) * M2 + li];
     } else {
@@ -225,7 +247,7 @@ __device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, in
     }
 }
 
-template <typename T, int D, int M2>
+template <typename T, int D, int M2, bool GW>
 __global__ void __launch_bounds__(kResampleThreads)
     k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
@@ -297,7 +319,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
     LaneWindow<T, D, M2> lw;
-    lw.load(coef, li);
+    lw.load(coef, li, wp.m);
 
     for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
         const int n = min(CH, sp.z - c0);
@@ -338,7 +360,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 fr[d] = st.fr[d][ks];
             }
             const long long gk = c0 + ks;  // sorted position of the node
-            node_weights<T, D, M2>(w, lw, fr, gk, li, window, wp);
+            node_weights<GW, T, D, M2>(w, lw, fr, gk, li, window, wp);
             T ar = (T)0, ai = (T)0;
             if constexpr (D == 1) {
                 const C v = tile[l[0] + li];
@@ -346,7 +368,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 ai = w[0] * v.y;
             } else if constexpr (D == 2) {
                 T w0[M2];
-                row_weights_2d<T, M2>(w0, w[0], gk, li, gbase, window, wp);
+                row_weights_2d<GW, T, M2>(w0, w[0], gk, li, gbase, window, wp);
                 const C *row = tile + l[0] * P[1] + l[1] + li;
 #pragma unroll
                 for (int a = 0; a < M2; ++a) {
@@ -438,7 +460,7 @@ template <> struct FixedPoint<double> {
 // the tile extended by the (2m-1)-wide trailing halo, in LDS, and writes that
 // padded tile to its own slot of the scratch buffer.  Every node's stencil lies
 // inside the padded tile, so the tap loops carry no bounds tests.
-template <typename T, int D, int M2>
+template <typename T, int D, int M2, bool GW>
 __global__ void __launch_bounds__(kResampleThreads)
     k_spread(cplx<T> *__restrict__ pad, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
@@ -477,7 +499,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
     LaneWindow<T, D, M2> lw;
-    lw.load(coef, li);
+    lw.load(coef, li, wp.m);
 
     // Stage the chunk of nodes [c0, c0 + n) into LDS: all global loads of the
     // thread's nodes are issued before the first one is waited for (indices are
@@ -555,7 +577,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 fr[d] = st.fr[d][ks];
             }
             const long long gk = c0 + ks;  // sorted position of the node
-            node_weights<T, D, M2>(w, lw, fr, gk, li, window, wp);
+            node_weights<GW, T, D, M2>(w, lw, fr, gk, li, window, wp);
             // the lane's tap along the last axis, with the value and the scale folded in
             const T ws = valid ? w[D - 1] * scale : (T)0;
             const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
@@ -563,7 +585,7 @@ __global__ void __launch_bounds__(kResampleThreads)
                 FP::add(acc + SL * (l[0] + li), pr, pi);
             } else if constexpr (D == 2) {
                 T w0[M2];
-                row_weights_2d<T, M2>(w0, w[0], gk, li, gbase, window, wp);
+                row_weights_2d<GW, T, M2>(w0, w[0], gk, li, gbase, window, wp);
                 unsigned long long *ap = acc + SL * (l[0] * P[1] + l[1] + li);
                 const int rs = SL * P[1];
 #pragma unroll
@@ -721,6 +743,7 @@ template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
         wp.beta[d] = d < p.D ? (T)(M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d])) : (T)0;
     wp.tab = (const T *)p.wtab;
     wp.S = p.lin_S;
+    wp.m = p.m;
     return wp;
 }
 
@@ -728,9 +751,11 @@ template <typename T, int D, int M2>
 hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
     const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
-    hipError_t e = allow_lds(k_interp<T, D, M2>, shm, static_lds<T, D>());
+    const bool gw = p.window != NFFT_WINDOW_POLY;
+    auto kern = gw ? k_interp<T, D, M2, true> : k_interp<T, D, M2, false>;
+    hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_interp<T, D, M2>), dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
+    hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
                        (long long)p.G, (long long)p.M);
@@ -750,9 +775,11 @@ hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStr
             // window maximum psi_hat_Base(0) = sinh(beta)/pi, with margin for the polynomial fit
             wprod *= 1.5 * sinh(beta) / M_PI;
         }
-        hipError_t e = allow_lds(k_spread<T, D, M2>, shm, static_lds<T, D>());
+        const bool gw = p.window != NFFT_WINDOW_POLY;
+        auto kern = gw ? k_spread<T, D, M2, true> : k_spread<T, D, M2, false>;
+        hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_spread<T, D, M2>), dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
+        hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
                            (cplx<T> *)pad, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                            p.subs, (const T *)p.coef, p.window, win_params<T>(p), (T)wprod,
                            (const cplx<T> *)fhat, pstride, (long long)p.M);

@@ -29,10 +29,12 @@ class Plan:
     precomputation options); ``max_block_nodes``: cap on nodes per resampling
     work item; ``tune``: if > 0 (and no tile is given), the library's autotuner
     picks the tiles, timing each candidate ``tune`` times (``tuned_ms`` then
-    holds the chosen plan's forward + adjoint milliseconds).
+    holds the chosen plan's forward + adjoint milliseconds); ``wide``: the (2m+2)-point
+    stencil with the untruncated window.
     """
 
-    def __init__(self, x, N, m=4, sigma=2.0, tile=None, window="poly", max_block_nodes=0, tune=0):
+    def __init__(self, x, N, m=4, sigma=2.0, tile=None, window="poly", max_block_nodes=0, tune=0,
+                 wide=False):
         if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
             raise TypeError("x must be a CUDA (HIP) tensor")
         N = tuple(int(v) for v in N)
@@ -61,6 +63,7 @@ class Plan:
                 opts.tile[d] = int(q)
         opts.window = _lib.WINDOWS[window]
         opts.max_block_nodes = int(max_block_nodes)
+        opts.wide = int(bool(wide))
         Narr = (ctypes.c_int64 * self.D)(*N)
         handle = ctypes.c_void_p()
         self.tuned_ms = None

@@ -73,6 +73,13 @@ def test_option_errors(lib):
     o = _lib.Options()
     o.tile[2] = 8  # axis beyond D
     assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -1
+    o = _lib.Options()
+    o.wide = 2
+    assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -1
+    o = _lib.Options()
+    o.wide = 1
+    o.window = _lib.NFFT_WINDOW_LINEAR  # the table does not reach beyond |u| = 1
+    assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -2
 
 
 def test_null_plan_calls(lib):

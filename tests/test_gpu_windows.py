@@ -66,3 +66,40 @@ def test_linear_matches_oracle(device, N, M, m, sigma, dt):
     if (m, sigma) in NDFT_GATE:
         gate = NDFT_GATE[(m, sigma)] + tol
         assert rel2(fg.cpu().numpy(), ndft.ndft_forward(xs, f)) < 2 * gate
+
+
+# 3-D: the padded spreading tile (tile + 2m+1 halo, 16 B per cell in c64) must fit in LDS,
+# which needs a tile edge of 10..12 at m = 4: Ntilde = 48 allows 12
+WIDE = [((256,), 512, 4, 2.0, "c128"), ((64, 64), 5000, 4, 2.0, "c64"),
+        ((48, 64), 3000, 3, 2.0, "c128"), ((24, 24, 24), 3000, 4, 2.0, "c64"),
+        ((32, 32), 2000, 6, 2.0, "c128")]
+
+
+@pytest.mark.parametrize("window", ["poly", "direct"])
+@pytest.mark.parametrize("N,M,m,sigma,dt", WIDE)
+def test_wide_stencil_matches_oracle(device, window, N, M, m, sigma, dt):
+    x = wl.uniform_nodes(M, len(N), config=63, stream=0)
+    f = wl.cn01(N, config=63, stream=1)
+    fh = wl.cn01((M,), config=63, stream=2)
+    p, xs = make_plan(device, x, N, m, sigma, dt, window=window, wide=True)
+    fg = p.forward(to_dev(f, dt, device)).cpu().numpy()
+    yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    print("wide", window, N, m, dt, flush=True)
+    tol = e2e_tol(N, sigma, m, dt) * (30 if window == "direct" and dt == "c64" else 1)
+    assert rel2(fg, na.forward(xs, f, m, sigma, window=window, wide=True)) < tol
+    assert rel2(yg, na.adjoint(xs, fh, N, m, sigma, window=window, wide=True)) < tol
+
+
+@pytest.mark.parametrize("m", [3, 4])
+def test_wide_stencil_accuracy_ordering_on_gpu(device, m):
+    """2m points < 2m+2 points (untruncated window) < 2(m+1) points, against the NDFT."""
+    N, M = (48, 64), 3000
+    x = wl.uniform_nodes(M, 2, config=64, stream=0)
+    f = wl.cn01(N, config=64, stream=1)
+    errs = []
+    for mm, wide in [(m, False), (m, True), (m + 1, False)]:
+        p, xs = make_plan(device, x, N, mm, 2.0, "c128", wide=wide)
+        errs.append(rel2(p.forward(to_dev(f, "c128", device)).cpu().numpy(),
+                         ndft.ndft_forward(xs, f)))
+    print("ordering", m, errs, flush=True)
+    assert errs[2] < errs[1] < errs[0]
