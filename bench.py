@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--sigma", type=float, default=2.0)
     ap.add_argument("--window", default="poly", choices=["poly", "direct", "tensor", "linear", "full"],
                     help="window evaluation (the paper's precomputation options)")
+    ap.add_argument("--wide", action="store_true",
+                    help="(2m+2)-point stencil with the untruncated window")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
@@ -385,7 +387,7 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    plan = Plan(xt, w["N"], m=args.m, sigma=args.sigma, window=args.window)
+    plan = Plan(xt, w["N"], m=args.m, sigma=args.sigma, window=args.window, wide=args.wide)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
@@ -430,7 +432,7 @@ def main():
     ach = algo[dominant] / (dom_ms * 1e-3) / 1e9
     traffic = None
     kname = (STAGE_KERNEL.get((w["D"], args.dtype), {}).get(dominant)
-             if args.m == 4 and args.window == "poly" else None)
+             if args.m == 4 and args.window == "poly" and not args.wide else None)
     if kname:
         traffic = stored_traffic(args.workload, args.dtype, kname)
     roofline = {"bound": "hbm", "kernel": kname or dominant, "achieved": round(ach, 1),
@@ -447,7 +449,7 @@ def main():
                    "sigma": args.sigma, "nodes": w["nodes"],
                    "complex": "complex64" if args.dtype == "c64" else "complex128",
                    "Ntilde": list(info["Ntilde"]), "tile": list(info["tile"]),
-                   "window": args.window},
+                   "window": args.window, "stencil": "2m+2" if args.wide else "2m"},
         "plan_ms": round(plan_ms, 2),
         "roofline": roofline,
         "kernels": kernels,
@@ -456,7 +458,8 @@ def main():
     if not args.profile_only:
         # FP32 result against FP64 on the same GPU (same FP32-rounded nodes and inputs)
         if args.dtype == "c64":
-            p64 = Plan(xt.double(), w["N"], m=args.m, sigma=args.sigma, window=args.window)
+            p64 = Plan(xt.double(), w["N"], m=args.m, sigma=args.sigma, window=args.window,
+                       wide=args.wide)
             f64 = p64.forward(ft.to(torch.complex128))
             y64 = p64.adjoint(fht.to(torch.complex128))
             fwd_err = (torch.linalg.norm(fout.to(torch.complex128) - f64) / torch.linalg.norm(f64)).item()
