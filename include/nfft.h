@@ -11,7 +11,8 @@
  *   adjoint (type 1, Algorithm 2 "Adjoint NFFT") approximates
  *       y_n    = sum_j fhat_j exp(+2 pi i n . x_j),         n in I_N
  *
- * with I_N the centred index set (n_d = -N_d/2 .. N_d/2-1, N_d even), an
+ * with I_N the centred index set (n_d = -floor(N_d/2) .. N_d - 1 - floor(N_d/2): for even
+ * N_d -N_d/2 .. N_d/2-1, for odd N_d -(N_d-1)/2 .. (N_d-1)/2), an
  * oversampled grid Ntilde_d ~= sigma N_d, and a Kaiser-Bessel window truncated to
  * 2m grid points per axis.  Both are computed as resampling correction
  * (deconvolution), unnormalised oversampled FFT and window resampling
@@ -24,7 +25,7 @@
  *          NFFT_C128.  Any real value is accepted; nodes are taken modulo 1
  *          (the transform is 1-periodic in x).
  *   f, y   prod(N) complex values (interleaved re, im), storage index
- *          i_d = n_d + N_d/2 (centred).
+ *          i_d = n_d + floor(N_d/2) (centred).
  *   fhat   M complex values in the caller's node order.
  *
  * Ownership: the caller owns x, f, fhat and y.  A plan copies what it needs
@@ -59,7 +60,7 @@ typedef enum {
 enum {
     NFFT_OK = 0,
     NFFT_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, sigma <= 1, ...) */
-    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (odd N, D > 3, ...) */
+    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (D > 3, ...) */
     NFFT_ERR_NOMEM = -3,       /* device allocation failed */
     NFFT_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch failure, ...) */
     NFFT_ERR_NODES = -5        /* a node coordinate is NaN or infinite */
@@ -99,7 +100,7 @@ typedef struct {
  * Create a plan (Algorithm 1/2 inputs D, m, N, Ntilde and the nodes).
  *   out    receives the plan handle (unchanged on error)
  *   D      1, 2 or 3
- *   N      host array of D even sizes >= 2
+ *   N      host array of D sizes >= 2 (even or odd)
  *   M      number of nodes, >= 0 (M = 0 is allowed)
  *   x      device pointer to the nodes (may be NULL when M == 0)
  *   m      window half-width, 1..10 (the range the paper studies is 3..10)

@@ -34,7 +34,8 @@ template <typename C> __device__ inline C cmul_si(C a, int s) {
 }
 
 // Position on the oversampled axis of the r-th entry of the centred index set
-// I_N (n = r - N/2), i.e. (n mod Nt): r < N/2 -> Nt - N/2 + r, else r - N/2.
+// I_N (n = r - floor(N/2), also for odd N), i.e. (n mod Nt):
+// r < floor(N/2) -> Nt - floor(N/2) + r, else r - floor(N/2).
 __host__ __device__ inline int band_pos(int r, int N, int Nt) {
     return r < N / 2 ? Nt - N / 2 + r : r - N / 2;
 }

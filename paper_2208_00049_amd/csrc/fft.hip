@@ -219,11 +219,11 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
                 if (dst[u] >= 0) lds[dst[u]] = v[u];
         }
     }
-    if (a.in_band_N) {
+    if (a.in_band_N) {  // rows ceil(N/2) .. L - floor(N/2) - 1 hold no n of I_N
         const int nz = L - nin;
         for (int idx = tid; idx < nz * B; idx += nthr) {
             const int bb = idx & (B - 1), r = idx >> lgB;
-            lds[bb * LP + nin / 2 + r] = zero;
+            lds[bb * LP + (nin - nin / 2) + r] = zero;
         }
     }
     __syncthreads();
@@ -446,8 +446,9 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
 #pragma unroll
             for (int j = 0; j < KM; ++j) {
                 const int k = t + j * fl.tpl;
+                // n = r - floor(N/2) sits at k = n mod L: n >= 0 for k < ceil(N/2)
                 int r = -1;
-                if (k < Nl / 2) r = k + Nl / 2;
+                if (k < Nl - Nl / 2) r = k + Nl / 2;
                 else if (k >= L - Nl / 2 && k < L) r = k - (L - Nl / 2);
                 const int rr = r >= 0 ? r : 0;
                 const C x = src[frow + rr];

@@ -222,7 +222,6 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
     int64_t G = 1;
     for (int d = 0; d < D; ++d) {
         if (N[d] < 2) return NFFT_ERR_ARG;
-        if (N[d] % 2) return NFFT_ERR_UNSUPPORTED;
         const int64_t Nt = oversampled(N[d], sigma);
         if (Nt < 2 * (2 * m + (opts && opts->wide ? 2 : 0))) return NFFT_ERR_ARG;
         if (Nt > (dtype == NFFT_C64 ? 4096 : 2048)) return NFFT_ERR_UNSUPPORTED;

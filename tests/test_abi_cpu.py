@@ -53,7 +53,7 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     (dict(D=0), -1), (dict(D=4, N=(8, 8, 8, 8)), -2), (dict(N=None), -1),
     (dict(M=-1), -1), (dict(M=5, x=None), -1), (dict(m=0, x=FAKE), -1), (dict(m=11, x=FAKE), -2),
     (dict(sigma=1.0, x=FAKE), -1), (dict(sigma=float("nan"), x=FAKE), -1),
-    (dict(dtype=7, x=FAKE), -1), (dict(N=(63, 64), x=FAKE), -2), (dict(N=(1, 64), x=FAKE), -1),
+    (dict(dtype=7, x=FAKE), -1), (dict(D=4, N=(8, 8, 8, 8), x=FAKE), -2), (dict(N=(1, 64), x=FAKE), -1),
     (dict(N=(4, 64), m=4, x=FAKE), -1), (dict(N=(4096, 64), x=FAKE), -2),
 ])
 def test_argument_errors_without_gpu(lib, kw, code):
@@ -104,11 +104,11 @@ def test_batch_and_tuner_argument_errors(lib):
     assert lib.nfft_batch_create(ctypes.byref(out), 2, plans, 0) == -1
     N = (ctypes.c_int64 * 2)(64, 64)
     ms = ctypes.c_double()
-    # sigma <= 1, odd N, reps < 1
+    # sigma <= 1, D > 3, reps < 1
     assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(1.0), 0,
                                       None, 2, None, ctypes.byref(ms)) == -1
-    Nodd = (ctypes.c_int64 * 2)(63, 64)
-    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, Nodd, 0, None, 4, ctypes.c_double(2.0),
+    N4 = (ctypes.c_int64 * 4)(8, 8, 8, 8)
+    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 4, N4, 0, None, 4, ctypes.c_double(2.0),
                                       0, None, 2, None, ctypes.byref(ms)) == -2
     assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(2.0), 0,
                                       None, 0, None, ctypes.byref(ms)) == -1

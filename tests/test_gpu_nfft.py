@@ -247,3 +247,21 @@ def test_explicit_tiles_and_small_blocks(device):
             ref = (fg, yg)
         else:
             assert rel2(fg, ref[0]) < 1e-13 and rel2(yg, ref[1]) < 1e-13, kw
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M", [((25,), 300), ((23, 31), 3000), ((9, 10, 11), 2000),
+                                 ((33, 64), 4000)])
+def test_odd_sizes(device, dt, N, M):
+    """Odd N (n = -(N-1)/2 .. (N-1)/2): the zero-pad band and the crop follow floor(N/2)."""
+    m, sigma = 4, 2.0
+    x = wl.uniform_nodes(M, len(N), config=85, stream=0)
+    f = wl.cn01(N, config=85, stream=1)
+    fh = wl.cn01((M,), config=85, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh)
+    print("odd", N, dt, p.info(), flush=True)
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(fg, na.forward(xs, f, m, sigma)) < tol
+    assert rel2(yg, na.adjoint(xs, fh, N, m, sigma)) < tol
+    gate = NDFT_GATE[(m, sigma)] + tol
+    assert rel2(fg, ndft.ndft_forward(xs, f)) < gate

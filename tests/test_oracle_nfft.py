@@ -199,3 +199,14 @@ def test_wide_stencil_is_a_plain_sum_on_tiny_input():
         want += na.window_hat_full((y - l) / m, beta) * g[l % 16]
     got = na.resample_forward(x, g, N, m, Nt, window="direct", wide=True)[0]
     assert abs(got - want) < 1e-12 * abs(want)
+
+
+@pytest.mark.parametrize("N", [(25,), (23, 31), (9, 10, 11)])
+def test_odd_sizes_against_ndft(N):
+    """Odd N (n = -(N-1)/2 .. (N-1)/2, subsection "NDFT"): the NFFT oracle meets the same gate."""
+    D = len(N)
+    x = wl.uniform_nodes(400, D, config=73, stream=0)
+    f = wl.cn01(N, config=73, stream=1)
+    fh = wl.cn01((400,), config=73, stream=2)
+    assert _rel2(na.forward(x, f, 4, 2.0), ndft.ndft_forward(x, f)) < 1e-6
+    assert _rel2(na.adjoint(x, fh, N, 4, 2.0), ndft.ndft_adjoint(x, fh, N)) < 1e-6
