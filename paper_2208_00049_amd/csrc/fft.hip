@@ -30,6 +30,26 @@ __device__ inline int xcd_block(int b, int nblocks) {
     return (b % kNumXcd) * (full / kNumXcd) + b / kNumXcd;
 }
 
+// Copy the twiddle table (L values) into LDS: every thread issues its loads,
+// up to eight at a time, before it writes any of them.
+template <typename C>
+__device__ inline void copy_table(C *dst, const C *__restrict__ src, int L, int tid, int nthr) {
+    constexpr int U = 8;
+    for (int base = 0; base < L; base += U * nthr) {
+        C v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * nthr + tid;
+            v[u] = src[j < L ? j : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * nthr + tid;
+            if (j < L) dst[j] = v[u];
+        }
+    }
+}
+
 template <typename C, int R> struct Dft;
 
 template <typename C> struct Dft<C, 2> {
@@ -192,8 +212,7 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
 
     // twiddle table after the B lines (when it fits)
     C *twl = lds + B * LP;
-    if (fl.tw_lds)
-        for (int j = tid; j < L; j += nthr) twl[j] = ((const C *)fl.tw)[j];
+    if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, nthr);
     // load the band (or the whole lines): U loads per thread in flight at once
     const int nin = a.in_band_N ? a.in_band_N : L;
     {
@@ -298,8 +317,7 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
         rng[2 * idx] = ps.tile_sub[q];
         rng[2 * idx + 1] = ps.tile_sub[q + 1];
     }
-    if (fl.tw_lds)
-        for (int j = tid; j < L; j += nthr) twl[j] = ((const C *)fl.tw)[j];
+    if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, nthr);
     __syncthreads();
 
     const C *pad = (const C *)ps.pad + blockIdx.y * ps.cstride;
@@ -400,8 +418,7 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     const bool active = b < c.lines_per_block && line_id < c.nlines;
     C *line = lds + (b < c.lines_per_block ? b : 0) * LP;
     C *twl = lds + c.lines_per_block * LP;  // twiddle table after the lines (when it fits)
-    if (fl.tw_lds)
-        for (int j = tid; j < L; j += blockDim.x) twl[j] = ((const C *)fl.tw)[j];
+    if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, (int)blockDim.x);
     const int D = c.D;
     const T *declast = D == 1 ? dec0 : (D == 2 ? dec1 : dec2);
 

@@ -274,6 +274,35 @@ __global__ void __launch_bounds__(kResampleThreads)
             P[d] = g.Q[d] + M2 - 1;
         }
     }
+    // the first chunk's node loads go out before the tile copy, so that both
+    // latencies overlap (the chunk is written to LDS after the copy)
+    constexpr int SJ = (CH + kResampleThreads - 1) / kResampleThreads;
+    NodeRec<T, D> rec[SJ];
+    int pm[SJ];
+    auto load_chunk = [&](int c0, int n) {
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) {
+            const int node = c0 + min((int)threadIdx.x + j * kResampleThreads, n - 1);
+            rec[j] = nodes[node];
+            pm[j] = perm[node];
+        }
+    };
+    auto store_chunk = [&](int n) {
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) {
+            const int k = threadIdx.x + j * kResampleThreads;
+            if (k < n) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    st.l[d][k] = rec[j].o[d] - t0[d];
+                    st.fr[d][k] = rec[j].fr[d];
+                }
+                st.idx[k] = pm[j];
+            }
+        }
+    };
+    load_chunk(sp.y, min(CH, sp.z - sp.y));
+
     // copy the tile and its trailing halo into LDS, wrapping at the grid edge;
     // eight loads per thread are in flight before the first LDS write
     {
@@ -323,30 +352,9 @@ __global__ void __launch_bounds__(kResampleThreads)
 
     for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
         const int n = min(CH, sp.z - c0);
-        {
-            // all loads first (indices clamped into the item), then the LDS writes
-            constexpr int SJ = (CH + kResampleThreads - 1) / kResampleThreads;
-            NodeRec<T, D> rec[SJ];
-            int pm[SJ];
-#pragma unroll
-            for (int j = 0; j < SJ; ++j) {
-                const int node = c0 + min(threadIdx.x + j * kResampleThreads, n - 1);
-                rec[j] = nodes[node];
-                pm[j] = perm[node];
-            }
-#pragma unroll
-            for (int j = 0; j < SJ; ++j) {
-                const int k = threadIdx.x + j * kResampleThreads;
-                if (k < n) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        st.l[d][k] = rec[j].o[d] - t0[d];
-                        st.fr[d][k] = rec[j].fr[d];
-                    }
-                    st.idx[k] = pm[j];
-                }
-            }
-        }
+        // all loads first (indices clamped into the item), then the LDS writes
+        if (c0 > sp.y) load_chunk(c0, n);
+        store_chunk(n);
         __syncthreads();  // also completes the tile copy on the first chunk
         for (int base = wave * NPW; base < n; base += (kResampleThreads / 64) * NPW) {
             const int k = base + grp;
