@@ -132,12 +132,16 @@ template <typename C> struct Dft<C, 5> {
 
 // One Stockham pass on an LDS line; every thread of the workgroup calls it
 // (the barriers are workgroup-wide), `active` says whether this thread owns a line.
-template <typename C, int R>
-__device__ inline void stockham_pass(C *line, bool active, int L, int p, int t, int tpl,
-                                     const C *tw, int dir) {
+// One Stockham pass on an LDS line; every thread of the workgroup calls it
+// (the barriers are workgroup-wide), `active` says whether this thread owns a
+// line.  DIR (-1 forward, +1 adjoint) is a compile-time constant, so the
+// butterflies' multiplications by +-i fold; POW2 (L a power of two, so p is one
+// too) turns the index arithmetic into masks.
+template <typename C, int R, int DIR, bool POW2>
+__device__ inline void stockham_pass(C *line, bool active, int L, int p, int twstep, int t, int tpl,
+                                     const C *tw) {
     constexpr int NB = (8 + R - 1) / R;  // butterflies per thread when tpl = L / 8
     const int nbf = L / R;
-    const int twstep = L / (p * R);
     C x[NB][R];
     int kk[NB];
 #pragma unroll
@@ -145,7 +149,7 @@ __device__ inline void stockham_pass(C *line, bool active, int L, int p, int t, 
         const int i = t + q * tpl;
         kk[q] = 0;
         if (active && i < nbf) {
-            const int k = i % p;
+            const int k = POW2 ? (i & (p - 1)) : i % p;
             kk[q] = k;
 #pragma unroll
             for (int r = 0; r < R; ++r) x[q][r] = line[i + r * nbf];
@@ -153,10 +157,10 @@ __device__ inline void stockham_pass(C *line, bool active, int L, int p, int t, 
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     const C w = tw[r * k * twstep];
-                    x[q][r] = dir < 0 ? cmul(x[q][r], w) : cmulc(x[q][r], w);
+                    x[q][r] = DIR < 0 ? cmul(x[q][r], w) : cmulc(x[q][r], w);
                 }
             }
-            Dft<C, R>::run(x[q], dir);
+            Dft<C, R>::run(x[q], DIR);
         }
     }
     __syncthreads();
@@ -172,18 +176,23 @@ __device__ inline void stockham_pass(C *line, bool active, int L, int p, int t, 
     __syncthreads();
 }
 
-// tw: the line's twiddle table W^j, j < L, in LDS
-template <typename C>
-__device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, const C *tw, int dir) {
+// tw: the line's twiddle table W^j, j < L (LDS or global)
+template <typename C, int DIR, bool POW2>
+__device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, const C *tw) {
     int p = 1;
     for (int s = 0; s < fl.npass; ++s) {
         const int R = fl.rad[s];
+        const int twstep = fl.L / (p * R);  // uniform
         switch (R) {
-            case 8: stockham_pass<C, 8>(line, active, fl.L, p, t, fl.tpl, tw, dir); break;
-            case 4: stockham_pass<C, 4>(line, active, fl.L, p, t, fl.tpl, tw, dir); break;
-            case 2: stockham_pass<C, 2>(line, active, fl.L, p, t, fl.tpl, tw, dir); break;
-            case 5: stockham_pass<C, 5>(line, active, fl.L, p, t, fl.tpl, tw, dir); break;
-            default: stockham_pass<C, 3>(line, active, fl.L, p, t, fl.tpl, tw, dir); break;
+            case 8: stockham_pass<C, 8, DIR, POW2>(line, active, fl.L, p, twstep, t, fl.tpl, tw); break;
+            case 4: stockham_pass<C, 4, DIR, POW2>(line, active, fl.L, p, twstep, t, fl.tpl, tw); break;
+            case 2: stockham_pass<C, 2, DIR, POW2>(line, active, fl.L, p, twstep, t, fl.tpl, tw); break;
+            case 5:
+                if constexpr (!POW2) stockham_pass<C, 5, DIR, POW2>(line, active, fl.L, p, twstep, t, fl.tpl, tw);
+                break;
+            default:
+                if constexpr (!POW2) stockham_pass<C, 3, DIR, POW2>(line, active, fl.L, p, twstep, t, fl.tpl, tw);
+                break;
         }
         p *= R;
     }
@@ -191,7 +200,7 @@ __device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, 
 
 // Strided axis pass: the workgroup owns B consecutive inner columns of one outer
 // position; rows are read and written B complex values at a time.
-template <typename T>
+template <typename T, int DIR, bool POW2>
 __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl, AxisPass a) {
     using C = cplx<T>;
     grid += blockIdx.y * a.cstride;  // channel
@@ -249,8 +258,8 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
 
     const int b = tid / fl.tpl, t = tid % fl.tpl;
     const bool active = b < B;
-    if (fl.tw_lds) line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, twl, a.dir);
-    else line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw, a.dir);
+    if (fl.tw_lds) line_fft<C, DIR, POW2>(lds + (active ? b : 0) * LP, active, t, fl, twl);
+    else line_fft<C, DIR, POW2>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw);
 
     const int nout = a.out_band_N ? a.out_band_N : L;
     for (int idx = tid; idx < nout * B; idx += nthr) {
@@ -266,9 +275,10 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
 // items' padded-tile values (the halo merge, with the same summation order as
 // the merge kernel).  The B columns of a workgroup lie in one tile column, so
 // the item ranges of the tiles along axis 0 are read into LDS once.
-template <typename T, int D>
+template <typename T, int D, bool POW2>
 __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftLine fl, AxisPass a,
                                                              PadSource ps) {
+    constexpr int DIR = +1;  // the adjoint's first pass
     using C = cplx<T>;
     grid += blockIdx.y * a.cstride;  // channel
     constexpr int ER = 1 << (D - 1);  // shifts along the axes after axis 0
@@ -387,8 +397,8 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
 
     const int b = tid / fl.tpl, t = tid % fl.tpl;
     const bool active = b < B;
-    if (fl.tw_lds) line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, twl, a.dir);
-    else line_fft<C>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw, a.dir);
+    if (fl.tw_lds) line_fft<C, DIR, POW2>(lds + (active ? b : 0) * LP, active, t, fl, twl);
+    else line_fft<C, DIR, POW2>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw);
 
     const int nout = a.out_band_N ? a.out_band_N : L;
     for (int idx = tid; idx < nout * B; idx += nthr) {
@@ -402,7 +412,7 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
 // mode 1: f -> grid; the line of outer position (i0, i1) in I_N gets
 // f[i0][i1][r] * beta_0[i0] beta_1[i1] beta_last[r] at (r - N/2) mod Nt, zeros
 // elsewhere.  mode 2: grid -> y, y[i0][i1][r] = line[(r - N/2) mod Nt] * factors.
-template <typename T>
+template <typename T, int DIR, bool POW2>
 __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T> *dst, FftLine fl,
                                                      ContigPass c, const T *dec0, const T *dec1,
                                                      const T *dec2) {
@@ -490,8 +500,8 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     }
     __syncthreads();
 
-    if (fl.tw_lds) line_fft<C>(line, active, t, fl, twl, c.dir);
-    else line_fft<C>(line, active, t, fl, (const C *)fl.tw, c.dir);
+    if (fl.tw_lds) line_fft<C, DIR, POW2>(line, active, t, fl, twl);
+    else line_fft<C, DIR, POW2>(line, active, t, fl, (const C *)fl.tw);
 
     if (active) {
         if (c.mode == 2) {
@@ -527,12 +537,15 @@ static hipError_t fft_axis_t(const nfft_plan_s &p, void *grid, const AxisPass &a
     size_t shm = 0;
     const FftLine fl = with_lds_table(p, p.line[a.axis], B, sizeof(cplx<T>), shm);
     const dim3 g((unsigned)(((a.inner + B - 1) / B) * a.outer_len), (unsigned)a.K);
+    const bool pow2 = (fl.L & (fl.L - 1)) == 0;
+    auto kern = a.dir < 0 ? (pow2 ? k_fft_strided<T, -1, true> : k_fft_strided<T, -1, false>)
+                          : (pow2 ? k_fft_strided<T, 1, true> : k_fft_strided<T, 1, false>);
     if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_strided<T>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fft_strided<T>, g, dim3(B * fl.tpl), shm, s, (cplx<T> *)grid, fl, a);
+    hipLaunchKernelGGL(kern, g, dim3(B * fl.tpl), shm, s, (cplx<T> *)grid, fl, a);
     return hipGetLastError();
 }
 
@@ -543,12 +556,15 @@ static hipError_t fft_contig_t(const nfft_plan_s &p, const void *src, void *dst,
     size_t shm = 0;
     const FftLine fl = with_lds_table(p, p.line[p.D - 1], B, sizeof(cplx<T>), shm);
     const dim3 g((unsigned)((c.nlines + B - 1) / B), (unsigned)c.K);
+    const bool pow2 = (fl.L & (fl.L - 1)) == 0;
+    auto kern = c.dir < 0 ? (pow2 ? k_fft_contig<T, -1, true> : k_fft_contig<T, -1, false>)
+                          : (pow2 ? k_fft_contig<T, 1, true> : k_fft_contig<T, 1, false>);
     if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_contig<T>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_fft_contig<T>, g, dim3(B * fl.tpl), shm, s, (const cplx<T> *)src,
+    hipLaunchKernelGGL(kern, g, dim3(B * fl.tpl), shm, s, (const cplx<T> *)src,
                        (cplx<T> *)dst, fl, c, (const T *)p.deconv[0], (const T *)p.deconv[1],
                        (const T *)p.deconv[2]);
     return hipGetLastError();
@@ -570,30 +586,23 @@ hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const Axi
     PadSource ps{pad, p.tile_sub, p.geom, p.geom.taps,
                  (long long)p.nsub * (long long)padded_cells(p.geom, p.D)};
     const dim3 g((unsigned)(a.inner / B), (unsigned)a.K);
-    const void *k = nullptr;
-    if (p.dtype == NFFT_C64) k = p.D == 2 ? (const void *)k_fft_axis0_from_pad<float, 2>
-                                          : (const void *)k_fft_axis0_from_pad<float, 3>;
-    else k = p.D == 2 ? (const void *)k_fft_axis0_from_pad<double, 2>
-                      : (const void *)k_fft_axis0_from_pad<double, 3>;
-    if (shm > 65536) {
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
+    const bool pow2 = (fl.L & (fl.L - 1)) == 0;
+#define NFFT_PAD_LAUNCH(T, DD)                                                                     \
+    {                                                                                              \
+        auto kern = pow2 ? k_fft_axis0_from_pad<T, DD, true> : k_fft_axis0_from_pad<T, DD, false>; \
+        if (shm > 65536) {                                                                         \
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),              \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
+            if (e != hipSuccess) return e;                                                         \
+        }                                                                                          \
+        hipLaunchKernelGGL(kern, g, dim3(B * fl.tpl), shm, s, (cplx<T> *)grid, fl, a, ps);         \
     }
     if (p.dtype == NFFT_C64) {
-        if (p.D == 2)
-            hipLaunchKernelGGL((k_fft_axis0_from_pad<float, 2>), g, dim3(B * fl.tpl), shm, s,
-                               (cplx<float> *)grid, fl, a, ps);
-        else
-            hipLaunchKernelGGL((k_fft_axis0_from_pad<float, 3>), g, dim3(B * fl.tpl), shm, s,
-                               (cplx<float> *)grid, fl, a, ps);
+        if (p.D == 2) NFFT_PAD_LAUNCH(float, 2) else NFFT_PAD_LAUNCH(float, 3)
     } else {
-        if (p.D == 2)
-            hipLaunchKernelGGL((k_fft_axis0_from_pad<double, 2>), g, dim3(B * fl.tpl), shm, s,
-                               (cplx<double> *)grid, fl, a, ps);
-        else
-            hipLaunchKernelGGL((k_fft_axis0_from_pad<double, 3>), g, dim3(B * fl.tpl), shm, s,
-                               (cplx<double> *)grid, fl, a, ps);
+        if (p.D == 2) NFFT_PAD_LAUNCH(double, 2) else NFFT_PAD_LAUNCH(double, 3)
     }
+#undef NFFT_PAD_LAUNCH
     return hipGetLastError();
 }
 

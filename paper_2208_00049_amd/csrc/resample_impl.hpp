@@ -428,38 +428,43 @@ __global__ void __launch_bounds__(kResampleThreads)
 //         overflow below 2^33 contributions per grid point).
 //   c128: c*s is split into hi = floor(c*s / 2^32) and lo = c*s - hi*2^32 in
 //         [0, 2^32), added to an int64 and a uint64 per component (96 bits).
-// The accumulators of a grid point are adjacent: [Re slots][Im slots].
+// The accumulators are planes of the padded tile (structure of arrays): plane
+// s holds slot s of every cell, so one atomic instruction of a wavefront (eight
+// nodes' rows of 2m consecutive cells) touches consecutive 8-byte words of one
+// plane and spreads over all LDS banks.  Planes: c64 [Re][Im]; c128 [Re hi][Re
+// lo][Im hi][Im lo].
 template <typename T> struct FixedPoint;
 
 template <> struct FixedPoint<float> {
     static constexpr int kSlots = 1;  // int64 slots per component
     static constexpr double kLimit = 1073741824.0;  // 2^30
-    // a: the grid point's accumulators; cr, ci: scaled contributions, |c| < 2^30
-    __device__ static inline void add(unsigned long long *a, float cr, float ci) {
+    // a: the cell's word in plane 0; ps: plane size (cells); cr, ci: scaled, |c| < 2^30
+    __device__ static inline void add(unsigned long long *a, int ps, float cr, float ci) {
         atomicAdd(a, (unsigned long long)(long long)(int)cr);
-        atomicAdd(a + 1, (unsigned long long)(long long)(int)ci);
+        atomicAdd(a + ps, (unsigned long long)(long long)(int)ci);
     }
-    __device__ static inline double read(const unsigned long long *a, int comp) {
-        return (double)(long long)a[comp];
+    __device__ static inline double read(const unsigned long long *a, int ps, int comp) {
+        return (double)(long long)a[(size_t)comp * ps];
     }
 };
 
 template <> struct FixedPoint<double> {
     static constexpr int kSlots = 2;
     static constexpr double kLimit = 4611686018427387904.0;  // 2^62
-    __device__ static inline void add1(unsigned long long *a, double v) {
+    __device__ static inline void add1(unsigned long long *a, int ps, double v) {
         const int hi = __double2int_rd(v * 2.3283064365386963e-10);  // floor(v / 2^32)
         const double rest = v - (double)hi * 4294967296.0;               // in [0, 2^32)
         const unsigned lo = __double2uint_rd(rest);
         atomicAdd(a, (unsigned long long)(long long)hi);
-        atomicAdd(a + 1, (unsigned long long)lo);
+        atomicAdd(a + ps, (unsigned long long)lo);
     }
-    __device__ static inline void add(unsigned long long *a, double cr, double ci) {
-        add1(a, cr);
-        add1(a + 2, ci);
+    __device__ static inline void add(unsigned long long *a, int ps, double cr, double ci) {
+        add1(a, ps, cr);
+        add1(a + 2 * (size_t)ps, ps, ci);
     }
-    __device__ static inline double read(const unsigned long long *a, int comp) {
-        return (double)(long long)a[2 * comp] * 4294967296.0 + (double)a[2 * comp + 1];
+    __device__ static inline double read(const unsigned long long *a, int ps, int comp) {
+        const unsigned long long *c = a + (size_t)2 * comp * ps;
+        return (double)(long long)c[0] * 4294967296.0 + (double)c[ps];
     }
 };
 
@@ -590,26 +595,26 @@ __global__ void __launch_bounds__(kResampleThreads)
             const T ws = valid ? w[D - 1] * scale : (T)0;
             const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
             if constexpr (D == 1) {
-                FP::add(acc + SL * (l[0] + li), pr, pi);
+                FP::add(acc + (l[0] + li), ptot, pr, pi);
             } else if constexpr (D == 2) {
                 T w0[M2];
                 row_weights_2d<GW, T, M2>(w0, w[0], gk, li, gbase, window, wp);
-                unsigned long long *ap = acc + SL * (l[0] * P[1] + l[1] + li);
-                const int rs = SL * P[1];
+                unsigned long long *ap = acc + (l[0] * P[1] + l[1] + li);
+                const int rs = P[1];
 #pragma unroll
-                for (int a = 0; a < M2; ++a) FP::add(ap + a * rs, w0[a] * pr, w0[a] * pi);
+                for (int a = 0; a < M2; ++a) FP::add(ap + a * rs, ptot, w0[a] * pr, w0[a] * pi);
             } else {
                 T w0[M2], w1[M2];
                 BcastAll<M2, 0, T>::run(w0, w[0], gbase);
                 BcastAll<M2, 0, T>::run(w1, w[1], gbase);
-                unsigned long long *ap = acc + SL * ((l[0] * P[1] + l[1]) * P[2] + l[2] + li);
-                const int rs1 = SL * P[2], rs0 = SL * P[1] * P[2];
+                unsigned long long *ap = acc + ((l[0] * P[1] + l[1]) * P[2] + l[2] + li);
+                const int rs1 = P[2], rs0 = P[1] * P[2];
 #pragma unroll
                 for (int a = 0; a < M2; ++a) {
                     const T ar = w0[a] * pr, ai = w0[a] * pi;
                     unsigned long long *rp = ap + a * rs0;
 #pragma unroll
-                    for (int b = 0; b < M2; ++b) FP::add(rp + b * rs1, w1[b] * ar, w1[b] * ai);
+                    for (int b = 0; b < M2; ++b) FP::add(rp + b * rs1, ptot, w1[b] * ar, w1[b] * ai);
                 }
             }
         }
@@ -620,8 +625,8 @@ __global__ void __launch_bounds__(kResampleThreads)
     const T inv = (T)(1.0 / (double)scale);
     C *out = pad + (size_t)blockIdx.x * ptot;
     for (int idx = threadIdx.x; idx < ptot; idx += kResampleThreads) {
-        const unsigned long long *ap = acc + SL * idx;
-        out[idx] = cmake<C>((T)FP::read(ap, 0) * inv, (T)FP::read(ap, 1) * inv);
+        const unsigned long long *ap = acc + idx;
+        out[idx] = cmake<C>((T)FP::read(ap, ptot, 0) * inv, (T)FP::read(ap, ptot, 1) * inv);
     }
 }
 
