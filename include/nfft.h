@@ -60,7 +60,7 @@ typedef enum {
 enum {
     NFFT_OK = 0,
     NFFT_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, sigma <= 1, ...) */
-    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (D > 3, ...) */
+    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (D > 4, ...) */
     NFFT_ERR_NOMEM = -3,       /* device allocation failed */
     NFFT_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch failure, ...) */
     NFFT_ERR_NODES = -5        /* a node coordinate is NaN or infinite */
@@ -80,12 +80,16 @@ enum {
                                20, 23, 24 for m = 1..8, 24 above), linear interpolation */
     NFFT_WINDOW_FULL = 4    /* the paper's FULL precomputation: per node all (2m)^D weight
                                products (the nonzeros of the sparse matrix B); D <= 2,
-                               D = 3 returns NFFT_ERR_UNSUPPORTED */
+                               D >= 3 returns NFFT_ERR_UNSUPPORTED */
 };
 
 typedef struct {
-    int tile[3];          /* tile edge per axis in grid points, 0 = automatic.  Must divide
-                             Ntilde_d, be >= 2m and leave >= 2 tiles per axis. */
+    int tile[4];          /* tile edge per axis in grid points, all 0 = automatic.  D <= 3:
+                             must divide Ntilde_d, be >= the stencil width and leave >= 2
+                             tiles per axis.  D = 4: must divide Ntilde_d; the spreading
+                             workgroup of a tile reads at most 81 tiles' nodes, the product
+                             over the axes of min(Ntilde_d/Q_d, 2 + (taps-2)/Q_d), else
+                             NFFT_ERR_UNSUPPORTED. */
     int window;           /* NFFT_WINDOW_POLY (default), _DIRECT, _TENSOR, _LINEAR or _FULL */
     int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
                              into items of at most this many), 0 = automatic (1024) */
@@ -93,13 +97,18 @@ typedef struct {
                              beyond its truncation interval (the alternative of subsection
                              "Window Size Considerations"); 0 (default): 2m points.  Not
                              available with NFFT_WINDOW_LINEAR. */
-    int reserved[4];      /* must be zero */
+    int reserved[3];      /* must be zero */
 } nfft_options;
 
 /*
  * Create a plan (Algorithm 1/2 inputs D, m, N, Ntilde and the nodes).
  *   out    receives the plan handle (unchanged on error)
- *   D      1, 2 or 3
+ *   D      1, 2, 3 or 4.  D <= 3 resamples through LDS tiles of the grid; D = 4
+ *          (whose tile plus stencil halo does not fit in LDS) interpolates from
+ *          the grid in device memory, one wavefront per node, and spreads
+ *          output-driven: each grid point is summed by one thread over the
+ *          nodes that reach it (no atomics, no scratch; reproducible bit for
+ *          bit by the same plan).
  *   N      host array of D sizes >= 2 (even or odd)
  *   M      number of nodes, >= 0 (M = 0 is allowed)
  *   x      device pointer to the nodes (may be NULL when M == 0)
@@ -231,13 +240,14 @@ int nfft_plan_grid(nfft_plan_t p, void **grid);
  * nfft_plan_timing waits for the last recorded event and returns, for the most
  * recent forward and adjoint call, the elapsed milliseconds of each stage:
  *   0 forward: resampling correction + zero pad + FFT along the last axis
- *   1 forward: FFT along axis 1 (3-D only)      2 forward: FFT along axis 0
+ *   1 forward: FFT along axis 1 (3-D; 4-D: axes 2 and 1, the last one
+ *              recorded is kept)            2 forward: FFT along axis 0
  *   3 forward: interpolation
  *   4 adjoint: spreading into the work items' padded tiles (1-D, 3-D: and
- *              the halo merge into the grid)
+ *              the halo merge into the grid; 4-D: straight into the grid)
  *   5 adjoint: FFT along axis 0 (2-D: reads the padded tiles and performs
  *              the halo merge on the way)
- *   6 adjoint: FFT along axis 1 (3-D)
+ *   6 adjoint: FFT along axis 1 (3-D; 4-D: axes 1 and 2, the last kept)
  *   7 adjoint: FFT along the last axis + crop + resampling correction
  * Stages a plan does not run report 0.  ms must hold NFFT_NUM_STAGES values.
  * Timing adds an event record per kernel; leave it off when timing whole calls.
@@ -255,7 +265,8 @@ int nfft_plan_timing(nfft_plan_t p, double *ms);
  *            complex values, device).
  *   stage 4 (spreading): reads fhat (`in`, M complex values, device) and
  *            writes the plan's padded tiles; in 1-D and 3-D also the halo
- *            merge into the plan's grid, as in nfft_adjoint.
+ *            merge into the plan's grid, as in nfft_adjoint (4-D: writes the
+ *            plan's grid).
  * Errors: NFFT_ERR_ARG for another stage, reps < 1 or a missing pointer
  * (when M > 0); NFFT_ERR_HIP for a failed launch or event.
  */

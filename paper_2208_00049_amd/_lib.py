@@ -38,9 +38,9 @@ STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "sp
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int * 3), ("window", ctypes.c_int),
+    _fields_ = [("tile", ctypes.c_int * 4), ("window", ctypes.c_int),
                 ("max_block_nodes", ctypes.c_int), ("wide", ctypes.c_int),
-                ("reserved", ctypes.c_int * 4)]
+                ("reserved", ctypes.c_int * 3)]
 
 
 class NfftError(RuntimeError):

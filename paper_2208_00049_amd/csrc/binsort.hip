@@ -177,7 +177,9 @@ hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int 
     switch (p.D) {
         case 1: f ? keys_t<float, 1>(p, x, keys, counts, bad, s) : keys_t<double, 1>(p, x, keys, counts, bad, s); break;
         case 2: f ? keys_t<float, 2>(p, x, keys, counts, bad, s) : keys_t<double, 2>(p, x, keys, counts, bad, s); break;
-        default: f ? keys_t<float, 3>(p, x, keys, counts, bad, s) : keys_t<double, 3>(p, x, keys, counts, bad, s); break;
+        case 3: f ? keys_t<float, 3>(p, x, keys, counts, bad, s) : keys_t<double, 3>(p, x, keys, counts, bad, s); break;
+        case 4: f ? keys_t<float, 4>(p, x, keys, counts, bad, s) : keys_t<double, 4>(p, x, keys, counts, bad, s); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -194,7 +196,9 @@ hipError_t launch_node_scatter(nfft_plan_s &p, const void *x, const int *keys, i
     switch (p.D) {
         case 1: f ? scatter_t<float, 1>(p, x, keys, cursor, s) : scatter_t<double, 1>(p, x, keys, cursor, s); break;
         case 2: f ? scatter_t<float, 2>(p, x, keys, cursor, s) : scatter_t<double, 2>(p, x, keys, cursor, s); break;
-        default: f ? scatter_t<float, 3>(p, x, keys, cursor, s) : scatter_t<double, 3>(p, x, keys, cursor, s); break;
+        case 3: f ? scatter_t<float, 3>(p, x, keys, cursor, s) : scatter_t<double, 3>(p, x, keys, cursor, s); break;
+        case 4: f ? scatter_t<float, 4>(p, x, keys, cursor, s) : scatter_t<double, 4>(p, x, keys, cursor, s); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -213,8 +213,16 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
     const int nchunk = (int)((a.inner + B - 1) / B);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int o = blk / nchunk;
-    const long long obase =
-        (long long)(a.outer_band_N ? band_pos(o, a.outer_band_N, a.outer_Nt) : o) * a.outer_stride;
+    long long obase = 0;
+    {
+        int rem = o;
+        for (int d = a.axis - 1; d >= 0; --d) {
+            const int id = rem % a.outer_n[d];
+            rem /= a.outer_n[d];
+            const int pos = a.outer_band[d] ? band_pos(id, a.outer_n[d], a.outer_Nt[d]) : id;
+            obase += (long long)pos * a.outer_stride[d];
+        }
+    }
     const long long inner = a.inner;
     const long long i0 = (long long)(blk - o * nchunk) * B;
     const C zero = cmake<C>((T)0, (T)0);
@@ -409,13 +417,16 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
 }
 
 // Last-axis pass on contiguous lines.  mode 0: grid -> grid over all lines.
-// mode 1: f -> grid; the line of outer position (i0, i1) in I_N gets
-// f[i0][i1][r] * beta_0[i0] beta_1[i1] beta_last[r] at (r - N/2) mod Nt, zeros
-// elsewhere.  mode 2: grid -> y, y[i0][i1][r] = line[(r - N/2) mod Nt] * factors.
+// mode 1: f -> grid; the line of outer position (i_0, .., i_{D-2}) in I_N gets
+// f[i_0]..[r] * beta_0[i_0] .. beta_last[r] at (r - floor(N/2)) mod Nt, zeros
+// elsewhere.  mode 2: grid -> y, y[i_0]..[r] = line[(r - floor(N/2)) mod Nt] * factors.
+template <typename T> struct DecPtrs {
+    const T *d[kMaxD];  // resampling-correction factors per axis
+};
+
 template <typename T, int DIR, bool POW2>
 __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T> *dst, FftLine fl,
-                                                     ContigPass c, const T *dec0, const T *dec1,
-                                                     const T *dec2) {
+                                                     ContigPass c, DecPtrs<T> dec) {
     using C = cplx<T>;
     src += blockIdx.y * c.src_cstride;  // channel
     dst += blockIdx.y * c.dst_cstride;
@@ -430,37 +441,32 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     C *twl = lds + c.lines_per_block * LP;  // twiddle table after the lines (when it fits)
     if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, (int)blockDim.x);
     const int D = c.D;
-    const T *declast = D == 1 ? dec0 : (D == 2 ? dec1 : dec2);
+    const T *declast = dec.d[D - 1];
 
-    int i0 = 0, i1 = 0;
-    if (D == 2) {
-        i0 = line_id;
-    } else if (D == 3) {
-        i0 = line_id / c.outer_len[1];
-        i1 = line_id - i0 * c.outer_len[1];
+    // outer indices i_0..i_{D-2} of the line (the last fastest), its grid row and f row
+    int iv[kMaxD] = {0, 0, 0, 0};
+    {
+        int rem = line_id;
+        for (int d = D - 2; d >= 0; --d) {
+            iv[d] = rem % c.outer_len[d];
+            rem /= c.outer_len[d];
+        }
     }
     long long grow = 0, frow = 0;
     T fac = (T)1;
-    if (D >= 2) {
-        const int p0 = c.outer_band[0] ? band_pos(i0, c.N[0], c.Nt[0]) : i0;
-        if (D == 2) {
-            grow = (long long)p0 * L;
-            frow = (long long)i0 * c.N[1];
-        } else {
-            const int p1 = c.outer_band[1] ? band_pos(i1, c.N[1], c.Nt[1]) : i1;
-            grow = ((long long)p0 * c.Nt[1] + p1) * L;
-            frow = ((long long)i0 * c.N[1] + i1) * c.N[2];
-        }
-        if (c.mode != 0 && active) {
-            fac = dec0[i0];
-            if (D == 3) fac *= dec1[i1];
-        }
+    for (int d = 0; d < D - 1; ++d) {
+        const int pd = c.outer_band[d] ? band_pos(iv[d], c.N[d], c.Nt[d]) : iv[d];
+        grow = grow * c.Nt[d] + pd;
+        frow = frow * c.N[d] + iv[d];
+        if (c.mode != 0 && active) fac *= dec.d[d][iv[d]];
     }
+    grow *= L;
+    frow *= c.N[D - 1];
     // derivative channels (mode 1): channel d multiplies f by -2 pi i n_d
     const T twopi = (T)6.283185307179586476925;
     if (c.deriv && (int)blockIdx.y < D - 1) {
-        const int nd = blockIdx.y == 0 ? i0 - c.N[0] / 2 : i1 - c.N[1] / 2;
-        fac *= (T)nd * twopi;
+        const int d = blockIdx.y;
+        fac *= (T)(iv[d] - c.N[d] / 2) * twopi;
     }
     const int Nl = c.N[D - 1];
 
@@ -564,9 +570,10 @@ static hipError_t fft_contig_t(const nfft_plan_s &p, const void *src, void *dst,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
+    DecPtrs<T> dec;
+    for (int d = 0; d < kMaxD; ++d) dec.d[d] = (const T *)p.deconv[d];
     hipLaunchKernelGGL(kern, g, dim3(B * fl.tpl), shm, s, (const cplx<T> *)src,
-                       (cplx<T> *)dst, fl, c, (const T *)p.deconv[0], (const T *)p.deconv[1],
-                       (const T *)p.deconv[2]);
+                       (cplx<T> *)dst, fl, c, dec);
     return hipGetLastError();
 }
 

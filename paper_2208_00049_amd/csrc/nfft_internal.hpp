@@ -8,7 +8,7 @@
 
 namespace nfft {
 
-constexpr int kMaxD = 3;
+constexpr int kMaxD = 4;
 constexpr int kMaxRadixPasses = 16;
 constexpr int kResampleThreads = 256;  // workgroup size of the resampling kernels
 
@@ -35,6 +35,15 @@ struct Geom {
     int taps;        // stencil points per axis: 2m, or 2m + 2 with the wide stencil
     int lo;          // stencil points before the node's cell: taps/2 - 1
 };
+
+// Output-driven spreading (D = 4): a node binned in tile p - b along axis d can
+// reach tile p only for b <= 1 + (taps - 2) / Q_d; the candidate tiles per axis
+// are those r_d = min(T_d, 2 + (taps - 2) / Q_d) tiles.
+__host__ __device__ inline int gather_reach(const Geom &g, int d) {
+    const int r = 2 + (g.taps - 2) / g.Q[d];
+    return r < g.T[d] ? r : g.T[d];
+}
+constexpr int kGatherMaxTiles = 81;  // candidate tiles of one spreading workgroup (3^4)
 
 // Cells of a tile extended by the (2m-1)-wide trailing halo of every axis.
 inline size_t padded_cells(const Geom &g, int D) {
@@ -64,10 +73,14 @@ struct FftLine {
 struct AxisPass {
     int axis;
     int inner;            // prod of Nt over the axes after `axis` (> 1: strided pass)
-    int outer_len;        // number of outer (prefix) positions processed
-    int outer_band_N;     // 0: outer positions are 0..outer_len-1; else band of I_N (N = this)
-    int outer_Nt;         // oversampled size of the outer axis (band case)
-    long long outer_stride;  // elements between consecutive outer positions
+    int outer_len;        // number of outer (prefix) positions processed = prod outer_n
+    // the outer positions enumerate the axes 0..axis-1 (the last fastest): per axis
+    // outer_n[d] positions, either the band of I_N (outer_band[d], n_d -> n_d mod Nt)
+    // or 0..outer_n[d]-1; outer_stride[d] = elements between consecutive grid rows of d
+    int outer_n[kMaxD];
+    int outer_band[kMaxD];
+    int outer_Nt[kMaxD];
+    long long outer_stride[kMaxD];
     int in_band_N;        // 0: load the whole line; else only the band rows (others are zero)
     int out_band_N;       // 0: store the whole line; else only the band rows
     int lines_per_block;  // B, a power of two
@@ -91,8 +104,8 @@ struct ContigPass {
     int mode;             // 0 plain grid->grid, 1 f -> grid (deconv + pad), 2 grid -> y (crop + deconv)
     int D;
     int nlines;           // number of lines processed
-    int outer_len[2];     // lengths of the outer axes 0..D-2 as enumerated
-    int outer_band[2];    // per outer axis: 1 = band of I_N, 0 = full
+    int outer_len[kMaxD - 1];   // lengths of the outer axes 0..D-2 as enumerated
+    int outer_band[kMaxD - 1];  // per outer axis: 1 = band of I_N, 0 = full
     int N[kMaxD];
     int Nt[kMaxD];
     int lines_per_block;
@@ -126,7 +139,7 @@ struct nfft_plan_s {
 
     // device buffers
     void *grid = nullptr;          // G complex
-    void *deconv[nfft::kMaxD] = {nullptr, nullptr, nullptr};  // N_d reals (plan type)
+    void *deconv[nfft::kMaxD] = {};  // N_d reals (plan type)
     void *coef = nullptr;          // 2m x (2m+1) reals (plan type), window polynomial
     void *nodes = nullptr;         // M sorted NodeRec
     int *perm = nullptr;           // M: sorted position -> caller's node index
@@ -140,7 +153,7 @@ struct nfft_plan_s {
     void *grid_many = nullptr;
     void *pad_many = nullptr;
     int many_cap = 0;              // channels the two buffers hold
-    void *twiddle[nfft::kMaxD] = {nullptr, nullptr, nullptr};
+    void *twiddle[nfft::kMaxD] = {};
     nfft::FftLine line[nfft::kMaxD];
 
     // optional per-stage timing (events recorded around each kernel launch)

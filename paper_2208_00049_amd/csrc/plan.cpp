@@ -40,6 +40,10 @@ int64_t oversampled(int64_t N, double sigma) {
 }
 
 size_t csize(nfft_dtype t) { return t == NFFT_C64 ? 8 : 16; }
+
+// D <= 3 resamples through LDS tiles with padded-tile scratch; D = 4 works on
+// the grid directly (no scratch).
+bool tiled_resampling(const nfft_plan_s &p) { return p.D <= 3; }
 size_t rsize(nfft_dtype t) { return t == NFFT_C64 ? 4 : 8; }
 
 size_t node_rec_size(nfft_dtype t, int D) {
@@ -47,13 +51,15 @@ size_t node_rec_size(nfft_dtype t, int D) {
         switch (D) {
             case 1: return sizeof(NodeRec<float, 1>);
             case 2: return sizeof(NodeRec<float, 2>);
-            default: return sizeof(NodeRec<float, 3>);
+            case 3: return sizeof(NodeRec<float, 3>);
+            default: return sizeof(NodeRec<float, 4>);
         }
     }
     switch (D) {
         case 1: return sizeof(NodeRec<double, 1>);
         case 2: return sizeof(NodeRec<double, 2>);
-        default: return sizeof(NodeRec<double, 3>);
+        case 3: return sizeof(NodeRec<double, 3>);
+        default: return sizeof(NodeRec<double, 4>);
     }
 }
 
@@ -122,8 +128,37 @@ int pick_edge(int64_t Nt, int want, int taps) {
     return 0;
 }
 
+// D = 4 resamples from the grid in HBM (no LDS tile): a tile edge is any
+// divisor of Nt; the spreading workgroup reads the nodes of at most
+// kGatherMaxTiles tiles, which needs Q_d >= taps/2 on most axes.  Default: the
+// smallest divisor >= taps/2 (few candidate nodes per grid point).
+int choose_tiles_4d(const int64_t *Nt, int taps, const int *req, int *Q) {
+    const bool given = req && (req[0] || req[1] || req[2] || req[3]);
+    Geom g{};
+    g.taps = taps;
+    int nb = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (given) {
+            if (req[d] < 1 || Nt[d] % req[d]) return NFFT_ERR_ARG;
+            Q[d] = req[d];
+        } else {
+            Q[d] = (int)Nt[d];
+            for (int q = taps / 2; q < Nt[d]; ++q)
+                if (Nt[d] % q == 0) {
+                    Q[d] = q;
+                    break;
+                }
+        }
+        g.Q[d] = Q[d];
+        g.T[d] = (int)(Nt[d] / Q[d]);
+        nb *= gather_reach(g, d);
+    }
+    return nb <= kGatherMaxTiles ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
+}
+
 int choose_tiles(int D, const int64_t *Nt, int taps, nfft_dtype dt, const int *req, size_t budget,
                  int *Q) {
+    if (D == 4) return choose_tiles_4d(Nt, taps, req, Q);
     const size_t cs = csize(dt);
     if (req && (req[0] || req[1] || req[2])) {
         for (int d = 0; d < D; ++d) {
@@ -230,13 +265,13 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
     }
     if (opts) {
         if (opts->window < NFFT_WINDOW_POLY || opts->window > NFFT_WINDOW_FULL) return NFFT_ERR_ARG;
-        if (opts->window == NFFT_WINDOW_FULL && D == 3) return NFFT_ERR_UNSUPPORTED;
+        if (opts->window == NFFT_WINDOW_FULL && D >= 3) return NFFT_ERR_UNSUPPORTED;
         if (opts->wide != 0 && opts->wide != 1) return NFFT_ERR_ARG;
         if (opts->wide && opts->window == NFFT_WINDOW_LINEAR) return NFFT_ERR_UNSUPPORTED;
         if (opts->max_block_nodes < 0) return NFFT_ERR_ARG;
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 3; ++i)
             if (opts->reserved[i]) return NFFT_ERR_ARG;
-        for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < kMaxD; ++d)
             if (opts->tile[d] < 0 || (d >= D && opts->tile[d] != 0)) return NFFT_ERR_ARG;
     }
     return NFFT_OK;
@@ -365,7 +400,7 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         int dev_lds = 0;
         TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
         p->lds_limit = dev_lds;
-        int Q[3] = {1, 1, 1};
+        int Q[kMaxD] = {1, 1, 1, 1};
         const int *req = opts ? opts->tile : nullptr;
         int trc = choose_tiles(D, p->Nt, taps, dtype, req, kLdsBudget, Q);
         if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds > kLdsBudget)
@@ -446,7 +481,7 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     TRY(hipStreamSynchronize(s));
     p->nsub = host_nsub;
     if (host_bad) rc = NFFT_ERR_NODES;
-    if (rc == NFFT_OK && p->nsub > 0)
+    if (rc == NFFT_OK && p->nsub > 0 && tiled_resampling(*p))
         TRY(hipMalloc(&p->pad, (size_t)p->nsub * padded_cells(p->geom, D) * cs));
     if (rc == NFFT_OK && p->window != NFFT_WINDOW_POLY && p->window != NFFT_WINDOW_DIRECT) {
         // window tables of the precomputation modes (FP64 evaluation, plan type storage)
@@ -532,6 +567,21 @@ struct StageTimer {
 
 // forward FFT with the resampling correction fused into the first (last-axis)
 // pass; K channels: f at stride prod(N), grids at stride G
+// Outer structure of the strided pass along axis a: the axes before it, each
+// either its band of I_N (band = true) or its whole oversampled length.
+void set_outer(AxisPass &ap, const nfft_plan_s &p, int a, bool band) {
+    ap.outer_len = 1;
+    for (int d = 0; d < a; ++d) {
+        ap.outer_n[d] = band ? (int)p.N[d] : (int)p.Nt[d];
+        ap.outer_band[d] = band ? 1 : 0;
+        ap.outer_Nt[d] = (int)p.Nt[d];
+        long long st = 1;
+        for (int e = d + 1; e < p.D; ++e) st *= p.Nt[e];
+        ap.outer_stride[d] = st;
+        ap.outer_len *= ap.outer_n[d];
+    }
+}
+
 // deriv: K = D channels from one f, channel d with coefficients -2 pi i n_d f_n
 hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, hipStream_t s,
                        bool deriv = false) {
@@ -567,13 +617,7 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, h
         ap.axis = a;
         ap.inner = 1;
         for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
-        ap.outer_len = 1;
-        if (a == 1) {  // D == 3: outer axis 0 holds only the band rows
-            ap.outer_len = (int)p.N[0];
-            ap.outer_band_N = (int)p.N[0];
-            ap.outer_Nt = (int)p.Nt[0];
-            ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
-        }
+        set_outer(ap, p, a, true);  // the axes before a hold only their band rows
         ap.in_band_N = (int)p.N[a];
         ap.out_band_N = 0;
         ap.dir = -1;
@@ -581,7 +625,7 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, h
         ap.cstride = p.G;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
         {
-            StageTimer t(p, a == 1 ? 1 : 2, s);
+            StageTimer t(p, a == 0 ? 2 : 1, s);
             e = launch_fft_axis(p, grid, ap, s);
         }
         if (e != hipSuccess) return e;
@@ -601,13 +645,7 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pa
         ap.axis = a;
         ap.inner = 1;
         for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
-        ap.outer_len = 1;
-        if (a == 1) {
-            ap.outer_len = (int)p.N[0];
-            ap.outer_band_N = (int)p.N[0];
-            ap.outer_Nt = (int)p.Nt[0];
-            ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
-        }
+        set_outer(ap, p, a, true);  // the axes before a were cropped to their band
         ap.in_band_N = 0;
         ap.out_band_N = (int)p.N[a];
         ap.dir = +1;
@@ -619,7 +657,7 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pa
             while (p.geom.Q[D - 1] % ap.lines_per_block) ap.lines_per_block /= 2;
         hipError_t e;
         {
-            StageTimer t(p, a == 1 ? 6 : 5, s);
+            StageTimer t(p, a == 0 ? 5 : 6, s);
             e = merge_here ? launch_fft_axis0_from_pad(p, grid, ap, pad, s)
                            : launch_fft_axis(p, grid, ap, s);
         }
@@ -674,11 +712,7 @@ hipError_t plain_fft(const nfft_plan_s &p, void *grid, int dir, hipStream_t s) {
         ap.axis = a;
         ap.inner = 1;
         for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
-        ap.outer_len = 1;
-        if (a == 1) {
-            ap.outer_len = (int)p.Nt[0];
-            ap.outer_stride = (long long)p.Nt[1] * p.Nt[2];
-        }
+        set_outer(ap, p, a, false);
         ap.dir = dir;
         ap.K = 1;
         ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
@@ -697,7 +731,7 @@ hipError_t ensure_channels(nfft_plan_s &p, int K) {
     p.many_cap = 0;
     const size_t cs = csize(p.dtype);
     hipError_t e = hipMalloc(&p.grid_many, (size_t)K * p.G * cs);
-    if (e == hipSuccess && p.nsub > 0)
+    if (e == hipSuccess && p.nsub > 0 && tiled_resampling(p))
         e = hipMalloc(&p.pad_many, (size_t)K * p.nsub * padded_cells(p.geom, p.D) * cs);
     if (e == hipSuccess) p.many_cap = K;
     return e;

@@ -169,12 +169,13 @@ int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M,
     if (vrc != NFFT_OK) return vrc;
     nfft_options base{};
     if (opts) base = *opts;
-    if (base.tile[0] || base.tile[1] || base.tile[2])  // tiles fixed by the caller
+    if (base.tile[0] || base.tile[1] || base.tile[2] || base.tile[3])  // tiles fixed by the caller
         return nfft_plan_create_ex(out, D, N, M, x, m, sigma, dtype, opts, stream);
     std::vector<std::vector<int>> tiles;
     if (D == 1) tiles = {{128}, {256}, {512}, {1024}};
     else if (D == 2) tiles = {{16, 16}, {16, 32}, {32, 32}, {32, 64}, {64, 64}};
-    else tiles = {{8, 8, 8}, {8, 8, 16}, {8, 16, 16}, {16, 16, 16}};
+    else if (D == 3) tiles = {{8, 8, 8}, {8, 8, 16}, {8, 16, 16}, {16, 16, 16}};
+    else tiles = {{4, 4, 4, 4}, {4, 4, 4, 8}, {4, 4, 8, 8}, {8, 8, 8, 8}};
 
     hipStream_t s = (hipStream_t)stream;
     // scratch input/output for the timing runs (values do not change the work)
@@ -236,7 +237,7 @@ int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M,
         try_one(o);
     }
     if (best && rc == NFFT_OK && base.max_block_nodes == 0) {
-        int bt[3] = {0, 0, 0};
+        int bt[4] = {0, 0, 0, 0};
         (void)nfft_plan_info(best, nullptr, nullptr, bt);
         for (int cap : {256, 512, 2048}) {
             if (rc != NFFT_OK) break;

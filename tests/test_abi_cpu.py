@@ -50,10 +50,11 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(D=0), -1), (dict(D=4, N=(8, 8, 8, 8)), -2), (dict(N=None), -1),
+    (dict(D=0), -1), (dict(D=5, N=(8,) * 5), -2), (dict(N=None), -1),
     (dict(M=-1), -1), (dict(M=5, x=None), -1), (dict(m=0, x=FAKE), -1), (dict(m=11, x=FAKE), -2),
     (dict(sigma=1.0, x=FAKE), -1), (dict(sigma=float("nan"), x=FAKE), -1),
-    (dict(dtype=7, x=FAKE), -1), (dict(D=4, N=(8, 8, 8, 8), x=FAKE), -2), (dict(N=(1, 64), x=FAKE), -1),
+    (dict(dtype=7, x=FAKE), -1), (dict(D=5, N=(8,) * 5, x=FAKE), -2), (dict(N=(1, 64), x=FAKE), -1),
+    (dict(D=4, N=(8, 8, 8, 1), x=FAKE), -1), (dict(D=4, N=(8, 8, 8, 4), m=4, x=FAKE), -1),
     (dict(N=(4, 64), m=4, x=FAKE), -1), (dict(N=(4096, 64), x=FAKE), -2),
 ])
 def test_argument_errors_without_gpu(lib, kw, code):
@@ -73,6 +74,13 @@ def test_option_errors(lib):
     o = _lib.Options()
     o.tile[2] = 8  # axis beyond D
     assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -1
+    o = _lib.Options()
+    o.tile[3] = 8
+    assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -1
+    o = _lib.Options()
+    o.window = _lib.NFFT_WINDOW_FULL  # (2m)^D products per node: D <= 2 only
+    assert _create(lib, D=3, N=(16, 16, 16), M=0, opts=ctypes.byref(o))[0] == -2
+    assert _create(lib, D=4, N=(8, 8, 8, 8), M=0, opts=ctypes.byref(o))[0] == -2
     o = _lib.Options()
     o.wide = 2
     assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -1
@@ -104,11 +112,11 @@ def test_batch_and_tuner_argument_errors(lib):
     assert lib.nfft_batch_create(ctypes.byref(out), 2, plans, 0) == -1
     N = (ctypes.c_int64 * 2)(64, 64)
     ms = ctypes.c_double()
-    # sigma <= 1, D > 3, reps < 1
+    # sigma <= 1, D > 4, reps < 1
     assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(1.0), 0,
                                       None, 2, None, ctypes.byref(ms)) == -1
-    N4 = (ctypes.c_int64 * 4)(8, 8, 8, 8)
-    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 4, N4, 0, None, 4, ctypes.c_double(2.0),
+    N5 = (ctypes.c_int64 * 5)(8, 8, 8, 8, 8)
+    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 5, N5, 0, None, 4, ctypes.c_double(2.0),
                                       0, None, 2, None, ctypes.byref(ms)) == -2
     assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(2.0), 0,
                                       None, 0, None, ctypes.byref(ms)) == -1

@@ -210,3 +210,17 @@ def test_odd_sizes_against_ndft(N):
     fh = wl.cn01((400,), config=73, stream=2)
     assert _rel2(na.forward(x, f, 4, 2.0), ndft.ndft_forward(x, f)) < 1e-6
     assert _rel2(na.adjoint(x, fh, N, 4, 2.0), ndft.ndft_adjoint(x, fh, N)) < 1e-6
+
+
+@pytest.mark.parametrize("N,m,gate", [((8, 8, 8, 8), 4, 1e-6), ((7, 6, 9, 8), 3, 3e-5)])
+def test_four_dimensional_against_ndft(N, m, gate):
+    """D = 4 (the method is dimension-agnostic, subsection "Direct NFFT"): the same gates,
+    and the approximate pair stays exactly adjoint."""
+    x = wl.uniform_nodes(300, 4, config=74, stream=0)
+    f = wl.cn01(N, config=74, stream=1)
+    fh = wl.cn01((300,), config=74, stream=2)
+    y = na.forward(x, f, m, 2.0)
+    a = na.adjoint(x, fh, N, m, 2.0)
+    assert _rel2(y, ndft.ndft_forward(x, f)) < gate
+    assert _rel2(a, ndft.ndft_adjoint(x, fh, N)) < gate
+    assert abs(np.vdot(fh, y) - np.vdot(a, f)) < 1e-13 * np.linalg.norm(fh) * np.linalg.norm(y)
