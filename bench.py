@@ -34,6 +34,7 @@ WORKLOADS = {
     "2d_n512_radial402x652": dict(D=2, N=(512, 512), M=402 * 652, nodes="radial", config=1),
     "3d_n128_m2097152_uniform": dict(D=3, N=(128, 128, 128), M=2097152, nodes="uniform", config=2),
     "1d_n256_m512_uniform": dict(D=1, N=(256,), M=512, nodes="uniform", config=0),
+    "4d_n16_m65536_uniform": dict(D=4, N=(16, 16, 16, 16), M=65536, nodes="uniform", config=5),
     # the runtime around the plans: K channels through one node set, and a batch of 64
     # independent transforms of random sizes run as one HIP graph
     "2d_n256_radial256x256_k32": dict(D=2, N=(256, 256), M=65536, nodes="radial256", config=3,
@@ -134,7 +135,9 @@ def inputs(w):
 
 
 def algorithmic_bytes(w, Nt, dtype):
-    """Per-launch algorithmic HBM bytes of every kernel of a step."""
+    """Per-launch algorithmic HBM bytes of every kernel of a step.  An FFT pass along
+    axis a reads (forward) or writes (adjoint) the band rows of that axis, with the
+    axes before it already cropped to their band and the axes after it whole."""
     c = 8 if dtype == "c64" else 16
     r = c // 2
     M, D, N = w["M"], w["D"], w["N"]
@@ -142,24 +145,20 @@ def algorithmic_bytes(w, Nt, dtype):
     nodes_and_values = M * (D * r + c)
     out = {"interp": nodes_and_values + G * c, "spread": nodes_and_values + G * c}
     nprod = int(np.prod(N))
-    if D == 1:
-        out["fwd_deconv_fft_last"] = nprod * c + G * c
-        out["adj_fft_last_deconv"] = G * c + nprod * c
-    elif D == 2:
-        band = N[0] * Nt[1]
-        out["fwd_deconv_fft_last"] = nprod * c + band * c
-        out["fwd_fft_axis0"] = band * c + G * c
-        out["adj_fft_axis0"] = G * c + band * c
-        out["adj_fft_last_deconv"] = band * c + nprod * c
-    else:
-        lines2 = N[0] * N[1] * Nt[2]
-        plane = N[0] * Nt[1] * Nt[2]
-        out["fwd_deconv_fft_last"] = nprod * c + lines2 * c
-        out["fwd_fft_axis1"] = lines2 * c + plane * c
-        out["fwd_fft_axis0"] = plane * c + G * c
-        out["adj_fft_axis0"] = G * c + plane * c
-        out["adj_fft_axis1"] = plane * c + lines2 * c
-        out["adj_fft_last_deconv"] = lines2 * c + nprod * c
+    last = int(np.prod(N[:D - 1])) * Nt[D - 1]
+    out["fwd_deconv_fft_last"] = nprod * c + last * c
+    out["adj_fft_last_deconv"] = last * c + nprod * c
+
+    def pass_bytes(a):
+        pre, post = int(np.prod(N[:a])), int(np.prod(Nt[a + 1:]))
+        return (pre * N[a] * post + pre * Nt[a] * post) * c
+    if D >= 2:
+        out["fwd_fft_axis0"] = out["adj_fft_axis0"] = pass_bytes(0)
+    if D >= 3:
+        # stages 1 and 6 keep the last middle-axis pass they recorded: axis 1 forward,
+        # axis D-2 adjoint
+        out["fwd_fft_axis1"] = pass_bytes(1)
+        out["adj_fft_axis1"] = pass_bytes(D - 2)
     return out
 
 

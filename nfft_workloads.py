@@ -92,6 +92,7 @@ WORKLOADS = {
     "2d_n512_radial402x652": dict(config=1, D=2, N=(512, 512), M=402 * 652, nodes="radial",
                                   spokes=402, samples=652),
     "3d_n128_m2097152": dict(config=2, D=3, N=(128, 128, 128), M=2097152, nodes="uniform"),
+    "4d_n16_m65536": dict(config=5, D=4, N=(16, 16, 16, 16), M=65536, nodes="uniform"),
     # batched / multi-channel (the runtime around the plans)
     "2d_n256_radial256x256_k32": dict(config=3, D=2, N=(256, 256), M=256 * 256, nodes="radial",
                                       spokes=256, samples=256, K=32),

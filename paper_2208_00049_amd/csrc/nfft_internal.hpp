@@ -36,14 +36,30 @@ struct Geom {
     int lo;          // stencil points before the node's cell: taps/2 - 1
 };
 
-// Output-driven spreading (D = 4): a node binned in tile p - b along axis d can
-// reach tile p only for b <= 1 + (taps - 2) / Q_d; the candidate tiles per axis
-// are those r_d = min(T_d, 2 + (taps - 2) / Q_d) tiles.
+// Tile-owner spreading (D = 4): a workgroup owns one tile and visits the nodes
+// whose stencil reaches into it.  A node binned in tile p - b along axis d can
+// reach tile p only for b <= 1 + (taps - 2) / Q_d: the candidate tiles per axis
+// are r_d = min(T_d, 2 + (taps - 2) / Q_d), their product at most
+// kGatherMaxTiles (tile edges >= taps / 2 keep r_d <= 3).
 __host__ __device__ inline int gather_reach(const Geom &g, int d) {
     const int r = 2 + (g.taps - 2) / g.Q[d];
     return r < g.T[d] ? r : g.T[d];
 }
-constexpr int kGatherMaxTiles = 81;  // candidate tiles of one spreading workgroup (3^4)
+constexpr int kGatherMaxTiles = 81;  // candidate tiles of one workgroup (3^4)
+// Candidate nodes staged per round by the tile-owner kernels (their box weights
+// take at most about 16 KiB), and the kernels' static LDS: staged candidates
+// (gk, slot, 3 ints per axis; D fractions, a value, the box weights) and the
+// candidate-tile ranges.
+constexpr int owner_chunk_n(int D, int taps, int rs) {
+    return 16384 / (D * taps * rs) >= 128 ? 128 : 16384 / (D * taps * rs) >= 64 ? 64 : 32;
+}
+constexpr size_t owner_static_lds(int D, int taps, int rs) {
+    return (size_t)owner_chunk_n(D, taps, rs) * (4 * (2 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
+           4 * (2 * kGatherMaxTiles + 1) + 256;
+}
+constexpr int kOwnerThreads = 512;  // workgroup of the tile-owner spreading kernel
+// Bytes per grid point of its LDS tile: 64-bit fixed-point slots, 2 (c64) or 4 (c128).
+inline size_t owner_cell_bytes(int cs) { return cs == 8 ? 16 : 32; }
 
 // Cells of a tile extended by the (2m-1)-wide trailing halo of every axis.
 inline size_t padded_cells(const Geom &g, int D) {
@@ -146,7 +162,7 @@ struct nfft_plan_s {
     int *key_start = nullptr;      // nkeys + 1
     int4 *subs = nullptr;          // nsub work items {tile, begin, end, 0}, grouped by tile
     int *tile_sub = nullptr;       // ntiles + 1: first work item of each tile
-    void *pad = nullptr;           // nsub padded tiles (spreading scratch), complex
+    void *pad = nullptr;           // nsub padded tiles (spreading scratch, D <= 3), complex
     void *wtab = nullptr;          // window tables: TENSOR / FULL per sorted node, LINEAR per axis
     long long lin_S = 0;           // LINEAR: entries per axis
     // multi-channel calls: K grids and K sets of padded tiles, grown on demand

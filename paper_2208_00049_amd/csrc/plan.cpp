@@ -21,6 +21,9 @@ namespace {
 constexpr int kMaxM = 10;
 constexpr size_t kLdsBudget = 65536;
 constexpr int kDefaultBlockNodes = 1024;
+// D = 4 interpolates one node per wavefront: small work items spread a tile's
+// nodes over many workgroups
+constexpr int kDefaultBlockNodes4d = 32;
 constexpr int kMaxChannels = 65535;  // channels of one multi-channel call (grid y dimension)
 
 bool is_235_smooth(int64_t v) {
@@ -41,9 +44,13 @@ int64_t oversampled(int64_t N, double sigma) {
 
 size_t csize(nfft_dtype t) { return t == NFFT_C64 ? 8 : 16; }
 
-// D <= 3 resamples through LDS tiles with padded-tile scratch; D = 4 works on
-// the grid directly (no scratch).
-bool tiled_resampling(const nfft_plan_s &p) { return p.D <= 3; }
+// Complex values of spreading scratch per channel: the work items' padded tiles
+// (D <= 3; D = 4 spreads straight into the grid).
+size_t scratch_cells(const nfft_plan_s &p) {
+    if (p.nsub == 0 || p.D > 3) return 0;
+    return (size_t)p.nsub * padded_cells(p.geom, p.D);
+}
+
 size_t rsize(nfft_dtype t) { return t == NFFT_C64 ? 4 : 8; }
 
 size_t node_rec_size(nfft_dtype t, int D) {
@@ -128,37 +135,66 @@ int pick_edge(int64_t Nt, int want, int taps) {
     return 0;
 }
 
-// D = 4 resamples from the grid in HBM (no LDS tile): a tile edge is any
-// divisor of Nt; the spreading workgroup reads the nodes of at most
-// kGatherMaxTiles tiles, which needs Q_d >= taps/2 on most axes.  Default: the
-// smallest divisor >= taps/2 (few candidate nodes per grid point).
-int choose_tiles_4d(const int64_t *Nt, int taps, const int *req, int *Q) {
-    const bool given = req && (req[0] || req[1] || req[2] || req[3]);
-    Geom g{};
-    g.taps = taps;
-    int nb = 1;
-    for (int d = 0; d < 4; ++d) {
-        if (given) {
+// D = 4: a spreading workgroup owns one tile (its fixed-point accumulators in
+// LDS) and reads the nodes of at most kGatherMaxTiles
+// tiles, which tile edges >= taps/2 guarantee.  A tile edge is any divisor of
+// Nt_d.  Default: per axis the smallest divisor >= max(8, taps/2), then the
+// largest edge shrinks (to a smaller divisor >= taps/2) until the tile fits the
+// workgroup LDS `budget`.
+int choose_tiles_4d(const int64_t *Nt, int taps, nfft_dtype dt, const int *req, size_t budget,
+                    int *Q) {
+    const size_t cs = csize(dt);
+    const size_t stat = owner_static_lds(4, taps, (int)rsize(dt));
+    auto fits = [&](const int *q) {
+        size_t cells = 1;
+        for (int d = 0; d < 4; ++d) cells *= (size_t)q[d];
+        return cells * owner_cell_bytes((int)cs) + stat <= budget;
+    };
+    auto reach_ok = [&](const int *q) {
+        Geom g{};
+        g.taps = taps;
+        int nb = 1;
+        for (int d = 0; d < 4; ++d) {
+            g.Q[d] = q[d];
+            g.T[d] = (int)(Nt[d] / q[d]);
+            nb *= gather_reach(g, d);
+        }
+        return nb <= kGatherMaxTiles;
+    };
+    if (req && (req[0] || req[1] || req[2] || req[3])) {
+        for (int d = 0; d < 4; ++d) {
             if (req[d] < 1 || Nt[d] % req[d]) return NFFT_ERR_ARG;
             Q[d] = req[d];
-        } else {
-            Q[d] = (int)Nt[d];
-            for (int q = taps / 2; q < Nt[d]; ++q)
-                if (Nt[d] % q == 0) {
-                    Q[d] = q;
-                    break;
-                }
         }
-        g.Q[d] = Q[d];
-        g.T[d] = (int)(Nt[d] / Q[d]);
-        nb *= gather_reach(g, d);
+        return reach_ok(Q) && fits(Q) ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
     }
-    return nb <= kGatherMaxTiles ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
+    const int lo = std::max(1, taps / 2);
+    for (int d = 0; d < 4; ++d) {
+        Q[d] = (int)Nt[d];
+        for (int q = std::max(8, lo); q < Nt[d]; ++q)
+            if (Nt[d] % q == 0) {
+                Q[d] = q;
+                break;
+            }
+    }
+    while (!fits(Q)) {
+        int best = -1, bq = 0;
+        for (int d = 0; d < 4; ++d) {
+            int q = Q[d] - 1;
+            while (q >= lo && Nt[d] % q) --q;
+            if (q >= lo && (best < 0 || Q[d] > Q[best])) {
+                best = d;
+                bq = q;
+            }
+        }
+        if (best < 0) return NFFT_ERR_UNSUPPORTED;
+        Q[best] = bq;
+    }
+    return reach_ok(Q) ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
 }
 
 int choose_tiles(int D, const int64_t *Nt, int taps, nfft_dtype dt, const int *req, size_t budget,
                  int *Q) {
-    if (D == 4) return choose_tiles_4d(Nt, taps, req, Q);
     const size_t cs = csize(dt);
     if (req && (req[0] || req[1] || req[2])) {
         for (int d = 0; d < D; ++d) {
@@ -367,7 +403,9 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     p->window = opts ? opts->window : NFFT_WINDOW_POLY;
     p->wide = opts ? opts->wide : 0;
     const int taps = 2 * m + (p->wide ? 2 : 0);
-    p->max_block_nodes = (opts && opts->max_block_nodes) ? opts->max_block_nodes : kDefaultBlockNodes;
+    p->max_block_nodes = (opts && opts->max_block_nodes) ? opts->max_block_nodes
+                         : D == 4                          ? kDefaultBlockNodes4d
+                                                           : kDefaultBlockNodes;
     p->G = 1;
     p->NN = 1;
     for (int d = 0; d < kMaxD; ++d) {
@@ -402,9 +440,14 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         p->lds_limit = dev_lds;
         int Q[kMaxD] = {1, 1, 1, 1};
         const int *req = opts ? opts->tile : nullptr;
-        int trc = choose_tiles(D, p->Nt, taps, dtype, req, kLdsBudget, Q);
-        if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds > kLdsBudget)
-            trc = choose_tiles(D, p->Nt, taps, dtype, req, (size_t)dev_lds - 1024, Q);
+        int trc;
+        if (D == 4) {
+            trc = choose_tiles_4d(p->Nt, taps, dtype, req, (size_t)dev_lds, Q);
+        } else {
+            trc = choose_tiles(D, p->Nt, taps, dtype, req, kLdsBudget, Q);
+            if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds > kLdsBudget)
+                trc = choose_tiles(D, p->Nt, taps, dtype, req, (size_t)dev_lds - 1024, Q);
+        }
         if (trc != NFFT_OK) {
             rc = trc;
             goto fail;
@@ -481,8 +524,7 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     TRY(hipStreamSynchronize(s));
     p->nsub = host_nsub;
     if (host_bad) rc = NFFT_ERR_NODES;
-    if (rc == NFFT_OK && p->nsub > 0 && tiled_resampling(*p))
-        TRY(hipMalloc(&p->pad, (size_t)p->nsub * padded_cells(p->geom, D) * cs));
+    if (rc == NFFT_OK && scratch_cells(*p) > 0) TRY(hipMalloc(&p->pad, scratch_cells(*p) * cs));
     if (rc == NFFT_OK && p->window != NFFT_WINDOW_POLY && p->window != NFFT_WINDOW_DIRECT) {
         // window tables of the precomputation modes (FP64 evaluation, plan type storage)
         size_t n = 0;
@@ -731,8 +773,8 @@ hipError_t ensure_channels(nfft_plan_s &p, int K) {
     p.many_cap = 0;
     const size_t cs = csize(p.dtype);
     hipError_t e = hipMalloc(&p.grid_many, (size_t)K * p.G * cs);
-    if (e == hipSuccess && p.nsub > 0 && tiled_resampling(p))
-        e = hipMalloc(&p.pad_many, (size_t)K * p.nsub * padded_cells(p.geom, p.D) * cs);
+    if (e == hipSuccess && scratch_cells(p) > 0)
+        e = hipMalloc(&p.pad_many, (size_t)K * scratch_cells(p) * cs);
     if (e == hipSuccess) p.many_cap = K;
     return e;
 }

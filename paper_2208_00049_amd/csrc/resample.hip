@@ -1,5 +1,5 @@
 // Instantiation and dispatch of the resampling kernels over (type, D, 2m).
-#include "resample_gather.hpp"
+#include "resample_4d.hpp"
 
 namespace nfft {
 
@@ -27,7 +27,7 @@ static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, h
         case 1: NFFT_DISPATCH_M(run_interp, T, 1, p, grid, fhat, s, K)
         case 2: NFFT_DISPATCH_M(run_interp, T, 2, p, grid, fhat, s, K)
         case 3: NFFT_DISPATCH_M(run_interp, T, 3, p, grid, fhat, s, K)
-        case 4: NFFT_DISPATCH_M(run_interp_gather, T, 4, p, grid, fhat, s, K)
+        case 4: NFFT_DISPATCH_M(run_interp_node, T, 4, p, grid, fhat, s, K)
         default: return hipErrorInvalidValue;
     }
 }
@@ -39,7 +39,7 @@ static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, h
         case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s, merge, K, pad)
         case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s, merge, K, pad)
         case 3: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s, merge, K, pad)
-        case 4: NFFT_DISPATCH_M(run_spread_gather, T, 4, p, fhat, grid, s, K)
+        case 4: NFFT_DISPATCH_M(run_spread_owner, T, 4, p, fhat, grid, s, K)
         default: return hipErrorInvalidValue;
     }
 }
