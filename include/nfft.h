@@ -92,7 +92,7 @@ typedef struct {
                              NFFT_ERR_UNSUPPORTED. */
     int window;           /* NFFT_WINDOW_POLY (default), _DIRECT, _TENSOR, _LINEAR or _FULL */
     int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
-                             into items of at most this many), 0 = automatic (1024; 32 for
+                             into items of at most this many), 0 = automatic (1024; 16 for
                              D = 4, whose interpolation takes one wavefront per node) */
     int wide;             /* 1: (2m+2)^D-point stencil with the untruncated window, sampled
                              beyond its truncation interval (the alternative of subsection

@@ -40,6 +40,17 @@ __host__ __device__ inline int band_pos(int r, int N, int Nt) {
     return r < N / 2 ? Nt - N / 2 + r : r - N / 2;
 }
 
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator dies, each with its own L2
+
+// Workgroups are dispatched round robin over the XCDs (block b runs on XCD b mod 8).
+// Renumber them so that each XCD gets a contiguous run of logical blocks: blocks
+// that share cache lines (neighbouring columns, neighbouring tiles) then share an L2.
+__device__ inline int xcd_block(int b, int nblocks) {
+    const int full = nblocks - nblocks % kNumXcd;
+    if (b >= full) return b;
+    return (b % kNumXcd) * (full / kNumXcd) + b / kNumXcd;
+}
+
 // q = n / d and r = n % d for 0 <= n < 2^22 and d >= 1, given rcp = 1/d in
 // float: the float quotient is off by at most one, which one step corrects.
 __device__ inline int small_divmod(int n, int d, float rcp, int &r) {

@@ -19,16 +19,6 @@
 namespace nfft {
 
 constexpr int kLinePad = 1;  // complex values of padding after each LDS line
-constexpr int kNumXcd = 8;   // MI355X: 8 accelerator dies, each with its own L2
-
-// Workgroups are dispatched round robin over the XCDs (block b runs on XCD b mod 8).
-// Renumber them so that each XCD gets a contiguous run of logical blocks: blocks
-// that share cache lines (neighbouring columns, neighbouring tiles) then share an L2.
-__device__ inline int xcd_block(int b, int nblocks) {
-    const int full = nblocks - nblocks % kNumXcd;
-    if (b >= full) return b;
-    return (b % kNumXcd) * (full / kNumXcd) + b / kNumXcd;
-}
 
 // Copy the twiddle table (L values) into LDS: every thread issues its loads,
 // up to eight at a time, before it writes any of them.

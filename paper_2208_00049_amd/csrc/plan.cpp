@@ -23,7 +23,7 @@ constexpr size_t kLdsBudget = 65536;
 constexpr int kDefaultBlockNodes = 1024;
 // D = 4 interpolates one node per wavefront: small work items spread a tile's
 // nodes over many workgroups
-constexpr int kDefaultBlockNodes4d = 32;
+constexpr int kDefaultBlockNodes4d = 16;
 constexpr int kMaxChannels = 65535;  // channels of one multi-channel call (grid y dimension)
 
 bool is_235_smooth(int64_t v) {

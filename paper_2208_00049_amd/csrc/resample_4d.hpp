@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     TapCoef<T, M2> ca, cb;
     ca.load(coef, window, wp.m, da, ta);
     if constexpr (NWT > 64) cb.load(coef, window, wp.m, db, tb);
-    const int4 sp = subs[blockIdx.x];
+    const int4 sp = subs[xcd_block(blockIdx.x, gridDim.x)];  // neighbouring tiles share an L2
     // the loop bound is uniform over the wavefront: all lanes stay active for the shuffles
     for (int j = sp.y + wave; j < sp.z; j += NW) {
         const NodeRec<T, D> rec = nodes[j];
@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(kOwnerThreads)
                   "staged candidates larger than the LDS the plan reserves for them");
     grid += blockIdx.y * gstride;
     fhat += blockIdx.y * fstride;
-    const OwnerTile<D> ot = owner_tile<D>(g, blockIdx.x);
+    const OwnerTile<D> ot = owner_tile<D>(g, xcd_block(blockIdx.x, gridDim.x));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwave = blockDim.x >> 6;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
