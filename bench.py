@@ -195,6 +195,56 @@ def cpu_baseline(x, f, fh, N, seconds):
                       % (sf, M, t1 - t0, sa, nprod, t2 - t1)}
 
 
+def cpu_nfft(x, f, fh, N, m, sigma, seconds):
+    """Time the plain FP64 NFFT of the oracle (numpy, Algorithms 1 and 2, one host thread)
+    on the same workload.  When the full node set would take too long, the forward and the
+    adjoint are each timed at two node-sample sizes and extrapolated linearly in M (the
+    FFT part is the intercept)."""
+    from oracle import nfft_alg as na
+    M = x.shape[0]
+
+    def pair(ms):
+        t0 = time.perf_counter()
+        na.forward(x[:ms], f, m, sigma)
+        t1 = time.perf_counter()
+        na.adjoint(x[:ms], fh[:ms], N, m, sigma)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+    s1 = min(M, 4096)
+    a1 = pair(s1)
+    per_node = max(sum(a1), 1e-9) / s1
+    if M == s1 or per_node * M < seconds:
+        tf, ta = pair(M) if M > s1 else a1
+        sample = "full workload, %d nodes" % M
+    else:
+        s2 = int(min(M, max(2 * s1, 0.5 * seconds / per_node)))
+        a2 = pair(s2)
+        slope = [(b - a) / (s2 - s1) for a, b in zip(a1, a2)]
+        tf, ta = [b + k * (M - s2) for b, k in zip(a2, slope)]
+        sample = ("timed at %d and %d of %d nodes, extrapolated linearly in the node count"
+                  % (s1, s2, M))
+    return {"value": M / (tf + ta), "unit": "pts/s", "cores": 1, "kind": "oracle NFFT (numpy)",
+            "fwd_s": round(tf, 3), "adj_s": round(ta, 3), "sample": sample}
+
+
+def rocfft_reference(Nt, cdt, reps=20):
+    """Milliseconds of one unpruned FFT of the oversampled grid by torch.fft (rocFFT),
+    timed with events on torch's stream: a reference point for the FFT passes."""
+    import torch
+    g = torch.randn(tuple(Nt), dtype=cdt, device="cuda:0")
+    dims = tuple(range(len(Nt)))
+    for _ in range(3):
+        torch.fft.fftn(g, dim=dims)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        torch.fft.fftn(g, dim=dims)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def timed(fn, steps, warmup):
     """Mean milliseconds of fn() over `steps` calls after `warmup` calls (HIP events)."""
     import torch
@@ -446,6 +496,27 @@ def main():
                 "traffic": round(traffic) if traffic is not None else None,
                 "algorithmic_bytes": algo[dominant], "launch_ms": round(dom_ms, 5)}
 
+    # spreading's own roof: its 64-bit LDS atomics (one per component and tap for c64,
+    # two for c128), against the rate a microbenchmark measured for ds_add_u64 on
+    # consecutive addresses (9.5 lane operations per clock per CU)
+    taps = 2 * args.m + (2 if args.wide else 0)
+    atomics = w["M"] * taps ** w["D"] * (2 if args.dtype == "c64" else 4)
+    lds_peak = 9.5 * 256 * 2.4e9
+    spread_ms = b2b.get("spread", avg_ms.get("spread"))
+    lds_roof = None
+    if spread_ms:
+        rate = atomics / (spread_ms * 1e-3)
+        lds_roof = {"kernel": "spread", "bound": "lds_atomic", "atomic_lane_ops": atomics,
+                    "achieved": round(rate / 1e12, 4), "peak": round(lds_peak / 1e12, 4),
+                    "unit": "T lane-ops/s", "frac": round(rate / lds_peak, 4)}
+    fwd_fft_ms = sum(v for k, v in avg_ms.items() if k.startswith("fwd_"))
+    rocfft = None
+    if not args.profile_only:
+        rocfft = {"grid": list(info["Ntilde"]),
+                  "torch_fft_ms": round(rocfft_reference(info["Ntilde"], cdt), 5),
+                  "ours_fwd_fft_ms": round(fwd_fft_ms, 5),
+                  "note": "ours: resampling correction + pruned FFT passes of one forward "
+                          "transform; torch.fft.fftn (rocFFT): plain unpruned FFT of the grid"}
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
@@ -460,6 +531,8 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "back_to_back_ms": {k: round(v, 5) for k, v in b2b.items()},
+        "rocfft_reference": rocfft,
+        "lds_roof": lds_roof,
     }
 
     if not args.profile_only:
@@ -475,9 +548,11 @@ def main():
             p64.close()
         if not args.no_cpu:
             xs = xt.double().cpu().numpy()
-            result["cpu_baseline"] = cpu_baseline(xs, ft.cpu().numpy().astype(np.complex128),
-                                                  fht.cpu().numpy().astype(np.complex128),
-                                                  w["N"], args.cpu_seconds)
+            fc = ft.cpu().numpy().astype(np.complex128)
+            fhc = fht.cpu().numpy().astype(np.complex128)
+            result["cpu_baseline"] = cpu_baseline(xs, fc, fhc, w["N"], args.cpu_seconds)
+            result["cpu_nfft"] = cpu_nfft(xs, fc, fhc, w["N"], args.m, args.sigma,
+                                          args.cpu_seconds)
     plan.close()
     print(json.dumps(result), flush=True)
 
