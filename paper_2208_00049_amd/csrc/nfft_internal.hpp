@@ -40,22 +40,22 @@ struct Geom {
 // whose stencil reaches into it.  A node binned in tile p - b along axis d can
 // reach tile p only for b <= 1 + (taps - 2) / Q_d: the candidate tiles per axis
 // are r_d = min(T_d, 2 + (taps - 2) / Q_d), their product at most
-// kGatherMaxTiles (tile edges >= taps / 2 keep r_d <= 3).
-__host__ __device__ inline int gather_reach(const Geom &g, int d) {
+// kOwnerMaxTiles (tile edges >= taps / 2 keep r_d <= 3).
+__host__ __device__ inline int owner_reach(const Geom &g, int d) {
     const int r = 2 + (g.taps - 2) / g.Q[d];
     return r < g.T[d] ? r : g.T[d];
 }
-constexpr int kGatherMaxTiles = 81;  // candidate tiles of one workgroup (3^4)
+constexpr int kOwnerMaxTiles = 81;  // candidate tiles of one workgroup (3^4)
 // Candidate nodes staged per round by the tile-owner kernels (their box weights
 // take at most about 16 KiB), and the kernels' static LDS: staged candidates
-// (gk, slot, 3 ints per axis; D fractions, a value, the box weights) and the
-// candidate-tile ranges.
+// (sorted position and 3 ints per axis; D fractions, a value, the box weights),
+// the candidate-tile ranges and the scale word.
 constexpr int owner_chunk_n(int D, int taps, int rs) {
     return 16384 / (D * taps * rs) >= 128 ? 128 : 16384 / (D * taps * rs) >= 64 ? 64 : 32;
 }
 constexpr size_t owner_static_lds(int D, int taps, int rs) {
-    return (size_t)owner_chunk_n(D, taps, rs) * (4 * (2 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
-           4 * (2 * kGatherMaxTiles + 1) + 256;
+    return (size_t)owner_chunk_n(D, taps, rs) * (4 * (1 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
+           4 * (2 * kOwnerMaxTiles + 1) + 256;
 }
 constexpr int kOwnerThreads = 512;  // workgroup of the tile-owner spreading kernel
 // Bytes per grid point of its LDS tile: 64-bit fixed-point slots, 2 (c64) or 4 (c128).

@@ -136,7 +136,7 @@ int pick_edge(int64_t Nt, int want, int taps) {
 }
 
 // D = 4: a spreading workgroup owns one tile (its fixed-point accumulators in
-// LDS) and reads the nodes of at most kGatherMaxTiles
+// LDS) and reads the nodes of at most kOwnerMaxTiles
 // tiles, which tile edges >= taps/2 guarantee.  A tile edge is any divisor of
 // Nt_d.  Default: per axis the smallest divisor >= max(8, taps/2), then the
 // largest edge shrinks (to a smaller divisor >= taps/2) until the tile fits the
@@ -157,9 +157,9 @@ int choose_tiles_4d(const int64_t *Nt, int taps, nfft_dtype dt, const int *req, 
         for (int d = 0; d < 4; ++d) {
             g.Q[d] = q[d];
             g.T[d] = (int)(Nt[d] / q[d]);
-            nb *= gather_reach(g, d);
+            nb *= owner_reach(g, d);
         }
-        return nb <= kGatherMaxTiles;
+        return nb <= kOwnerMaxTiles;
     };
     if (req && (req[0] || req[1] || req[2] || req[3])) {
         for (int d = 0; d < 4; ++d) {

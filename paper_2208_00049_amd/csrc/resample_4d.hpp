@@ -86,7 +86,7 @@ template <int D> __device__ inline OwnerTile<D> owner_tile(const Geom &g, int ti
         ot.tc[d] = rem % g.T[d];
         rem /= g.T[d];
         ot.t0[d] = ot.tc[d] * g.Q[d];
-        ot.r[d] = gather_reach(g, d);
+        ot.r[d] = owner_reach(g, d);
         ot.cells *= g.Q[d];
         ot.nb *= ot.r[d];
     }
@@ -372,9 +372,9 @@ __global__ void __launch_bounds__(kOwnerThreads)
     constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
     extern __shared__ unsigned char smem_raw[];
     __shared__ OwnerStage<T, D, M2> st;
-    __shared__ int nb_begin[kGatherMaxTiles], nb_pre[kGatherMaxTiles + 1];
+    __shared__ int nb_begin[kOwnerMaxTiles], nb_pre[kOwnerMaxTiles + 1];
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double
-    static_assert(sizeof(OwnerStage<T, D, M2>) + sizeof(int) * (2 * kGatherMaxTiles + 1) + 8 <=
+    static_assert(sizeof(OwnerStage<T, D, M2>) + sizeof(int) * (2 * kOwnerMaxTiles + 1) + 8 <=
                       owner_static_lds(D, M2, (int)sizeof(T)),
                   "staged candidates larger than the LDS the plan reserves for them");
     grid += blockIdx.y * gstride;
