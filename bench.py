@@ -189,7 +189,7 @@ def cpu_baseline(x, f, fh, N, seconds):
     t_fwd = (t1 - t0) * M / sf
     t_adj = (t2 - t1) * nprod / sa
     return {"value": M / (t_fwd + t_adj), "unit": "pts/s", "cores": ndft.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": "FP64 direct NDFT: forward at %d of %d nodes (%.2f s), adjoint at %d of %d "
                       "coefficients (%.2f s), scaled to the full transform pair"
                       % (sf, M, t1 - t0, sa, nprod, t2 - t1)}
@@ -243,6 +243,44 @@ def rocfft_reference(Nt, cdt, reps=20):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def call_stats(fns, reps, flush_bytes=0):
+    """Per-call milliseconds of each callable in `fns` (run in turn, `reps` times), timed
+    with events on torch's current stream -- the stream the plan's kernels run on.  With
+    flush_bytes, a buffer that large is written before every repetition (cold caches: the
+    256 MB Infinity Cache is evicted).  Returns {"min", "median", "mean"} per callable."""
+    import torch
+    buf = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda:0") if flush_bytes else None
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in fns] for _ in range(reps)]
+    for r in range(reps):
+        if buf is not None:
+            buf.fill_(float(r))
+        for i, fn in enumerate(fns):
+            ev[r][i][0].record()
+            fn()
+            ev[r][i][1].record()
+    torch.cuda.synchronize()
+    out = []
+    for i in range(len(fns)):
+        t = np.array([ev[r][i][0].elapsed_time(ev[r][i][1]) for r in range(reps)])
+        out.append({"min": float(t.min()), "median": float(np.median(t)), "mean": float(t.mean())})
+    return out
+
+
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "cores": len(os.sched_getaffinity(0))}
 
 
 def timed(fn, steps, warmup):
@@ -363,6 +401,7 @@ def bench_grad(args, w):
                    "sigma": args.sigma, "nodes": "radial 256 x 256, radial jitter U(+-0.5/Ntilde)",
                    "step": "forward, loss, backward (grad f, grad x)"},
         "plan_ms": round(plan_ms, 2),
+        "timing": timing,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -462,6 +501,19 @@ def main():
     ms_per_step = total_ms / args.steps
     value = w["M"] * args.steps / (total_ms * 1e-3)
 
+    # forward and adjoint separately, per-pair min/median, and with cold caches
+    reps = max(5, min(args.steps, 50))
+    fa = call_stats([lambda: plan.forward(ft, out=fout), lambda: plan.adjoint(fht, out=yout)], reps)
+    warm = call_stats([step], reps)[0]
+    cold = call_stats([step], min(reps, 10), flush_bytes=512 << 20)[0]
+    us = lambda d: {k: round(v * 1e3, 3) for k, v in d.items()}
+    timing = {"pair_us": us(warm), "pair_cold_us": us(cold), "fwd_us": us(fa[0]),
+              "adj_us": us(fa[1]),
+              "pts_s_fwd": round(w["M"] / (fa[0]["mean"] * 1e-3), 1),
+              "pts_s_adj": round(w["M"] / (fa[1]["mean"] * 1e-3), 1),
+              "note": "events around each call on the plan's stream, %d repetitions; cold: a "
+                      "512 MiB buffer written before each repetition" % reps}
+
     # per-kernel durations: a second pass of the same steps with stage events on
     plan.set_timing(True)
     sums = {}
@@ -528,6 +580,7 @@ def main():
                    "Ntilde": list(info["Ntilde"]), "tile": list(info["tile"]),
                    "window": args.window, "stencil": "2m+2" if args.wide else "2m"},
         "plan_ms": round(plan_ms, 2),
+        "timing": timing,
         "roofline": roofline,
         "kernels": kernels,
         "back_to_back_ms": {k: round(v, 5) for k, v in b2b.items()},
