@@ -92,8 +92,9 @@ typedef struct {
                              NFFT_ERR_UNSUPPORTED. */
     int window;           /* NFFT_WINDOW_POLY (default), _DIRECT, _TENSOR, _LINEAR or _FULL */
     int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
-                             into items of at most this many), 0 = automatic (1024; 16 for
-                             D = 4, whose interpolation takes one wavefront per node) */
+                             into items of at most this many), 0 = automatic (512 for D <= 2,
+                             1024 for D = 3, 16 for D = 4, whose interpolation takes one
+                             wavefront per node) */
     int wide;             /* 1: (2m+2)^D-point stencil with the untruncated window, sampled
                              beyond its truncation interval (the alternative of subsection
                              "Window Size Considerations"); 0 (default): 2m points.  Not
@@ -107,9 +108,9 @@ typedef struct {
  *   D      1, 2, 3 or 4.  D <= 3 resamples through LDS tiles of the grid; D = 4
  *          (whose tile plus stencil halo does not fit in LDS) interpolates from
  *          the grid in device memory, one wavefront per node, and spreads
- *          output-driven: each grid point is summed by one thread over the
- *          nodes that reach it (no atomics, no scratch; reproducible bit for
- *          bit by the same plan).
+ *          tile by tile: a workgroup owns one tile and adds every node whose
+ *          stencil reaches it in exact fixed point (no global atomics, no
+ *          scratch, bitwise reproducible).
  *   N      host array of D sizes >= 2 (even or odd)
  *   M      number of nodes, >= 0 (M = 0 is allowed)
  *   x      device pointer to the nodes (may be NULL when M == 0)

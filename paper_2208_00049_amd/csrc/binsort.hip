@@ -6,8 +6,16 @@
 // points o .. o+taps-1 (mod Nt) on that axis.  The node is binned by
 // the tile that holds its origin, and by a class bit per axis that says whether
 // its stencil runs past the end of that tile into the next one.  Sort key =
-// tile << D | class; counting sort = histogram, exclusive scan, scatter.
+// tile << D | class.  The bin boundaries come from a histogram and an exclusive
+// scan; the order is a stable radix sort of (key, node index) pairs (rocPRIM),
+// so nodes of one bin keep the caller's order and a plan is a deterministic
+// function of its nodes (its work items, and with them every summation order,
+// do not depend on the scheduling of the plan-time kernels).
 #include <math.h>
+
+#include <string.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.hpp"
 #include "nfft_internal.hpp"
@@ -76,12 +84,17 @@ __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, i
     atomicAdd(&counts[key], 1);
 }
 
+__global__ void k_iota(int *a, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = i;
+}
+
+// Sorted position pos holds node perm[pos]: its stencil origin and fraction per axis.
 template <typename T, int D>
-__global__ void k_node_scatter(const T *x, int M, Geom g, const int *keys, int *cursor, int *perm,
-                               NodeRec<T, D> *nodes) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
-    const int pos = atomicAdd(&cursor[keys[j]], 1);
+__global__ void k_node_gather(const T *x, int M, Geom g, const int *perm, NodeRec<T, D> *nodes) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= M) return;
+    const int j = perm[pos];
     NodeRec<T, D> rec;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -91,7 +104,6 @@ __global__ void k_node_scatter(const T *x, int M, Geom g, const int *keys, int *
         rec.o[d] = c.o;
         rec.fr[d] = (T)c.frac;
     }
-    perm[pos] = j;
     nodes[pos] = rec;
 }
 
@@ -164,10 +176,9 @@ static void keys_t(const nfft_plan_s &p, const void *x, int *keys, int *counts, 
 }
 
 template <typename T, int D>
-static void scatter_t(nfft_plan_s &p, const void *x, const int *keys, int *cursor,
-                      hipStream_t s) {
-    hipLaunchKernelGGL((k_node_scatter<T, D>), grid1d(p.M, 256), dim3(256), 0, s, (const T *)x,
-                       (int)p.M, p.geom, keys, cursor, p.perm, (NodeRec<T, D> *)p.nodes);
+static void gather_t(nfft_plan_s &p, const void *x, hipStream_t s) {
+    hipLaunchKernelGGL((k_node_gather<T, D>), grid1d(p.M, 256), dim3(256), 0, s, (const T *)x,
+                       (int)p.M, p.geom, p.perm, (NodeRec<T, D> *)p.nodes);
 }
 
 hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int *counts, int *bad,
@@ -189,15 +200,37 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_node_scatter(nfft_plan_s &p, const void *x, const int *keys, int *cursor,
-                               hipStream_t s) {
+static unsigned key_bits(int nkeys) {
+    unsigned b = 1;
+    while (b < 31 && (1u << b) < (unsigned)nkeys) ++b;
+    return b;
+}
+
+hipError_t node_sort_bytes(const nfft_plan_s &p, size_t *bytes) {
+    *bytes = 0;
     if (p.M == 0) return hipSuccess;
+    return rocprim::radix_sort_pairs(nullptr, *bytes, (const int *)nullptr, (int *)nullptr,
+                                     (const int *)nullptr, (int *)nullptr, (int)p.M, 0,
+                                     key_bits(p.nkeys), (hipStream_t)0);
+}
+
+hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int *keys_sorted,
+                            int *idx, void *tmp, size_t tmp_bytes, hipStream_t s) {
+    if (p.M == 0) return hipSuccess;
+    const int M = (int)p.M;
+    hipLaunchKernelGGL(k_iota, grid1d(M, 256), dim3(256), 0, s, idx, M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t bytes = tmp_bytes;
+    e = rocprim::radix_sort_pairs(tmp, bytes, keys, keys_sorted, (const int *)idx, p.perm, M, 0,
+                                  key_bits(p.nkeys), s);
+    if (e != hipSuccess) return e;
     const bool f = p.dtype == NFFT_C64;
     switch (p.D) {
-        case 1: f ? scatter_t<float, 1>(p, x, keys, cursor, s) : scatter_t<double, 1>(p, x, keys, cursor, s); break;
-        case 2: f ? scatter_t<float, 2>(p, x, keys, cursor, s) : scatter_t<double, 2>(p, x, keys, cursor, s); break;
-        case 3: f ? scatter_t<float, 3>(p, x, keys, cursor, s) : scatter_t<double, 3>(p, x, keys, cursor, s); break;
-        case 4: f ? scatter_t<float, 4>(p, x, keys, cursor, s) : scatter_t<double, 4>(p, x, keys, cursor, s); break;
+        case 1: f ? gather_t<float, 1>(p, x, s) : gather_t<double, 1>(p, x, s); break;
+        case 2: f ? gather_t<float, 2>(p, x, s) : gather_t<double, 2>(p, x, s); break;
+        case 3: f ? gather_t<float, 3>(p, x, s) : gather_t<double, 3>(p, x, s); break;
+        case 4: f ? gather_t<float, 4>(p, x, s) : gather_t<double, 4>(p, x, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -198,8 +198,10 @@ hipError_t launch_fill_zero_complex(void *a, int64_t n, bool dbl, hipStream_t s)
 hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int *counts, int *bad,
                             hipStream_t s);
 hipError_t launch_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
-hipError_t launch_node_scatter(nfft_plan_s &p, const void *x, const int *keys, int *cursor,
-                               hipStream_t s);
+// Stable bin sort: keys_sorted and idx hold M ints; tmp is node_sort_bytes() bytes.
+hipError_t node_sort_bytes(const nfft_plan_s &p, size_t *bytes);
+hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int *keys_sorted,
+                            int *idx, void *tmp, size_t tmp_bytes, hipStream_t s);
 hipError_t launch_subprob_count(const nfft_plan_s &p, int *counts, hipStream_t s);
 hipError_t launch_subprob_fill(nfft_plan_s &p, const int *sub_start, hipStream_t s);
 

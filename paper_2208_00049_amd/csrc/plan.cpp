@@ -20,10 +20,11 @@ namespace {
 
 constexpr int kMaxM = 10;
 constexpr size_t kLdsBudget = 65536;
-constexpr int kDefaultBlockNodes = 1024;
-// D = 4 interpolates one node per wavefront: small work items spread a tile's
-// nodes over many workgroups
-constexpr int kDefaultBlockNodes4d = 16;
+// Default cap on a work item's nodes, per D: 1-D/2-D dense tiles (a radial
+// trajectory's centre) split at 512 nodes balance best; 3-D tiles hold ~512 nodes
+// on average at sigma = 2 and keep 1024; D = 4 interpolates one node per
+// wavefront, so small items spread a tile's nodes over many workgroups.
+constexpr int kDefaultBlockNodes[5] = {0, 512, 512, 1024, 16};
 constexpr int kMaxChannels = 65535;  // channels of one multi-channel call (grid y dimension)
 
 bool is_235_smooth(int64_t v) {
@@ -403,9 +404,8 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     p->window = opts ? opts->window : NFFT_WINDOW_POLY;
     p->wide = opts ? opts->wide : 0;
     const int taps = 2 * m + (p->wide ? 2 : 0);
-    p->max_block_nodes = (opts && opts->max_block_nodes) ? opts->max_block_nodes
-                         : D == 4                          ? kDefaultBlockNodes4d
-                                                           : kDefaultBlockNodes;
+    p->max_block_nodes =
+        (opts && opts->max_block_nodes) ? opts->max_block_nodes : kDefaultBlockNodes[D];
     p->G = 1;
     p->NN = 1;
     for (int d = 0; d < kMaxD; ++d) {
@@ -425,8 +425,10 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     hipStream_t s = (hipStream_t)stream;
     const size_t cs = csize(dtype), rs = rsize(dtype);
     const int Z = 2 * m + 1, Theta = 2 * Z;
-    int *keys = nullptr, *counts = nullptr, *cursor = nullptr, *bad = nullptr, *subcnt = nullptr,
-        *substart = nullptr;
+    int *keys = nullptr, *counts = nullptr, *keys_sorted = nullptr, *idx = nullptr, *bad = nullptr,
+        *subcnt = nullptr, *substart = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_bytes = 0;
     double *polyscratch = nullptr;
     int host_bad = 0, host_nsub = 0;
     std::vector<double> qt, rr;
@@ -484,7 +486,10 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         TRY(hipMalloc(&p->nodes, (size_t)M * node_rec_size(dtype, D)));
         TRY(hipMalloc(&p->perm, (size_t)M * sizeof(int)));
         TRY(hipMalloc(&keys, (size_t)M * sizeof(int)));
-        TRY(hipMalloc(&cursor, (size_t)(p->nkeys + 1) * sizeof(int)));
+        TRY(hipMalloc(&keys_sorted, (size_t)M * sizeof(int)));
+        TRY(hipMalloc(&idx, (size_t)M * sizeof(int)));
+        TRY(node_sort_bytes(*p, &sort_bytes));
+        TRY(hipMalloc(&sort_tmp, std::max<size_t>(sort_bytes, 1)));
     }
 
     // FP64 precomputation: deconvolution factors, window polynomial, twiddles
@@ -511,11 +516,7 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     TRY(launch_fill_int(bad, 1, 0, s));
     TRY(launch_node_keys(*p, x, keys, counts, bad, s));
     TRY(launch_exclusive_scan(counts, p->key_start, p->nkeys, s));
-    if (M > 0) {
-        TRY(hipMemcpyAsync(cursor, p->key_start, (size_t)(p->nkeys + 1) * sizeof(int),
-                           hipMemcpyDeviceToDevice, s));
-        TRY(launch_node_scatter(*p, x, keys, cursor, s));
-    }
+    if (M > 0) TRY(launch_node_sort(*p, x, keys, keys_sorted, idx, sort_tmp, sort_bytes, s));
     TRY(launch_subprob_count(*p, subcnt, s));
     TRY(launch_exclusive_scan(subcnt, substart, p->geom.ntiles, s));
     TRY(launch_subprob_fill(*p, substart, s));
@@ -547,7 +548,9 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
 fail:
     (void)hipFree(keys);
     (void)hipFree(counts);
-    (void)hipFree(cursor);
+    (void)hipFree(keys_sorted);
+    (void)hipFree(idx);
+    (void)hipFree(sort_tmp);
     (void)hipFree(bad);
     (void)hipFree(subcnt);
     (void)hipFree(polyscratch);

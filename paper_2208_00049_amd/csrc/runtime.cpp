@@ -239,7 +239,7 @@ int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M,
     if (best && rc == NFFT_OK && base.max_block_nodes == 0) {
         int bt[4] = {0, 0, 0, 0};
         (void)nfft_plan_info(best, nullptr, nullptr, bt);
-        for (int cap : {256, 512, 2048}) {
+        for (int cap : {256, 512, 1024, 2048}) {
             if (rc != NFFT_OK) break;
             nfft_options o = base;
             for (int d = 0; d < D; ++d) o.tile[d] = bt[d];
