@@ -401,7 +401,6 @@ def bench_grad(args, w):
                    "sigma": args.sigma, "nodes": "radial 256 x 256, radial jitter U(+-0.5/Ntilde)",
                    "step": "forward, loss, backward (grad f, grad x)"},
         "plan_ms": round(plan_ms, 2),
-        "timing": timing,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -478,10 +477,17 @@ def main():
     yout = torch.empty(w["N"], dtype=cdt, device=dev)
     torch.cuda.synchronize()
 
-    t0 = time.perf_counter()
-    plan = Plan(xt, w["N"], m=args.m, sigma=args.sigma, window=args.window, wide=args.wide)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3
+    # plan time: the first plan of the process pays one-time module loading; the
+    # second one is the steady-state cost (the one a loop that re-plans sees)
+    plan_times = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        plan = Plan(xt, w["N"], m=args.m, sigma=args.sigma, window=args.window, wide=args.wide)
+        torch.cuda.synchronize()
+        plan_times.append((time.perf_counter() - t0) * 1e3)
+        if len(plan_times) == 1:
+            plan.close()
+    plan_first_ms, plan_ms = plan_times
     info = plan.info()
 
     def step():
@@ -584,6 +590,7 @@ def main():
                    "Ntilde": list(info["Ntilde"]), "tile": list(info["tile"]),
                    "window": args.window, "stencil": "2m+2" if args.wide else "2m"},
         "plan_ms": round(plan_ms, 2),
+        "plan_first_ms": round(plan_first_ms, 2),
         "timing": timing,
         "roofline": roofline,
         "kernels": kernels,

@@ -92,9 +92,10 @@ typedef struct {
                              NFFT_ERR_UNSUPPORTED. */
     int window;           /* NFFT_WINDOW_POLY (default), _DIRECT, _TENSOR, _LINEAR or _FULL */
     int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
-                             into items of at most this many), 0 = automatic (512 for D <= 2,
-                             1024 for D = 3, 16 for D = 4, whose interpolation takes one
-                             wavefront per node) */
+                             into items of at most this many), 0 = automatic (D <= 3: 1024,
+                             512 in 1-D/2-D when the tiles hold <= 512 nodes on average;
+                             16 for D = 4, whose interpolation takes one wavefront per
+                             node) */
     int wide;             /* 1: (2m+2)^D-point stencil with the untruncated window, sampled
                              beyond its truncation interval (the alternative of subsection
                              "Window Size Considerations"); 0 (default): 2m points.  Not

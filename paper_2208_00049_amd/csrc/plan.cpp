@@ -20,11 +20,15 @@ namespace {
 
 constexpr int kMaxM = 10;
 constexpr size_t kLdsBudget = 65536;
-// Default cap on a work item's nodes, per D: 1-D/2-D dense tiles (a radial
-// trajectory's centre) split at 512 nodes balance best; 3-D tiles hold ~512 nodes
-// on average at sigma = 2 and keep 1024; D = 4 interpolates one node per
-// wavefront, so small items spread a tile's nodes over many workgroups.
-constexpr int kDefaultBlockNodes[5] = {0, 512, 512, 1024, 16};
+// Default cap on a work item's nodes, per D.  1-D/2-D: 1024, or 512 when the
+// tiles hold at most 512 nodes on average -- then only locally dense tiles (a
+// radial trajectory's centre) are split, and smaller pieces balance them better,
+// while uniformly dense node sets keep fewer items per tile (each extra item adds
+// a padded tile to every halo merge).  3-D tiles hold ~512 nodes on average at
+// sigma = 2 and keep 1024.  D = 4 interpolates one node per wavefront, so small
+// items spread a tile's nodes over many workgroups.
+constexpr int kDefaultBlockNodes[5] = {0, 1024, 1024, 1024, 16};
+constexpr int kSparseBlockNodes = 512;
 constexpr int kMaxChannels = 65535;  // channels of one multi-channel call (grid y dimension)
 
 bool is_235_smooth(int64_t v) {
@@ -466,6 +470,8 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
             p->geom.ntiles *= p->geom.T[d];
         }
         p->nkeys = p->geom.ntiles << D;
+        if (!(opts && opts->max_block_nodes) && D <= 2 && M <= (int64_t)kSparseBlockNodes * p->geom.ntiles)
+            p->max_block_nodes = kSparseBlockNodes;
         subs_cap = p->geom.ntiles + M / p->max_block_nodes + 1;
     }
     TRY(hipMalloc(&p->grid, (size_t)p->G * cs));
