@@ -104,3 +104,18 @@ def test_adjoint_is_bitwise_reproducible(device, dt):
     for _ in range(3):
         b = p.adjoint(to_dev(fh, dt, device))
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_two_plans_of_the_same_nodes_agree_bitwise(device, dt):
+    """The bin sort is stable, so two plans of one node set have the same work items --
+    also where dense tiles are split (the radial centre) -- and give identical results."""
+    N, m, sigma = (512, 512), 4, 2.0
+    x = wl.workload_nodes("2d_n512_radial402x652")
+    f = wl.cn01(N, config=1, stream=1)
+    fh = wl.cn01((x.shape[0],), config=1, stream=2)
+    p1, _ = make_plan(device, x, N, m, sigma, dt, max_block_nodes=100)  # many split tiles
+    p2, _ = make_plan(device, x, N, m, sigma, dt, max_block_nodes=100)
+    print("two plans", dt, flush=True)
+    assert torch.equal(p1.adjoint(to_dev(fh, dt, device)), p2.adjoint(to_dev(fh, dt, device)))
+    assert torch.equal(p1.forward(to_dev(f, dt, device)), p2.forward(to_dev(f, dt, device)))
