@@ -164,11 +164,15 @@ int nfft_adjoint_many(nfft_plan_t p, int K, const void *fhat, void *y, void *str
 /*
  * Derivatives with respect to the nodes (for differentiable use).
  *   nfft_forward_deriv: dfhat[d][j] ~= sum_{n in I_N} (-2 pi i n_d) f_n exp(-2 pi i n.x_j),
- *     the partial derivative of the forward transform's output j along axis d,
- *     computed as D forward NFFTs of the coefficients -2 pi i n_d f_n (one
- *     multi-channel call that reads f once; the factor is applied in the
- *     resampling-correction pass).  f: prod(N) complex; dfhat: D x M complex
- *     (axis-major), device.  Uses the plan's multi-channel buffers (K = D).
+ *     the partial derivative of the forward transform's output j along axis d.
+ *     With the polynomial window and D <= 3 it is the derivative of the NFFT
+ *     itself: one resampling correction + FFT of f, then interpolation with the
+ *     derivative of the window along axis d (Nt_d P'_t(frac - 1/2)) -- the exact
+ *     gradient of what nfft_forward computes.  Otherwise it is D forward NFFTs of
+ *     the coefficients -2 pi i n_d f_n (one multi-channel call that reads f once;
+ *     the factor is applied in the resampling-correction pass; uses the plan's
+ *     multi-channel buffers, K = D).  f: prod(N) complex; dfhat: D x M complex
+ *     (axis-major), device.
  *   nfft_node_grad: grad_x[j*D + d] = Re(conj(a_j) dfhat[d][j]) for j < M, d < D
  *     (a: M complex; grad_x: M x D reals of the plan's real type, node-major like
  *     the nodes).  With a = the gradient of a real loss with respect to the

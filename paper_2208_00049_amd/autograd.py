@@ -8,11 +8,14 @@ z is 2 dL/d conj(z)):
 * adjoint  y = A(x)^H fhat:  grad_fhat = A g,
   grad_x[j, d] = Re(conj(fhat_j) dA_d g_j);
 
-with g the incoming gradient.  dA_d is the forward NFFT of the coefficients
--2 pi i n_d f_n (D channels in one multi-channel call, the factor applied in
-the library's resampling-correction pass), i.e. the derivative of the NDFT
-(subsection "NDFT" of "Mathematical Description", the definition of the NDFT)
-evaluated with the same NFFT approximation as the transform itself.
+with g the incoming gradient.  dA_d f is the library's nfft_forward_deriv: with
+the polynomial window (D <= 3) the derivative of the NFFT itself -- the
+oversampled spectrum interpolated with the derivative of the window along axis
+d, so the gradients are exact for the function the forward pass computes;
+otherwise the forward NFFT of the coefficients -2 pi i n_d f_n (the derivative
+of the NDFT, subsection "NDFT" of "Mathematical Description", evaluated with the
+NFFT approximation).  Both agree with the NDFT's derivative to about the
+transform's accuracy.
 
 The nodes are fixed when a plan is built; the functions here take the plan
 and the node tensor it was built from (the tensor carries the gradient).

@@ -221,6 +221,8 @@ hipError_t launch_node_grad(const nfft_plan_s &p, const void *a, const void *v, 
 // K channels: grids at stride G, fhat at stride M, padded tiles at stride pad_elems()
 hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
                          int K = 1);
+// derivative-of-window interpolation, D <= 3 with the polynomial window: dfhat D x M
+hipError_t launch_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat, hipStream_t s);
 // merge = false: only the padded tiles are produced (the next pass merges them)
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                          bool merge = true, int K = 1, void *pad = nullptr);

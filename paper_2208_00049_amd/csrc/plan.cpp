@@ -842,6 +842,12 @@ int nfft_forward_deriv(nfft_plan_t p, const void *f, void *dfhat, void *stream) 
     if (!p || !f || (p->M > 0 && !dfhat)) return NFFT_ERR_ARG;
     if (p->M == 0) return NFFT_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (p->window == NFFT_WINDOW_POLY && p->D <= 3) {
+        // derivative-of-window interpolation of the one oversampled spectrum
+        hipError_t e = forward_fft(*p, f, p->grid, 1, s);
+        if (e == hipSuccess) e = launch_interp_deriv(*p, p->grid, dfhat, s);
+        return hip_rc(e);
+    }
     hipError_t e = ensure_channels(*p, p->D);
     if (e == hipSuccess) e = forward_fft(*p, f, p->grid_many, p->D, s, true);
     if (e == hipSuccess) e = launch_interp(*p, p->grid_many, dfhat, s, p->D);

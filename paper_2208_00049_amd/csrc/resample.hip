@@ -33,6 +33,17 @@ static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, h
 }
 
 template <typename T>
+static hipError_t interp_deriv_t(const nfft_plan_s &p, const void *grid, void *dfhat,
+                                 hipStream_t s) {
+    switch (p.D) {
+        case 1: NFFT_DISPATCH_M(run_interp_deriv, T, 1, p, grid, dfhat, s)
+        case 2: NFFT_DISPATCH_M(run_interp_deriv, T, 2, p, grid, dfhat, s)
+        case 3: NFFT_DISPATCH_M(run_interp_deriv, T, 3, p, grid, dfhat, s)
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
 static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                            bool merge, int K, void *pad) {
     switch (p.D) {
@@ -48,6 +59,13 @@ hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hip
     if (p.nsub == 0) return hipSuccess;
     return p.dtype == NFFT_C64 ? interp_t<float>(p, grid, fhat, s, K)
                                : interp_t<double>(p, grid, fhat, s, K);
+}
+
+hipError_t launch_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat, hipStream_t s) {
+    if (p.nsub == 0) return hipSuccess;
+    if (p.window != NFFT_WINDOW_POLY || p.D > 3) return hipErrorInvalidValue;
+    return p.dtype == NFFT_C64 ? interp_deriv_t<float>(p, grid, dfhat, s)
+                               : interp_deriv_t<double>(p, grid, dfhat, s);
 }
 
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,

@@ -82,6 +82,21 @@ __device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, c
     return s > (T)0 ? sinh(beta * s) / ((T)M_PI * s) : beta / (T)M_PI;
 }
 
+// Polynomial window weight of a tap and its derivative in frac (one Horner pass
+// for both: P(z) and P'(z) at z = frac - 1/2).
+template <typename T, int M2>
+__device__ inline T poly_weight_d(const T *cf, T frac, T &dw) {
+    const T z = frac - (T)0.5;
+    T p = cf[M2], dp = (T)0;
+#pragma unroll
+    for (int k = M2 - 1; k >= 0; --k) {
+        dp = fma(dp, z, p);
+        p = fma(p, z, cf[k]);
+    }
+    dw = dp;
+    return p;
+}
+
 // ---- lane exchange within a group of G lanes -------------------------------
 
 // DPP control words (GFX9): quad_perm(p0,p1,p2,p3), row_shl:n, row_shr:n.
@@ -247,7 +262,12 @@ __device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, in
     }
 }
 
-template <typename T, int D, int M2, bool GW>
+// DV = true (polynomial window only): instead of fhat, the D partial derivatives
+// of the interpolated value with respect to the node's coordinates -- the
+// derivative-of-window interpolation d fhat_j / d x_jd = sum over the stencil of
+// Nt_d P'_{t_d}(frac_d - 1/2) prod_{e != d} P_{t_e} times the grid value -- written
+// to fhat[d * fstride + j].
+template <typename T, int D, int M2, bool GW, bool DV = false>
 __global__ void __launch_bounds__(kResampleThreads)
     k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
@@ -368,6 +388,79 @@ __global__ void __launch_bounds__(kResampleThreads)
                 fr[d] = st.fr[d][ks];
             }
             const long long gk = c0 + ks;  // sorted position of the node
+            if constexpr (DV) {
+                T dw[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) w[d] = poly_weight_d<T, M2>(lw.cf[d], fr[d], dw[d]);
+                T orr[D], oi[D];  // d/dx_d, real and imaginary parts
+                if constexpr (D == 1) {
+                    const C v = tile[l[0] + li];
+                    orr[0] = dw[0] * v.x;
+                    oi[0] = dw[0] * v.y;
+                } else if constexpr (D == 2) {
+                    T w0[M2], dw0[M2];
+                    BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                    BcastAll<M2, 0, T>::run(dw0, dw[0], gbase);
+                    const C *row = tile + l[0] * P[1] + l[1] + li;
+                    T sr = (T)0, si = (T)0, dr = (T)0, di = (T)0;
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) {
+                        const C v = row[a * P[1]];
+                        sr = fma(w0[a], v.x, sr);
+                        si = fma(w0[a], v.y, si);
+                        dr = fma(dw0[a], v.x, dr);
+                        di = fma(dw0[a], v.y, di);
+                    }
+                    orr[0] = dr * w[1];
+                    oi[0] = di * w[1];
+                    orr[1] = sr * dw[1];
+                    oi[1] = si * dw[1];
+                } else {
+                    T w0[M2], dw0[M2], w1[M2], dw1[M2];
+                    BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                    BcastAll<M2, 0, T>::run(dw0, dw[0], gbase);
+                    BcastAll<M2, 0, T>::run(w1, w[1], gbase);
+                    BcastAll<M2, 0, T>::run(dw1, dw[1], gbase);
+                    const C *base3 = tile + (l[0] * P[1] + l[1]) * P[2] + l[2] + li;
+                    T a0r = (T)0, a0i = (T)0, a1r = (T)0, a1i = (T)0, a2r = (T)0, a2i = (T)0;
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) {
+                        T rr = (T)0, ri = (T)0, qr = (T)0, qi = (T)0;
+                        const C *rowp = base3 + a * P[1] * P[2];
+#pragma unroll
+                        for (int b = 0; b < M2; ++b) {
+                            const C v = rowp[b * P[2]];
+                            rr = fma(w1[b], v.x, rr);
+                            ri = fma(w1[b], v.y, ri);
+                            qr = fma(dw1[b], v.x, qr);
+                            qi = fma(dw1[b], v.y, qi);
+                        }
+                        a0r = fma(dw0[a], rr, a0r);
+                        a0i = fma(dw0[a], ri, a0i);
+                        a1r = fma(w0[a], qr, a1r);
+                        a1i = fma(w0[a], qi, a1i);
+                        a2r = fma(w0[a], rr, a2r);
+                        a2i = fma(w0[a], ri, a2i);
+                    }
+                    orr[0] = a0r * w[2];
+                    oi[0] = a0i * w[2];
+                    orr[1] = a1r * w[2];
+                    oi[1] = a1i * w[2];
+                    orr[2] = a2r * dw[2];
+                    oi[2] = a2i * dw[2];
+                }
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    orr[d] = group_sum<M2>(orr[d], li);
+                    oi[d] = group_sum<M2>(oi[d], li);
+                }
+                if (valid && li == 0)
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        fhat[(long long)d * fstride + st.idx[ks]] =
+                            cmake<C>(orr[d] * (T)g.Nt[d], oi[d] * (T)g.Nt[d]);
+                continue;
+            }
             node_weights<GW, T, D, M2>(w, lw, fr, gk, li, window, wp);
             T ar = (T)0, ai = (T)0;
             if constexpr (D == 1) {
@@ -771,6 +864,21 @@ hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStr
     hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
+                       (long long)p.G, (long long)p.M);
+    return hipGetLastError();
+}
+
+// Derivative-of-window interpolation (polynomial window): dfhat is D x M complex.
+template <typename T, int D, int M2>
+hipError_t run_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat, hipStream_t s) {
+    if (p.nsub == 0) return hipSuccess;
+    const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
+    auto kern = k_interp<T, D, M2, false, true>;
+    hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(p.nsub, 1), dim3(kResampleThreads), shm, s,
+                       (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
+                       p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)dfhat,
                        (long long)p.G, (long long)p.M);
     return hipGetLastError();
 }

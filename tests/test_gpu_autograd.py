@@ -137,3 +137,46 @@ def test_gradcheck_small(device):
     # f-gradient; the node gradient is checked against the NDFT above
     assert torch.autograd.gradcheck(lambda ff: nfft(x, ff, plan=plan), (f,), eps=1e-6, atol=1e-7,
                                     rtol=1e-6)
+
+
+@pytest.mark.parametrize("N,dt,m,gate", [((256,), "c128", 4, 1e-5), ((32, 48), "c64", 4, 2e-5),
+                                         ((32, 48), "c128", 6, 1e-8), ((16, 12, 20), "c128", 4, 1e-5),
+                                         ((16, 12, 20), "c64", 3, 3e-4)])
+def test_forward_deriv_both_methods_match_ndft(device, N, dt, m, gate):
+    """nfft_forward_deriv with the polynomial window interpolates with the window's
+    derivative (the exact gradient of the NFFT); with DIRECT it runs D NFFTs of
+    -2 pi i n_d f.  Both approximate the NDFT derivative within (about) the NFFT's
+    own accuracy, relative-l2 over the D x M outputs."""
+    from paper_2208_00049_amd import Plan
+    M = 3000
+    x = wl.uniform_nodes(M, len(N), config=4, stream=8)
+    rdt = torch.float64 if dt == "c128" else torch.float32
+    cdt = torch.complex128 if dt == "c128" else torch.complex64
+    xt = torch.tensor(x, dtype=rdt, device=device)
+    xs = xt.double().cpu().numpy()
+    ft = torch.tensor(wl.cn01(N, config=4, stream=9), dtype=cdt, device=device)
+    f = ft.cpu().numpy().astype(np.complex128)
+    ref = ndft_deriv(xs, f, N)
+    got_poly = Plan(xt, N, m=m, sigma=2.0).forward_deriv(ft).cpu().numpy()
+    got_direct = Plan(xt, N, m=m, sigma=2.0, window="direct").forward_deriv(ft).cpu().numpy()
+    print("deriv", N, dt, m, rel2(got_poly, ref), rel2(got_direct, ref), flush=True)
+    assert rel2(got_poly, ref) < gate
+    assert rel2(got_direct, ref) < gate
+
+
+def test_gradcheck_nodes(device):
+    """With the polynomial window the node gradient is the exact derivative of the computed
+    NFFT (derivative-of-window interpolation), so torch.autograd.gradcheck passes for the
+    nodes too (FP64, m = 8: the truncated window's jump at the support edge, beta/sinh(beta)
+    of its peak, is far below the finite-difference tolerance)."""
+    from paper_2208_00049_amd.autograd import nfft, nfft_adjoint
+    N = (16, 16)
+    x = torch.tensor(wl.uniform_nodes(12, 2, config=4, stream=10), dtype=torch.float64,
+                     device=device, requires_grad=True)
+    f = torch.tensor(wl.cn01(N, config=4, stream=11), dtype=torch.complex128, device=device)
+    fh = torch.tensor(wl.cn01((12,), config=4, stream=12), dtype=torch.complex128, device=device)
+    # a plan is built per call from the perturbed nodes (plan=None)
+    assert torch.autograd.gradcheck(lambda xx: nfft(xx, f, m=8), (x,), eps=1e-6, atol=1e-6,
+                                    rtol=1e-5)
+    assert torch.autograd.gradcheck(lambda xx: nfft_adjoint(xx, fh, N, m=8), (x,), eps=1e-6,
+                                    atol=1e-6, rtol=1e-5)
