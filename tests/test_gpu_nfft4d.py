@@ -143,3 +143,26 @@ def test_d4_forward_derivative(device):
     idx = np.meshgrid(*[np.arange(n) - n // 2 for n in N], indexing="ij")
     want = np.stack([ndft.ndft_forward(xs, (-2j * np.pi) * idx[d] * f) for d in range(4)])
     assert rel2(got, want) < NDFT_GATE[(3, 2.0)] * 10
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M,m", [((8, 8, 8, 8), 2000, 4), ((7, 6, 9, 8), 1500, 3)])
+def test_d4_single_steps_match_oracle(device, dt, N, M, m):
+    """The steps on their own: resampling forward/adjoint against the oracle's resampling on
+    the same oversampled grid, and the 4-D FFT of the grid against numpy."""
+    from test_gpu_nfft import C128_VS_ORACLE, C64_VS_ORACLE
+    x = wl.uniform_nodes(M, 4, config=129, stream=0)
+    p, xs = make_plan(device, x, N, m, 2.0, dt)
+    Nt = p.Ntilde
+    ghat = wl.cn01(Nt, config=129, stream=1)
+    fh = wl.cn01((M,), config=129, stream=2)
+    tol = C128_VS_ORACLE if dt == "c128" else C64_VS_ORACLE
+    got = p.resample_forward(to_dev(ghat, dt, device)).cpu().numpy()
+    assert rel2(got, na.resample_forward(xs, ghat, N, m, Nt)) < tol
+    spread = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    assert rel2(spread, na.resample_adjoint(xs, fh, N, m, Nt)) < tol
+    ftol = 1e-13 if dt == "c128" else 2e-6
+    fw = p.fft_grid(to_dev(ghat, dt, device), -1).cpu().numpy()
+    assert rel2(fw, np.fft.fftn(ghat)) < ftol
+    bw = p.fft_grid(to_dev(ghat, dt, device), +1).cpu().numpy()
+    assert rel2(bw, np.fft.ifftn(ghat) * ghat.size) < ftol
