@@ -71,8 +71,9 @@ def nfft(x, f, plan=None, m=4, sigma=2.0):
     return _Forward.apply(f, x, plan)
 
 
-def nfft_adjoint(x, fhat, N, plan=None, m=4, sigma=2.0):
-    """Differentiable adjoint NFFT (with respect to fhat and the nodes x)."""
+def nfft_adjoint(x, N, fhat, plan=None, m=4, sigma=2.0):
+    """Differentiable adjoint NFFT (with respect to fhat and the nodes x); the argument order
+    is that of the package's nfft_adjoint."""
     if plan is None:
         plan = Plan(x.detach(), tuple(N), m=m, sigma=sigma)
     return _Adjoint.apply(fhat, x, plan)

@@ -91,7 +91,7 @@ def test_adjoint_gradients_match_ndft(device, dt, m):
     plan = Plan(xt, N, m=m, sigma=2.0)
     x_req = xt.clone().requires_grad_(True)
     fh_req = fht.clone().requires_grad_(True)
-    loss = (nfft_adjoint(x_req, fh_req, N, plan=plan) - zt).abs().pow(2).sum()
+    loss = (nfft_adjoint(x_req, N, fh_req, plan=plan) - zt).abs().pow(2).sum()
     loss.backward()
     s = ndft.ndft_adjoint(xs, fh, N) - z
     gfh_ref = 2 * ndft.ndft_forward(xs, s)
@@ -178,5 +178,5 @@ def test_gradcheck_nodes(device):
     # a plan is built per call from the perturbed nodes (plan=None)
     assert torch.autograd.gradcheck(lambda xx: nfft(xx, f, m=8), (x,), eps=1e-6, atol=1e-6,
                                     rtol=1e-5)
-    assert torch.autograd.gradcheck(lambda xx: nfft_adjoint(xx, fh, N, m=8), (x,), eps=1e-6,
+    assert torch.autograd.gradcheck(lambda xx: nfft_adjoint(xx, N, fh, m=8), (x,), eps=1e-6,
                                     atol=1e-6, rtol=1e-5)
