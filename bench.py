@@ -81,8 +81,8 @@ PROFILE_TAG = {("2d_n512_m262144_uniform", "c64"): "n512_m262144_c64_uniform",
 
 # stage name -> kernel whose launch the stage times (when one kernel makes the stage)
 STAGE_KERNEL = {
-    (2, "c64"): {"spread": "nfft::k_spread<float, 2, 8, false>",
-                 "interp": "nfft::k_interp<float, 2, 8, false, false>"},
+    (2, "c64"): {"spread": "nfft::k_spread<float, 2, 8, false, 256>",
+                 "interp": "nfft::k_interp<float, 2, 8, false, false, 256>"},
     (4, "c64"): {"spread": "nfft::k_spread_owner<float, 4, 8>",
                  "interp": "nfft::k_interp_node<float, 4, 8>"},
 }

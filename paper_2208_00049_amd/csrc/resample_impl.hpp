@@ -267,8 +267,8 @@ __device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, in
 // derivative-of-window interpolation d fhat_j / d x_jd = sum over the stencil of
 // Nt_d P'_{t_d}(frac_d - 1/2) prod_{e != d} P_{t_e} times the grid value -- written
 // to fhat[d * fstride + j].
-template <typename T, int D, int M2, bool GW, bool DV = false>
-__global__ void __launch_bounds__(kResampleThreads)
+template <typename T, int D, int M2, bool GW, bool DV = false, int NT = kResampleThreads>
+__global__ void __launch_bounds__(NT)
     k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
              const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat,
@@ -296,13 +296,13 @@ __global__ void __launch_bounds__(kResampleThreads)
     }
     // the first chunk's node loads go out before the tile copy, so that both
     // latencies overlap (the chunk is written to LDS after the copy)
-    constexpr int SJ = (CH + kResampleThreads - 1) / kResampleThreads;
+    constexpr int SJ = (CH + NT - 1) / NT;
     NodeRec<T, D> rec[SJ];
     int pm[SJ];
     auto load_chunk = [&](int c0, int n) {
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
-            const int node = c0 + min((int)threadIdx.x + j * kResampleThreads, n - 1);
+            const int node = c0 + min((int)threadIdx.x + j * NT, n - 1);
             rec[j] = nodes[node];
             pm[j] = perm[node];
         }
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     auto store_chunk = [&](int n) {
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
-            const int k = threadIdx.x + j * kResampleThreads;
+            const int k = threadIdx.x + j * NT;
             if (k < n) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
@@ -332,12 +332,12 @@ __global__ void __launch_bounds__(kResampleThreads)
         const float rl = 1.0f / (float)P[D - 1];
         const float r1 = D == 3 ? 1.0f / (float)P[1] : 1.0f;
         constexpr int U = 8;
-        for (int base = 0; base < total; base += U * kResampleThreads) {
+        for (int base = 0; base < total; base += U * NT) {
             C v[U];
             int dst[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int idx = base + u * kResampleThreads + threadIdx.x;
+                const int idx = base + u * NT + threadIdx.x;
                 dst[u] = idx < total ? idx : -1;
                 int col;
                 const int row = small_divmod(idx < total ? idx : 0, P[D - 1], rl, col);
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kResampleThreads)
         if (c0 > sp.y) load_chunk(c0, n);
         store_chunk(n);
         __syncthreads();  // also completes the tile copy on the first chunk
-        for (int base = wave * NPW; base < n; base += (kResampleThreads / 64) * NPW) {
+        for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
             const int k = base + grp;
             const bool valid = grp < NPW && k < n;
             const int ks = valid ? k : 0;
@@ -566,8 +566,8 @@ template <> struct FixedPoint<double> {
 // the tile extended by the (2m-1)-wide trailing halo, in LDS, and writes that
 // padded tile to its own slot of the scratch buffer.  Every node's stencil lies
 // inside the padded tile, so the tap loops carry no bounds tests.
-template <typename T, int D, int M2, bool GW>
-__global__ void __launch_bounds__(kResampleThreads)
+template <typename T, int D, int M2, bool GW, int NT = kResampleThreads>
+__global__ void __launch_bounds__(NT)
     k_spread(cplx<T> *__restrict__ pad, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
              const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(kResampleThreads)
 #pragma unroll
     for (int d = 0; d < D; ++d) ptot *= P[d];
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
-    for (int i = threadIdx.x; i < SL * ptot; i += kResampleThreads) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < SL * ptot; i += NT) acc[i] = 0ull;
     if (threadIdx.x == 0) amax_bits = 0ull;
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -610,14 +610,14 @@ __global__ void __launch_bounds__(kResampleThreads)
     // Stage the chunk of nodes [c0, c0 + n) into LDS: all global loads of the
     // thread's nodes are issued before the first one is waited for (indices are
     // clamped into the item, so the loads need no guard); returns max |Re|, |Im|.
-    constexpr int SJ = (CH + kResampleThreads - 1) / kResampleThreads;
+    constexpr int SJ = (CH + NT - 1) / NT;
     auto stage_chunk_nodes = [&](int c0, int n) -> T {
         NodeRec<T, D> rec[SJ];
         int pm[SJ];
         C val[SJ];
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
-            const int node = c0 + min(threadIdx.x + j * kResampleThreads, n - 1);
+            const int node = c0 + min(threadIdx.x + j * NT, n - 1);
             rec[j] = nodes[node];
             pm[j] = perm[node];
         }
@@ -626,7 +626,7 @@ __global__ void __launch_bounds__(kResampleThreads)
         T mx = (T)0;
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
-            const int k = threadIdx.x + j * kResampleThreads;
+            const int k = threadIdx.x + j * NT;
             if (k < n) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
@@ -644,7 +644,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     // pass over the item's nodes for the scale; the first chunk is staged on the way
     const int nitem = sp.z - sp.y;
     T amax = stage_chunk_nodes(sp.y, min(CH, nitem));
-    for (int v = CH + threadIdx.x; v < nitem; v += kResampleThreads) {
+    for (int v = CH + threadIdx.x; v < nitem; v += NT) {
         const C val = fhat[perm[sp.y + v]];
         amax = fmax(amax, fmax(fabs(val.x), fabs(val.y)));
     }
@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(kResampleThreads)
             (void)stage_chunk_nodes(c0, n);
             __syncthreads();
         }
-        for (int base = wave * NPW; base < n; base += (kResampleThreads / 64) * NPW) {
+        for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
             const int k = base + grp;
             const bool valid = grp < NPW && k < n;
             const int ks = valid ? k : 0;
@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(kResampleThreads)
     // the padded tile goes to the item's scratch slot, unscaled
     const T inv = (T)(1.0 / (double)scale);
     C *out = pad + (size_t)blockIdx.x * ptot;
-    for (int idx = threadIdx.x; idx < ptot; idx += kResampleThreads) {
+    for (int idx = threadIdx.x; idx < ptot; idx += NT) {
         const unsigned long long *ap = acc + idx;
         out[idx] = cmake<C>((T)FP::read(ap, ptot, 0) * inv, (T)FP::read(ap, ptot, 1) * inv);
     }
@@ -853,15 +853,26 @@ template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
     return wp;
 }
 
+// Workgroup size of the tiled resampling kernels: 256 threads, 512 for 3-D
+// complex128, whose large LDS tiles (the fixed-point accumulators of a 15^3
+// padded tile take 108 KB) leave room for one or two workgroups per CU -- twice
+// the wavefronts then hide more of the load latency (measured on the 3-D
+// 128^3 workload: interpolation 1.02 -> 0.76 ms, spreading 3.11 -> 2.72 ms; no
+// gain where LDS already admits four workgroups).
+template <typename T, int D> constexpr int resample_threads() {
+    return (sizeof(T) == 8 && D == 3) ? 512 : kResampleThreads;
+}
+
 template <typename T, int D, int M2>
 hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
+    constexpr int NT = resample_threads<T, D>();
     const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
     const bool gw = p.window != NFFT_WINDOW_POLY;
-    auto kern = gw ? k_interp<T, D, M2, true> : k_interp<T, D, M2, false>;
+    auto kern = gw ? k_interp<T, D, M2, true, false, NT> : k_interp<T, D, M2, false, false, NT>;
     hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
+    hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(NT), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
                        (long long)p.G, (long long)p.M);
@@ -872,11 +883,12 @@ hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStr
 template <typename T, int D, int M2>
 hipError_t run_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat, hipStream_t s) {
     if (p.nsub == 0) return hipSuccess;
+    constexpr int NT = resample_threads<T, D>();
     const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
-    auto kern = k_interp<T, D, M2, false, true>;
+    auto kern = k_interp<T, D, M2, false, true, NT>;
     hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(p.nsub, 1), dim3(kResampleThreads), shm, s,
+    hipLaunchKernelGGL(kern, dim3(p.nsub, 1), dim3(NT), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)dfhat,
                        (long long)p.G, (long long)p.M);
@@ -896,11 +908,12 @@ hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStr
             // window maximum psi_hat_Base(0) = sinh(beta)/pi, with margin for the polynomial fit
             wprod *= 1.5 * sinh(beta) / M_PI;
         }
+        constexpr int NT = resample_threads<T, D>();
         const bool gw = p.window != NFFT_WINDOW_POLY;
-        auto kern = gw ? k_spread<T, D, M2, true> : k_spread<T, D, M2, false>;
+        auto kern = gw ? k_spread<T, D, M2, true, NT> : k_spread<T, D, M2, false, NT>;
         hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(kResampleThreads), shm, s,
+        hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(NT), shm, s,
                            (cplx<T> *)pad, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                            p.subs, (const T *)p.coef, p.window, win_params<T>(p), (T)wprod,
                            (const cplx<T> *)fhat, pstride, (long long)p.M);
