@@ -57,10 +57,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(workload, dtype, kernel_name):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary of this workload, or None if there is none or the kernel sources have changed
-    since it was taken."""
+def stored_traffic(workload, dtype, kernel_names):
+    """HBM bytes per launch of a stage's kernels (summed) from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary of this workload, or None if there is none or the kernel
+    sources have changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "nfft%s_%s_traffic.json" % (workload[:2], PROFILE_TAG.get(
         (workload, dtype), "")))
     if not os.path.exists(path):
@@ -69,22 +69,29 @@ def stored_traffic(workload, dtype, kernel_name):
         rec = json.load(fh)
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    k = rec["kernels"].get(kernel_name)
-    if k is None:
-        return None
-    return k["fetch_bytes"] + k["write_bytes"]
+    total = 0.0
+    for name in kernel_names:
+        k = rec["kernels"].get(name)
+        if k is None:
+            return None
+        total += k["fetch_bytes"] + k["write_bytes"]
+    return total
 
 
 # profile summary file tag per (workload, dtype)
 PROFILE_TAG = {("2d_n512_m262144_uniform", "c64"): "n512_m262144_c64_uniform",
+               ("3d_n128_m2097152_uniform", "c64"): "n128_m2097152_c64_uniform",
                ("4d_n16_m65536_uniform", "c64"): "n16_m65536_c64_uniform"}
 
-# stage name -> kernel whose launch the stage times (when one kernel makes the stage)
+# stage name -> the kernels one back-to-back launch of the stage runs (in 3-D spreading
+# includes the halo merge kernel; in 2-D the merge is part of the adjoint's first FFT pass)
 STAGE_KERNEL = {
-    (2, "c64"): {"spread": "nfft::k_spread<float, 2, 8, false, 256>",
-                 "interp": "nfft::k_interp<float, 2, 8, false, false, 256>"},
-    (4, "c64"): {"spread": "nfft::k_spread_owner<float, 4, 8>",
-                 "interp": "nfft::k_interp_node<float, 4, 8>"},
+    (2, "c64"): {"spread": ["nfft::k_spread<float, 2, 8, false, 256>"],
+                 "interp": ["nfft::k_interp<float, 2, 8, false, false, 256>"]},
+    (3, "c64"): {"spread": ["nfft::k_spread<float, 3, 8, false, 512>", "nfft::k_spread_merge<float, 3>"],
+                 "interp": ["nfft::k_interp<float, 3, 8, false, false, 512>"]},
+    (4, "c64"): {"spread": ["nfft::k_spread_owner<float, 4, 8>"],
+                 "interp": ["nfft::k_interp_node<float, 4, 8>"]},
 }
 
 
@@ -549,11 +556,12 @@ def main():
         dom_ms = b2b[dominant]
     ach = algo[dominant] / (dom_ms * 1e-3) / 1e9
     traffic = None
-    kname = (STAGE_KERNEL.get((w["D"], args.dtype), {}).get(dominant)
-             if args.m == 4 and args.window == "poly" and not args.wide else None)
-    if kname:
-        traffic = stored_traffic(args.workload, args.dtype, kname)
-    roofline = {"bound": "hbm", "kernel": kname or dominant, "achieved": round(ach, 1),
+    knames = (STAGE_KERNEL.get((w["D"], args.dtype), {}).get(dominant)
+              if args.m == 4 and args.window == "poly" and not args.wide else None)
+    if knames:
+        traffic = stored_traffic(args.workload, args.dtype, knames)
+    roofline = {"bound": "hbm", "kernel": " + ".join(knames) if knames else dominant,
+                "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": round(traffic) if traffic is not None else None,
                 "algorithmic_bytes": algo[dominant], "launch_ms": round(dom_ms, 5)}

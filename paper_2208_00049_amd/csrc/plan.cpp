@@ -450,8 +450,14 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         if (D == 4) {
             trc = choose_tiles_4d(p->Nt, taps, dtype, req, (size_t)dev_lds, Q);
         } else {
-            trc = choose_tiles(D, p->Nt, taps, dtype, req, kLdsBudget, Q);
-            if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds > kLdsBudget)
+            // sparse 3-D node sets (under 1/4 node per grid point, e.g. sigma = 2 with
+            // M = |I_N|) take the larger 8 x 16 x 16 tiles that need the device's whole
+            // LDS: the padded-tile scratch per node is what dominates there
+            const bool sparse3d = D == 3 && 4 * M < p->G;
+            const size_t first = sparse3d && (size_t)dev_lds > kLdsBudget ? (size_t)dev_lds - 1024
+                                                                           : kLdsBudget;
+            trc = choose_tiles(D, p->Nt, taps, dtype, req, first, Q);
+            if (trc == NFFT_ERR_UNSUPPORTED && (size_t)dev_lds - 1024 > first)
                 trc = choose_tiles(D, p->Nt, taps, dtype, req, (size_t)dev_lds - 1024, Q);
         }
         if (trc != NFFT_OK) {

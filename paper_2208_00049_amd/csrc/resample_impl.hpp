@@ -853,14 +853,15 @@ template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
     return wp;
 }
 
-// Workgroup size of the tiled resampling kernels: 256 threads, 512 for 3-D
-// complex128, whose large LDS tiles (the fixed-point accumulators of a 15^3
-// padded tile take 108 KB) leave room for one or two workgroups per CU -- twice
-// the wavefronts then hide more of the load latency (measured on the 3-D
-// 128^3 workload: interpolation 1.02 -> 0.76 ms, spreading 3.11 -> 2.72 ms; no
-// gain where LDS already admits four workgroups).
+// Workgroup size of the tiled resampling kernels: 256 threads, 512 in 3-D,
+// whose large LDS tiles (the fixed-point accumulators of a 15 x 23 x 23 padded
+// tile take 127 KB in c64, a 15^3 one 108 KB in c128) leave room for one or two
+// workgroups per CU -- twice the wavefronts then hide more of the load latency
+// (measured on the 3-D 128^3 workload: c128 interpolation 1.02 -> 0.76 ms and
+// spreading 3.11 -> 2.72 ms; c64 with 8 x 16 x 16 tiles 1.65 -> 1.43 ms per
+// pair).  In 2-D, where four or more workgroups fit, 512 threads were slower.
 template <typename T, int D> constexpr int resample_threads() {
-    return (sizeof(T) == 8 && D == 3) ? 512 : kResampleThreads;
+    return D == 3 ? 512 : kResampleThreads;
 }
 
 template <typename T, int D, int M2>

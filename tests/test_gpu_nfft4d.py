@@ -1,11 +1,11 @@
 """GPU parity of the four-dimensional transforms (D = 4) against the oracle.
 
 The method is dimension-agnostic (paper, subsection "Direct NFFT": tensor-
-product window, D-variate FFT).  For D = 4 the library resamples without LDS
-tiles -- interpolation reads the grid in device memory, one wavefront per node;
-spreading is output-driven, one thread per grid point summing the nodes that
-reach it -- and runs its FFT passes over four axes.  The oracle's NFFT is
-written for any D.
+product window, D-variate FFT).  For D = 4 the library interpolates with one
+wavefront per node reading the grid in device memory, spreads tile by tile (a
+workgroup owns a grid tile and sums, in LDS and in fixed point, the taps of the
+nodes whose stencils reach it) and runs its FFT passes over four axes.  The
+oracle's NFFT is written for any D.
 
 Tolerances are those of the 1-3-D tests (e2e_tol: rounding on the oversampled
 grid amplified by the resampling correction); against the NDFT the oracle's
