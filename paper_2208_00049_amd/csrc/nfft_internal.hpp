@@ -57,7 +57,11 @@ constexpr size_t owner_static_lds(int D, int taps, int rs) {
     return (size_t)owner_chunk_n(D, taps, rs) * (4 * (1 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
            4 * (2 * kOwnerMaxTiles + 1) + 256;
 }
-constexpr int kOwnerThreads = 512;  // workgroup of the tile-owner spreading kernel
+// Workgroup of the tile-owner spreading kernel: 1024 threads, 16 wavefronts per
+// CU (the tile's accumulators take most of the LDS, one workgroup fits per CU),
+// which hide the staging and box-walk latencies: 4-D 16^4 c64 spreading 770 -> 548
+// us, c128 1105 -> 872 us against 512 threads.
+constexpr int kOwnerThreads = 1024;
 // Bytes per grid point of its LDS tile: 64-bit fixed-point slots, 2 (c64) or 4 (c128).
 inline size_t owner_cell_bytes(int cs) { return cs == 8 ? 16 : 32; }
 
