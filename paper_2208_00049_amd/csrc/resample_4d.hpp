@@ -319,6 +319,9 @@ __global__ void __launch_bounds__(kResampleThreads)
         if constexpr (NWT > 64)
             wb = axis_weight<T, M2>(cb, window, wp, D, j, db, tb, pick<T, D>(rec.fr, db));
         T ar = (T)0, ai = (T)0;
+        // unrolled so that eight grid loads are in flight per wavefront (rolled, the
+        // loop waited for each load before issuing the next)
+#pragma unroll 8
         for (int k = 0; k < NK; ++k) {
             const int f = k * 64 + lane;
             const bool ok = f < NT;
