@@ -47,11 +47,16 @@ __host__ __device__ inline int owner_reach(const Geom &g, int d) {
 }
 constexpr int kOwnerMaxTiles = 81;  // candidate tiles of one workgroup (3^4)
 // Candidate nodes staged per round by the tile-owner kernels (their box weights
-// take at most about 16 KiB), and the kernels' static LDS: staged candidates
-// (sorted position and 3 ints per axis; D fractions, a value, the box weights),
-// the candidate-tile ranges and the scale word.
+// take at most about 32 KiB in c64, 16 KiB in c128, whose accumulator tile is
+// twice as large), and the kernels' static LDS: staged candidates (sorted
+// position and 3 ints per axis; D fractions, a value, the box weights), the
+// candidate-tile ranges and the scale word.  Every round ends in a barrier
+// behind the dependent loads node record -> perm -> fhat, so larger rounds
+// expose that latency less often (4-D c64, m = 4: 128 -> 256 candidates,
+// spreading 548 -> 520 us).
 constexpr int owner_chunk_n(int D, int taps, int rs) {
-    return 16384 / (D * taps * rs) >= 128 ? 128 : 16384 / (D * taps * rs) >= 64 ? 64 : 32;
+    const int w = (rs == 4 ? 32768 : 16384) / (D * taps * rs);
+    return w >= 256 ? 256 : w >= 128 ? 128 : w >= 64 ? 64 : 32;
 }
 constexpr size_t owner_static_lds(int D, int taps, int rs) {
     return (size_t)owner_chunk_n(D, taps, rs) * (4 * (1 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
