@@ -518,18 +518,20 @@ def main():
     # profiler runs, whose kernel statistics should hold the timed loop's kernels only)
     timing = None
     if not args.profile_only:
-        reps = max(5, min(args.steps, 50))
+        # 200 repetitions, or as many as fit in about 2 s
+        reps = max(5, min(200, int(2000.0 / max(ms_per_step, 1e-3))))
         fa = call_stats([lambda: plan.forward(ft, out=fout), lambda: plan.adjoint(fht, out=yout)],
                         reps)
         warm = call_stats([step], reps)[0]
-        cold = call_stats([step], min(reps, 10), flush_bytes=512 << 20)[0]
+        creps = min(reps, 50)
+        cold = call_stats([step], creps, flush_bytes=512 << 20)[0]
         us = lambda d: {k: round(v * 1e3, 3) for k, v in d.items()}
         timing = {"pair_us": us(warm), "pair_cold_us": us(cold), "fwd_us": us(fa[0]),
                   "adj_us": us(fa[1]),
                   "pts_s_fwd": round(w["M"] / (fa[0]["mean"] * 1e-3), 1),
                   "pts_s_adj": round(w["M"] / (fa[1]["mean"] * 1e-3), 1),
-                  "note": "events around each call on the plan's stream, %d repetitions; cold: "
-                          "a 512 MiB buffer written before each repetition" % reps}
+                  "note": "events around each call on the plan's stream, %d repetitions (cold: %d); "
+                          "cold: a 512 MiB buffer written before each repetition" % (reps, creps)}
 
     # per-kernel durations: a second pass of the same steps with stage events on
     plan.set_timing(True)
