@@ -60,7 +60,7 @@ constexpr int owner_chunk_n(int D, int taps, int rs) {
 }
 constexpr size_t owner_static_lds(int D, int taps, int rs) {
     return (size_t)owner_chunk_n(D, taps, rs) * (4 * (1 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
-           4 * (2 * kOwnerMaxTiles + 1) + 256;
+           4 * (2 * kOwnerMaxTiles + 3) + 256;
 }
 // Workgroup of the tile-owner spreading kernel: 1024 threads, 16 wavefronts per
 // CU (the tile's accumulators take most of the LDS, one workgroup fits per CU),
@@ -69,6 +69,29 @@ constexpr size_t owner_static_lds(int D, int taps, int rs) {
 constexpr int kOwnerThreads = 1024;
 // Bytes per grid point of its LDS tile: 64-bit fixed-point slots, 2 (c64) or 4 (c128).
 inline size_t owner_cell_bytes(int cs) { return cs == 8 ? 16 : 32; }
+
+// LDS layout of the tile-owner accumulators: strides per axis and the cells of
+// one accumulator plane.  A wavefront adds to a box spanning several rows (axis
+// D-2) and planes (axis D-3) of the tile at once; with a row-major 8^4 tile the
+// planes lie 64 cells apart, on the same LDS banks, and the 64-bit atomics of
+// one instruction collide 3.8-fold on average (a count over all node offsets).
+// Padding the rows by one cell and the planes by four brings that to 2.4, at
+// 19 % more LDS; the padded layout is used where it fits.
+struct OwnerLayout {
+    int S[kMaxD];
+    int cells;
+};
+inline OwnerLayout owner_layout(const Geom &g, int D, bool pad) {
+    OwnerLayout l{};
+    l.S[D - 1] = 1;
+    for (int d = D - 2; d >= 0; --d) {
+        l.S[d] = g.Q[d + 1] * l.S[d + 1];
+        if (pad && d == D - 2) l.S[d] += 1;
+        if (pad && d == D - 3) l.S[d] += 4;
+    }
+    l.cells = g.Q[0] * l.S[0];
+    return l;
+}
 
 // Cells of a tile extended by the (2m-1)-wide trailing halo of every axis.
 inline size_t padded_cells(const Geom &g, int D) {

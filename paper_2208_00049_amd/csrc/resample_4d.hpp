@@ -207,19 +207,16 @@ __device__ inline TapCoef<T, M2> owner_coef(const T *__restrict__ coef, int wind
 // live = false, w = 0 and an in-range cell.  The candidate's box parameters are
 // uniform over the wavefront (scalar registers), the walk has no branches.
 template <typename T, int D, int M2, typename F>
-__device__ inline void owner_box(const OwnerStage<T, D, M2> &st, int k, const Geom &g, int lane,
-                                 F &&f) {
+__device__ inline void owner_box(const OwnerStage<T, D, M2> &st, int k, const Geom &g,
+                                 const OwnerLayout &lay, int lane, F &&f) {
     int n[D], loc0[D], tap0[D];
-    int npl = 1, s0 = 1;
+    int npl = 1;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         n[d] = __builtin_amdgcn_readfirstlane(st.n[d][k]);
         loc0[d] = __builtin_amdgcn_readfirstlane(st.loc0[d][k]);
         tap0[d] = __builtin_amdgcn_readfirstlane(st.tap0[d][k]);
-        if (d > 0) {
-            npl *= n[d];
-            s0 *= g.Q[d];
-        }
+        if (d > 0) npl *= n[d];
     }
     if (n[0] == 0 || npl == 0) return;
     float rc[D];
@@ -243,7 +240,7 @@ __device__ inline void owner_box(const OwnerStage<T, D, M2> &st, int k, const Ge
         for (int d = 1; d < D; ++d) {
             int loc = loc0[d] + u[d];
             if (loc >= g.Q[d]) loc -= g.Q[d];  // wraps only when the tile spans the axis
-            c1 = c1 * g.Q[d] + loc;
+            c1 += loc * lay.S[d];
             w1 *= wk[d * M2 + tap0[d] + u[d]];
         }
         w1 = ok ? w1 : (T)0;
@@ -253,14 +250,16 @@ __device__ inline void owner_box(const OwnerStage<T, D, M2> &st, int k, const Ge
             const int uc = in ? u0 : n[0] - 1;
             int l0 = loc0[0] + uc;
             if (l0 >= g.Q[0]) l0 -= g.Q[0];
-            f(ok && in, l0 * s0 + c1, w0[u0] * w1);
+            f(ok && in, l0 * lay.S[0] + c1, w0[u0] * w1);
         }
     }
 }
 
-// Global grid index of tile-local cell c.
+// Global grid index of tile-local cell c (row-major over the tile) and, in
+// *lds, its accumulator index in the layout lay.
 template <int D>
-__device__ inline long long owner_global(const OwnerTile<D> &ot, const Geom &g, int c) {
+__device__ inline long long owner_global(const OwnerTile<D> &ot, const Geom &g,
+                                         const OwnerLayout &lay, int c, int *lds) {
     int l[D];
     int rem = c;
 #pragma unroll
@@ -269,8 +268,13 @@ __device__ inline long long owner_global(const OwnerTile<D> &ot, const Geom &g, 
         rem /= g.Q[d];
     }
     long long idx = 0;
+    int li = 0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) idx = idx * g.Nt[d] + (ot.t0[d] + l[d]);
+    for (int d = 0; d < D; ++d) {
+        idx = idx * g.Nt[d] + (ot.t0[d] + l[d]);
+        li += l[d] * lay.S[d];
+    }
+    *lds = li;
     return idx;
 }
 
@@ -369,7 +373,8 @@ __global__ void __launch_bounds__(kOwnerThreads)
     k_spread_owner(cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
                    const int *__restrict__ perm, const int *__restrict__ key_start,
                    const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
-                   const cplx<T> *__restrict__ fhat, long long gstride, long long fstride) {
+                   const cplx<T> *__restrict__ fhat, long long gstride, long long fstride,
+                   OwnerLayout lay) {
     using C = cplx<T>;
     using FP = FixedPoint<T>;
     constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
@@ -377,17 +382,20 @@ __global__ void __launch_bounds__(kOwnerThreads)
     __shared__ OwnerStage<T, D, M2> st;
     __shared__ int nb_begin[kOwnerMaxTiles], nb_pre[kOwnerMaxTiles + 1];
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double
-    static_assert(sizeof(OwnerStage<T, D, M2>) + sizeof(int) * (2 * kOwnerMaxTiles + 1) + 8 <=
+    __shared__ int next_k[2];                 // candidate counters of even and odd rounds
+    static_assert(sizeof(OwnerStage<T, D, M2>) + sizeof(int) * (2 * kOwnerMaxTiles + 3) + 8 <=
                       owner_static_lds(D, M2, (int)sizeof(T)),
                   "staged candidates larger than the LDS the plan reserves for them");
     grid += blockIdx.y * gstride;
     fhat += blockIdx.y * fstride;
     const OwnerTile<D> ot = owner_tile<D>(g, xcd_block(blockIdx.x, gridDim.x));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
-    for (int c = threadIdx.x; c < SL * ot.cells; c += blockDim.x) acc[c] = 0ull;
-    if (threadIdx.x == 0) amax_bits = 0ull;
+    for (int c = threadIdx.x; c < SL * lay.cells; c += blockDim.x) acc[c] = 0ull;
+    if (threadIdx.x == 0) {
+        amax_bits = 0ull;
+        next_k[0] = next_k[1] = 0;
+    }
     owner_ranges<D>(ot, g, key_start, nb_begin, nb_pre);  // (its barriers cover the clearing)
     const int total = nb_pre[ot.nb];
 
@@ -415,22 +423,37 @@ __global__ void __launch_bounds__(kOwnerThreads)
 
     const TapCoef<T, M2> tc = owner_coef<T, D, M2>(coef, window, wp.m);
     constexpr int CH = OwnerStage<T, D, M2>::CH;
-    for (int c0 = 0; c0 < total; c0 += CH) {
+    int parity = 0;
+    for (int c0 = 0; c0 < total; c0 += CH, parity ^= 1) {
         const int n = min(CH, total - c0);
         owner_stage<true, T, D, M2>(st, c0, n, ot, g, nb_begin, nb_pre, nodes, perm, fhat, tc,
                                     window, wp);
-        for (int k = wave; k < n; k += nwave) {
+        if (threadIdx.x == 0) next_k[parity ^ 1] = 0;  // the next round's counter (unused now)
+        // Candidates go to the wavefronts on demand: boxes range from one point to
+        // taps^D, and a fixed assignment left wavefronts idle at the round's barrier.
+        // The next index is requested before the current box is walked.
+        int kn = 0;
+        if (lane == 0) kn = atomicAdd(&next_k[parity], 1);
+        kn = __builtin_amdgcn_readfirstlane(kn);
+        while (kn < n) {
+            const int k = kn;
+            int req = 0;
+            if (lane == 0) req = atomicAdd(&next_k[parity], 1);
             const T pr = st.vr[k] * scale, pi = st.vi[k] * scale;
-            owner_box<T, D, M2>(st, k, g, lane, [&](bool live, int cell, T w) {
-                if (live) FP::add(acc + cell, ot.cells, w * pr, w * pi);
+            owner_box<T, D, M2>(st, k, g, lay, lane, [&](bool live, int cell, T w) {
+                if (live) FP::add(acc + cell, lay.cells, w * pr, w * pi);
             });
+            kn = __builtin_amdgcn_readfirstlane(req);
         }
         __syncthreads();
     }
     const T inv = (T)(1.0 / (double)scale);
-    for (int c = threadIdx.x; c < ot.cells; c += blockDim.x)
-        grid[owner_global<D>(ot, g, c)] =
-            cmake<C>((T)FP::read(acc + c, ot.cells, 0) * inv, (T)FP::read(acc + c, ot.cells, 1) * inv);
+    for (int c = threadIdx.x; c < ot.cells; c += blockDim.x) {
+        int li;
+        const long long gi = owner_global<D>(ot, g, lay, c, &li);
+        grid[gi] = cmake<C>((T)FP::read(acc + li, lay.cells, 0) * inv,
+                            (T)FP::read(acc + li, lay.cells, 1) * inv);
+    }
 }
 
 template <typename T, int D, int M2>
@@ -448,9 +471,12 @@ hipError_t run_interp_node(const nfft_plan_s &p, const void *grid, void *fhat, h
 template <typename T, int D, int M2>
 hipError_t run_spread_owner(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                             int K) {
-    int cells = 1;
-    for (int d = 0; d < D; ++d) cells *= p.geom.Q[d];
-    const size_t shm = (size_t)cells * 2 * FixedPoint<T>::kSlots * sizeof(unsigned long long);
+    // padded accumulator layout where it fits beside the staged candidates
+    const size_t stat = owner_static_lds(D, M2, (int)sizeof(T));
+    const size_t cell_bytes = 2 * FixedPoint<T>::kSlots * sizeof(unsigned long long);
+    OwnerLayout lay = owner_layout(p.geom, D, true);
+    if ((size_t)lay.cells * cell_bytes + stat > (size_t)p.lds_limit) lay = owner_layout(p.geom, D, false);
+    const size_t shm = (size_t)lay.cells * cell_bytes;
     double wprod = 1.0;
     for (int d = 0; d < D; ++d) {
         const double beta = M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]);
@@ -458,12 +484,12 @@ hipError_t run_spread_owner(const nfft_plan_s &p, const void *fhat, void *grid, 
         wprod *= 1.5 * sinh(beta) / M_PI;
     }
     auto kern = k_spread_owner<T, D, M2>;
-    hipError_t e = allow_lds(kern, shm, owner_static_lds(D, M2, (int)sizeof(T)));
+    hipError_t e = allow_lds(kern, shm, stat);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(p.geom.ntiles, K), dim3(kOwnerThreads), shm, s,
                        (cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.key_start, (const T *)p.coef, p.window, win_params<T>(p), (T)wprod,
-                       (const cplx<T> *)fhat, (long long)p.G, (long long)p.M);
+                       (const cplx<T> *)fhat, (long long)p.G, (long long)p.M, lay);
     return hipGetLastError();
 }
 
