@@ -22,11 +22,13 @@
 // reach it).  Per node it walks only the box where the stencil and the tile
 // intersect (one interval per axis, since taps + Q_d <= Nt_d when T_d >= 2; the
 // whole stencil, wrapped, when the tile spans the axis): lanes take the box
-// points of the axes 1..D-1 and loop over axis 0.  Contributions go into the
-// tile in LDS with 64-bit fixed-point atomics (the scheme of the tiled kernels:
-// a power-of-two scale from the largest |value| of the tile's candidates; exact,
-// order-independent sums), and the tile is written to the grid once.  No global
-// atomics, no scratch, no halo merge; bitwise reproducible.
+// points of the axes 1..D-1 and loop over axis 0, and a wavefront takes its
+// next node from a per-round counter when it is done with a box.
+// Contributions go into the tile in LDS with 64-bit fixed-point atomics (the
+// scheme of the tiled kernels: a power-of-two scale from the largest |value| of
+// the tile's candidates; exact, order-independent sums), and the tile is
+// written to the grid once.  No global atomics, no scratch, no halo merge;
+// bitwise reproducible.
 #pragma once
 
 #include "resample_impl.hpp"
@@ -54,7 +56,7 @@ __device__ inline T axis_weight(const TapCoef<T, M2> &tc, int window, const WinP
                              wp.m);
 }
 
-// Candidates staged per round: the box weights take at most about 16 KiB.
+// Candidates staged per round (owner_chunk_n).
 template <typename T, int D, int M2> constexpr int owner_chunk() {
     return owner_chunk_n(D, M2, (int)sizeof(T));
 }
@@ -67,7 +69,7 @@ template <typename T, int D, int M2> struct OwnerStage {
     int tap0[D][CH];  // stencil tap of the first box point
     int n[D][CH];     // box extent (0: the stencil misses the tile)
     T fr[D][CH];
-    T vr[CH], vi[CH];  // spreading: the node's value
+    T vr[CH], vi[CH];  // the node's value
     T w[CH][D * M2];   // axis weights of the box taps
 };
 
@@ -128,7 +130,7 @@ __device__ inline void owner_ranges(const OwnerTile<D> &ot, const Geom &g,
 // Stage candidates [c0, c0 + n) of the concatenated ranges: box per axis, then
 // the weights of the box taps -- thread tid computes tap (tid mod D*M2) of the
 // candidates tid / (D*M2), + nper, ... (tc: its coefficients).  Ends with a barrier.
-template <bool SPREAD, typename T, int D, int M2>
+template <typename T, int D, int M2>
 __device__ inline void owner_stage(OwnerStage<T, D, M2> &st, int c0, int n, const OwnerTile<D> &ot,
                                    const Geom &g, const int *nb_begin, const int *nb_pre,
                                    const NodeRec<T, D> *__restrict__ nodes,
@@ -148,11 +150,9 @@ __device__ inline void owner_stage(OwnerStage<T, D, M2> &st, int c0, int n, cons
         const int gk = nb_begin[i] + (q - nb_pre[i]);
         const NodeRec<T, D> rec = nodes[gk];
         st.gk[tid] = gk;
-        if constexpr (SPREAD) {
-            const cplx<T> v = fhat[perm[gk]];
-            st.vr[tid] = v.x;
-            st.vi[tid] = v.y;
-        }
+        const cplx<T> v = fhat[perm[gk]];
+        st.vr[tid] = v.x;
+        st.vi[tid] = v.y;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             int loc0, tap0, cnt;
@@ -426,8 +426,8 @@ __global__ void __launch_bounds__(kOwnerThreads)
     int parity = 0;
     for (int c0 = 0; c0 < total; c0 += CH, parity ^= 1) {
         const int n = min(CH, total - c0);
-        owner_stage<true, T, D, M2>(st, c0, n, ot, g, nb_begin, nb_pre, nodes, perm, fhat, tc,
-                                    window, wp);
+        owner_stage<T, D, M2>(st, c0, n, ot, g, nb_begin, nb_pre, nodes, perm, fhat, tc, window,
+                              wp);
         if (threadIdx.x == 0) next_k[parity ^ 1] = 0;  // the next round's counter (unused now)
         // Candidates go to the wavefronts on demand: boxes range from one point to
         // taps^D, and a fixed assignment left wavefronts idle at the round's barrier.
