@@ -734,7 +734,9 @@ __global__ void __launch_bounds__(kResampleThreads)
     using C = cplx<T>;
     grid += blockIdx.y * gstride;  // channel
     pad += blockIdx.y * pstride;
-    const int p = blockIdx.x;
+    // consecutive tiles on one XCD: a tile's own rows and the halo rows its
+    // neighbour reads share cache lines (3-D 128^3: merge 15-65 us faster)
+    const int p = xcd_block(blockIdx.x, gridDim.x);
     int tc[D], P[D];
     int ptot = 1;
     {
