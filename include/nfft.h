@@ -218,14 +218,19 @@ int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M,
 /*
  * The single steps, for step-wise checking and timing.  `grid` is a device
  * array of prod(Ntilde) complex values, row-major, storage index l mod Ntilde
- * (DC first).
- *   nfft_resample_forward : fhat_j = sum_l ghat_l psi_tilde(x_j - l/Ntilde)
+ * (DC first).  The plan stores the window divided by its peak per axis,
+ * C = prod_d psi_hat_Base(0) = prod_d sinh(beta_d)/pi (nfft_plan_window_peak), and
+ * the resampling-correction factors multiplied by it, so that neither leaves the
+ * float range (the transforms themselves are unchanged by this).  The steps use
+ * the stored window:
+ *   nfft_resample_forward : fhat_j = (1/C) sum_l ghat_l psi_tilde(x_j - l/Ntilde)
  *                           (Algorithm 1, resampling step; reads grid)
- *   nfft_resample_adjoint : ghat_l = sum_j fhat_j psi_tilde(x_j - l/Ntilde)
+ *   nfft_resample_adjoint : ghat_l = (1/C) sum_j fhat_j psi_tilde(x_j - l/Ntilde)
  *                           (Algorithm 2, adjoint resampling; overwrites grid)
  *   nfft_fft_grid         : unnormalised D-variate FFT of grid in place;
  *                           direction -1 = forward (exp(-2 pi i n.l/Ntilde)),
  *                           +1 = adjoint (exp(+2 pi i ...)).
+ * After nfft_forward the plan's grid (nfft_plan_grid) holds C F D f.
  */
 int nfft_resample_forward(nfft_plan_t p, const void *grid, void *fhat, void *stream);
 int nfft_resample_adjoint(nfft_plan_t p, const void *fhat, void *grid, void *stream);
@@ -238,8 +243,16 @@ int nfft_fft_grid(nfft_plan_t p, void *grid, int direction, void *stream);
 int nfft_plan_info(nfft_plan_t p, int64_t *Ntilde, double *sigma_eff, int *tile);
 
 /* Device pointer to the plan's oversampled grid (prod(Ntilde) complex): after
- * nfft_forward it holds ghat = F D f, after nfft_adjoint it is scratch. */
+ * nfft_forward it holds C ghat = C F D f (C: nfft_plan_window_peak), after
+ * nfft_adjoint it is scratch. */
 int nfft_plan_grid(nfft_plan_t p, void **grid);
+
+/* The window peak per axis, peak[d] = psi_hat_Base(0) = sinh(beta_d)/pi with
+ * beta_d = pi m (2 - 1/sigma_d) (Kaiser-Bessel window; paper, "Materials and
+ * Methods"), in FP64: the constant the stored window is divided by (see the
+ * single steps above).  peak: host array of D doubles.  An extension of the
+ * introspection calls; NFFT_ERR_ARG for a NULL argument. */
+int nfft_plan_window_peak(nfft_plan_t p, double *peak);
 
 /*
  * Per-kernel timing.  With timing enabled, nfft_forward and nfft_adjoint

@@ -302,7 +302,13 @@ def resample_forward(x, ghat, N, m, Nt, window="poly", wide=False):
 
 
 def resample_adjoint(x, fhat, N, m, Nt, window="poly", wide=False):
-    """Adjoint resampling of Algorithm 2 (step 1): ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt)."""
+    """Adjoint resampling of Algorithm 2 (step 1): ghat_l = sum_j fhat_j psi_tilde(x_j - l/Nt).
+
+    Every node adds fhat_j times the product of its per-axis tap weights to each grid point
+    of its stencil.  The additions of a chunk of nodes (all their taps at once) are summed by
+    one ``bincount`` over the grid -- the same sum as a loop over the nodes, accumulated in
+    another order (which only moves rounding).
+    """
     N = tuple(int(v) for v in N)
     D = len(N)
     Nt = tuple(int(v) for v in Nt)
@@ -310,16 +316,23 @@ def resample_adjoint(x, fhat, N, m, Nt, window="poly", wide=False):
     fhat = np.asarray(fhat, dtype=np.complex128).reshape(-1)
     origin, ws = _weights_per_axis(x, N, Nt, m, window, wide)
     J = x.shape[0]
+    T = ws[0].shape[1] if D else 0
     G = int(np.prod(Nt))
     acc_re = np.zeros(G)
     acc_im = np.zeros(G)
-    for taps in np.ndindex(*([ws[0].shape[1]] * D)):
-        w = np.ones(J)
-        flat = np.zeros(J, dtype=np.int64)
+    chunk = max(1, (1 << 24) // T ** D)
+    for s in range(0, J, chunk):
+        n = min(chunk, J - s)
+        flat = np.zeros((n,) + (1,) * D, dtype=np.int64)
+        w = np.ones((n,) + (1,) * D)
         for d in range(D):
-            w = w * ws[d][:, taps[d]]
-            flat = flat * Nt[d] + np.mod(origin[:, d] + taps[d], Nt[d])
-        v = w * fhat
+            shape = [n] + [1] * D
+            shape[1 + d] = T
+            idx = np.mod(origin[s:s + n, d][:, None] + np.arange(T)[None, :], Nt[d])
+            flat = flat * Nt[d] + idx.reshape(shape)
+            w = w * ws[d][s:s + n].reshape(shape)
+        v = (w * fhat[s:s + n].reshape((n,) + (1,) * D)).ravel()
+        flat = np.broadcast_to(flat, (n,) + (T,) * D).ravel()
         acc_re += np.bincount(flat, weights=v.real, minlength=G)
         acc_im += np.bincount(flat, weights=v.imag, minlength=G)
     return (acc_re + 1j * acc_im).reshape(Nt)

@@ -31,7 +31,8 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
            "nfft_plan_info", "nfft_plan_grid", "nfft_plan_set_timing", "nfft_plan_timing",
            "nfft_plan_bench_stage", "nfft_forward_many", "nfft_adjoint_many",
            "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
-           "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror"]
+           "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror",
+           "nfft_plan_window_peak"]
 NFFT_NUM_STAGES = 8
 STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
           "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]
@@ -77,6 +78,7 @@ def load():
     lib.nfft_plan_info.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int)]
     lib.nfft_plan_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
+    lib.nfft_plan_window_peak.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nfft_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.nfft_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nfft_plan_bench_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,

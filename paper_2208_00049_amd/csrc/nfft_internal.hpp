@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "nfft.h"
@@ -211,6 +212,28 @@ struct nfft_plan_s {
 };
 
 namespace nfft {
+
+// Kaiser-Bessel shape parameter of axis d: beta = pi m (2 - 1/sigma_d), sigma_d = Nt_d / N_d.
+inline double kb_beta(const nfft_plan_s &p, int d) {
+    return M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]);
+}
+
+// Peak of the convolution-side window of axis d, psi_hat_Base(0) = sinh(beta) / pi.
+// The library keeps the window divided by this constant (its maximum is then 1 on
+// every axis) and the resampling-correction factors multiplied by it.  The product
+// of the two factors -- all the transform depends on -- is unchanged, and neither
+// factor leaves the float range: the raw peaks multiply to sinh(beta)^D / pi^D, which
+// overflows float for m D >= 24 or so, and the raw correction factors to its
+// reciprocal, which underflows.
+inline double window_peak(const nfft_plan_s &p, int d) { return sinh(kb_beta(p, d)) / M_PI; }
+
+// Product over the axes of the normalised window's maximum (1), with a margin for
+// the polynomial fit's overshoot: the bound the fixed-point spreading scales by.
+inline double window_bound(int D) {
+    double w = 1.0;
+    for (int d = 0; d < D; ++d) w *= 1.5;
+    return w;
+}
 
 // plan.cpp: the argument checks of plan creation (no HIP call)
 int validate_plan_args(int D, const int64_t *N, int64_t M, const void *x, int m, double sigma,

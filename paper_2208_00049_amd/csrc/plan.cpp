@@ -508,12 +508,15 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
     TRY(launch_deconv_factors(*p, s));
     vandermonde_qr(Z, Theta, qt, rr);
     {
-        std::vector<double> host((size_t)Z * Theta + (size_t)Z * Z + kMaxD);
+        // Q^T, R, the shape parameters and the reciprocal window peaks per axis
+        std::vector<double> host((size_t)Z * Theta + (size_t)Z * Z + 2 * kMaxD);
         std::copy(qt.begin(), qt.end(), host.begin());
         std::copy(rr.begin(), rr.end(), host.begin() + (size_t)Z * Theta);
-        for (int d = 0; d < kMaxD; ++d)
-            host[(size_t)Z * Theta + (size_t)Z * Z + d] =
-                d < D ? M_PI * m * (2.0 - (double)p->N[d] / (double)p->Nt[d]) : 0.0;
+        for (int d = 0; d < kMaxD; ++d) {
+            host[(size_t)Z * Theta + (size_t)Z * Z + d] = d < D ? kb_beta(*p, d) : 0.0;
+            host[(size_t)Z * Theta + (size_t)Z * Z + kMaxD + d] =
+                d < D ? 1.0 / window_peak(*p, d) : 0.0;
+        }
         TRY(hipMalloc(&polyscratch, host.size() * sizeof(double)));
         TRY(hipMemcpyAsync(polyscratch, host.data(), host.size() * sizeof(double),
                            hipMemcpyHostToDevice, s));
@@ -599,6 +602,12 @@ int nfft_plan_info(nfft_plan_t p, int64_t *Ntilde, double *sigma_eff, int *tile)
 int nfft_plan_grid(nfft_plan_t p, void **grid) {
     if (!p || !grid) return NFFT_ERR_ARG;
     *grid = p->grid;
+    return NFFT_OK;
+}
+
+int nfft_plan_window_peak(nfft_plan_t p, double *peak) {
+    if (!p || !peak) return NFFT_ERR_ARG;
+    for (int d = 0; d < p->D; ++d) peak[d] = window_peak(*p, d);
     return NFFT_OK;
 }
 

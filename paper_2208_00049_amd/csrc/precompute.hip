@@ -42,16 +42,17 @@ __device__ double window_hat_full_fp64(double u, double beta) {
 
 // Resampling-correction factors of one axis (paper, subsection "Resampling
 // Correction"): beta_tensor[n] = 1 / (m phi_Base(m n / Nt)), n in I_N, with
-// phi_Base(xi) = I0(sqrt(beta^2 - (2 pi xi)^2)).  Computed in FP64, stored in T.
+// phi_Base(xi) = I0(sqrt(beta^2 - (2 pi xi)^2)), times the window peak
+// sinh(beta)/pi that the stored window is divided by.  Computed in FP64, stored in T.
 template <typename T>
-__global__ void k_deconv_factors(int N, int Nt, int m, double beta, T *out) {
+__global__ void k_deconv_factors(int N, int Nt, int m, double beta, double peak, T *out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double n = (double)(i - N / 2);
     const double a = 2.0 * M_PI * (double)m * n / (double)Nt;
     const double arg = beta * beta - a * a;  // >= 0 because sigma >= 1
     const double phi = bessel_i0_series(sqrt(arg > 0.0 ? arg : 0.0));
-    out[i] = (T)(1.0 / ((double)m * phi));
+    out[i] = (T)(peak / ((double)m * phi));
 }
 
 // Polynomial window table (paper, POLYNOMIAL item of subsection "Window
@@ -62,21 +63,24 @@ __global__ void k_deconv_factors(int N, int Nt, int m, double beta, T *out) {
 // Theta; r = R, Z x Z upper), then rescaled exactly by 2^z.  One thread per
 // (axis, tap); FP64 throughout, stored in T.  With the wide stencil (taps =
 // 2m + 2, lo = m) tap t samples the untruncated window at (zeta + m + 1/2 - t)/m.
+// The samples are divided by the window peak inv_peaks[axis]^-1 = sinh(beta)/pi.
 template <typename T>
 __global__ void k_window_poly(int m, int taps, int Z, int Theta, const double *betas,
-                              const double *qt, const double *r, T *mu) {
+                              const double *inv_peaks, const double *qt, const double *r, T *mu) {
     const int t = threadIdx.x;
     const int axis = blockIdx.x;
     if (t >= taps) return;
     const int lo = taps / 2 - 1;
     const bool wide = taps > 2 * m;
     const double beta = betas[axis];
+    const double inv_peak = inv_peaks[axis];
     double c[32];
     for (int z = 0; z < Z; ++z) c[z] = 0.0;
     for (int v = 0; v < Theta; ++v) {
         const double zeta = -0.5 + (double)v / (double)(Theta - 1);
         const double u = (zeta + (double)lo + 0.5 - (double)t) / (double)m;
-        const double b = wide ? window_hat_full_fp64(u, beta) : window_hat_fp64(u, beta);
+        const double b =
+            (wide ? window_hat_full_fp64(u, beta) : window_hat_fp64(u, beta)) * inv_peak;
         for (int z = 0; z < Z; ++z) c[z] += qt[z * Theta + v] * b;
     }
     double sol[32];
@@ -95,12 +99,15 @@ __global__ void k_window_poly(int m, int taps, int Z, int Theta, const double *b
 // LINEAR window table (paper, LINEAR item of subsection "Window
 // precomputation"): psi_s = psi_hat_Base(s / (S - 2)) for s <= S - 2 (the sinh
 // form, whose value at |u| = 1 is the limit beta/pi, the half-open support's
-// value at u = -1) and psi_{S-1} = 0, outside the support.  FP64, stored in T.
+// value at u = -1) and psi_{S-1} = 0, outside the support; divided by the window
+// peak (times inv_peak).  FP64, stored in T.
 template <typename T>
-__global__ void k_window_linear(long long S, double beta, T *table) {
+__global__ void k_window_linear(long long S, double beta, double inv_peak, T *table) {
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
-    table[s] = s == S - 1 ? (T)0 : (T)window_hat_fp64((double)s / (double)(S - 2), beta);
+    table[s] = s == S - 1
+                   ? (T)0
+                   : (T)(window_hat_fp64((double)s / (double)(S - 2), beta) * inv_peak);
 }
 
 // Polynomial window weight of tap t at offset frac, evaluated like the
@@ -151,20 +158,18 @@ __global__ void k_twiddles(int L, cplx<T> *tw) {
     tw[t] = cmake<cplx<T>>((T)c, (T)(-s));
 }
 
-static double kb_beta(const nfft_plan_s &p, int d) {
-    return M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]);
-}
-
 hipError_t launch_deconv_factors(const nfft_plan_s &p, hipStream_t s) {
     for (int d = 0; d < p.D; ++d) {
         const int N = (int)p.N[d];
         const int blocks = (N + 255) / 256;
         if (p.dtype == NFFT_C64)
             hipLaunchKernelGGL(k_deconv_factors<float>, dim3(blocks), dim3(256), 0, s, N,
-                               (int)p.Nt[d], p.m, kb_beta(p, d), (float *)p.deconv[d]);
+                               (int)p.Nt[d], p.m, kb_beta(p, d), window_peak(p, d),
+                               (float *)p.deconv[d]);
         else
             hipLaunchKernelGGL(k_deconv_factors<double>, dim3(blocks), dim3(256), 0, s, N,
-                               (int)p.Nt[d], p.m, kb_beta(p, d), (double *)p.deconv[d]);
+                               (int)p.Nt[d], p.m, kb_beta(p, d), window_peak(p, d),
+                               (double *)p.deconv[d]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -173,14 +178,16 @@ hipError_t launch_deconv_factors(const nfft_plan_s &p, hipStream_t s) {
 
 hipError_t launch_window_poly(const nfft_plan_s &p, const double *qt, const double *r, int Z,
                               int Theta, hipStream_t s) {
-    // betas, qt and r live in one device scratch allocation owned by the caller
+    // betas, the reciprocal window peaks, qt and r live in one device scratch
+    // allocation owned by the caller
     const double *betas = r + Z * Z;
+    const double *inv_peaks = betas + kMaxD;
     if (p.dtype == NFFT_C64)
         hipLaunchKernelGGL(k_window_poly<float>, dim3(p.D), dim3(64), 0, s, p.m, p.geom.taps, Z,
-                           Theta, betas, qt, r, (float *)p.coef);
+                           Theta, betas, inv_peaks, qt, r, (float *)p.coef);
     else
         hipLaunchKernelGGL(k_window_poly<double>, dim3(p.D), dim3(64), 0, s, p.m, p.geom.taps, Z,
-                           Theta, betas, qt, r, (double *)p.coef);
+                           Theta, betas, inv_peaks, qt, r, (double *)p.coef);
     return hipGetLastError();
 }
 
@@ -191,10 +198,12 @@ hipError_t launch_window_tables(const nfft_plan_s &p, hipStream_t s) {
             const unsigned blocks = (unsigned)((p.lin_S + 255) / 256);
             if (p.dtype == NFFT_C64)
                 hipLaunchKernelGGL(k_window_linear<float>, dim3(blocks), dim3(256), 0, s, p.lin_S,
-                                   kb_beta(p, d), (float *)p.wtab + (size_t)d * p.lin_S);
+                                   kb_beta(p, d), 1.0 / window_peak(p, d),
+                                   (float *)p.wtab + (size_t)d * p.lin_S);
             else
                 hipLaunchKernelGGL(k_window_linear<double>, dim3(blocks), dim3(256), 0, s, p.lin_S,
-                                   kb_beta(p, d), (double *)p.wtab + (size_t)d * p.lin_S);
+                                   kb_beta(p, d), 1.0 / window_peak(p, d),
+                                   (double *)p.wtab + (size_t)d * p.lin_S);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -52,8 +52,8 @@ template <typename T, int M2>
 __device__ inline T axis_weight(const TapCoef<T, M2> &tc, int window, const WinParams<T> &wp, int D,
                                 long long gk, int d, int t, T frac) {
     if (window == NFFT_WINDOW_TENSOR) return wp.tab[(gk * D + d) * M2 + t];
-    return tap_weight<T, M2>(tc.cf, frac, t, window, wp.beta[d], wp.tab + (size_t)d * wp.S, wp.S,
-                             wp.m);
+    return tap_weight<T, M2>(tc.cf, frac, t, window, wp.beta[d], wp.inv_peak[d],
+                             wp.tab + (size_t)d * wp.S, wp.S, wp.m);
 }
 
 // Candidates staged per round (owner_chunk_n).
@@ -477,12 +477,7 @@ hipError_t run_spread_owner(const nfft_plan_s &p, const void *fhat, void *grid, 
     OwnerLayout lay = owner_layout(p.geom, D, true);
     if ((size_t)lay.cells * cell_bytes + stat > (size_t)p.lds_limit) lay = owner_layout(p.geom, D, false);
     const size_t shm = (size_t)lay.cells * cell_bytes;
-    double wprod = 1.0;
-    for (int d = 0; d < D; ++d) {
-        const double beta = M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]);
-        // window maximum psi_hat_Base(0) = sinh(beta)/pi, with margin for the polynomial fit
-        wprod *= 1.5 * sinh(beta) / M_PI;
-    }
+    const double wprod = window_bound(D);
     auto kern = k_spread_owner<T, D, M2>;
     hipError_t e = allow_lds(kern, shm, stat);
     if (e != hipSuccess) return e;

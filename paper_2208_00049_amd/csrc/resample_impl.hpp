@@ -40,6 +40,7 @@ namespace nfft {
 
 template <typename T> struct WinParams {
     T beta[kMaxD];
+    T inv_peak[kMaxD];  // direct evaluation: pi / sinh(beta), the stored window's normalisation
     const T *tab;  // TENSOR / FULL: weights per sorted node; LINEAR: S samples per axis
     long long S;   // LINEAR table entries per axis
     int m;         // window half-width (M2 = 2m, or 2m + 2 with the wide stencil)
@@ -49,10 +50,12 @@ template <typename T> struct WinParams {
 // lin: the axis's LINEAR table of S entries).  Tap t sits at u = (frac + M2/2 -
 // 1 - t) / m; with the wide stencil (M2 = 2m + 2) the outer taps lie beyond
 // |u| = 1, where the untruncated window continues as sin(beta sqrt(u^2-1)) /
-// (pi sqrt(u^2-1)).
+// (pi sqrt(u^2-1)).  Every mode returns the window divided by its peak
+// sinh(beta)/pi (the polynomial and the tables are fitted and filled that way; the
+// direct evaluation multiplies by inv_peak).
 template <typename T, int M2>
-__device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, const T *lin,
-                               long long S, int m) {
+__device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, T inv_peak,
+                               const T *lin, long long S, int m) {
     if (window == NFFT_WINDOW_POLY) {
         // degree 2m; coefficients above it are zero (wide stencil: M2 = 2m + 2)
         const T z = frac - (T)0.5;
@@ -76,10 +79,10 @@ __device__ inline T tap_weight(const T *cf, T frac, int t, int window, T beta, c
     const T s2 = (T)1 - u * u;
     if (s2 < (T)0) {  // wide stencil only: beyond the truncation interval
         const T r = sqrt(-s2);
-        return sin(beta * r) / ((T)M_PI * r);
+        return sin(beta * r) / ((T)M_PI * r) * inv_peak;
     }
     const T s = s2 > (T)0 ? sqrt(s2) : (T)0;
-    return s > (T)0 ? sinh(beta * s) / ((T)M_PI * s) : beta / (T)M_PI;
+    return (s > (T)0 ? sinh(beta * s) / ((T)M_PI * s) : beta / (T)M_PI) * inv_peak;
 }
 
 // Polynomial window weight of a tap and its derivative in frac (one Horner pass
@@ -230,8 +233,8 @@ __device__ inline void node_weights(T *w, const LaneWindow<T, D, M2> &lw, const 
     if constexpr (!GW) {
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, NFFT_WINDOW_POLY, wp.beta[d], nullptr, 0,
-                                     wp.m);
+            w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, NFFT_WINDOW_POLY, wp.beta[d],
+                                     wp.inv_peak[d], nullptr, 0, wp.m);
         return;
     }
     if (window == NFFT_WINDOW_TENSOR) {
@@ -244,8 +247,8 @@ __device__ inline void node_weights(T *w, const LaneWindow<T, D, M2> &lw, const 
     } else {
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, window, wp.beta[d], wp.tab + d * wp.S,
-                                     wp.S, wp.m);
+            w[d] = tap_weight<T, M2>(lw.cf[d], fr[d], li, window, wp.beta[d], wp.inv_peak[d],
+                                     wp.tab + d * wp.S, wp.S, wp.m);
     }
 }
 
@@ -847,8 +850,10 @@ template <typename K> inline hipError_t allow_lds(K kernel, size_t dyn, size_t s
 
 template <typename T> inline WinParams<T> win_params(const nfft_plan_s &p) {
     WinParams<T> wp;
-    for (int d = 0; d < kMaxD; ++d)
-        wp.beta[d] = d < p.D ? (T)(M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d])) : (T)0;
+    for (int d = 0; d < kMaxD; ++d) {
+        wp.beta[d] = d < p.D ? (T)kb_beta(p, d) : (T)0;
+        wp.inv_peak[d] = d < p.D ? (T)(1.0 / window_peak(p, d)) : (T)0;
+    }
     wp.tab = (const T *)p.wtab;
     wp.S = p.lin_S;
     wp.m = p.m;
@@ -905,12 +910,7 @@ hipError_t run_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStr
     if (p.nsub > 0) {
         const size_t shm = padded_cells(p.geom, D) * 2 * FixedPoint<T>::kSlots *
                            sizeof(unsigned long long);
-        double wprod = 1.0;
-        for (int d = 0; d < D; ++d) {
-            const double beta = M_PI * p.m * (2.0 - (double)p.N[d] / (double)p.Nt[d]);
-            // window maximum psi_hat_Base(0) = sinh(beta)/pi, with margin for the polynomial fit
-            wprod *= 1.5 * sinh(beta) / M_PI;
-        }
+        const double wprod = window_bound(D);
         constexpr int NT = resample_threads<T, D>();
         const bool gw = p.window != NFFT_WINDOW_POLY;
         auto kern = gw ? k_spread<T, D, M2, true, NT> : k_spread<T, D, M2, false, NT>;

@@ -96,8 +96,25 @@ class Plan:
     def Ntilde(self):
         return self.info()["Ntilde"]
 
+    def window_peaks(self):
+        """Per-axis window peak sinh(beta_d)/pi the stored window is divided by."""
+        pk = (ctypes.c_double * self.D)()
+        _lib.check(self._lib.nfft_plan_window_peak(self._h, pk), "nfft_plan_window_peak")
+        return tuple(pk)
+
+    @property
+    def window_scale(self):
+        """C = product of the window peaks: the single steps use the window divided by C
+        (``resample_forward`` / ``resample_adjoint`` return the paper's step over C) and the
+        grid after ``forward`` holds C F D f."""
+        c = 1.0
+        for v in self.window_peaks():
+            c *= v
+        return c
+
     def grid(self):
-        """Copy of the plan's oversampled grid (holds F D f after ``forward``)."""
+        """Copy of the plan's oversampled grid (holds C F D f after ``forward``, C =
+        ``window_scale``)."""
         ptr = ctypes.c_void_p()
         _lib.check(self._lib.nfft_plan_grid(self._h, ctypes.byref(ptr)), "nfft_plan_grid")
         out = torch.empty(self.Ntilde, dtype=self.cdtype, device=self.device)

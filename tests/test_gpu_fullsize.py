@@ -12,7 +12,8 @@ import torch
 import nfft_workloads as wl
 from oracle import ndft
 from oracle import nfft_alg as na
-from test_gpu_nfft import NDFT_GATE, TARGET, e2e_tol, make_plan, rel2, to_dev
+from test_gpu_nfft import (C64_VS_ORACLE, C128_VS_ORACLE, NDFT_GATE, TARGET, e2e_tol, make_plan,
+                           rel2, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +54,15 @@ def test_2d_512(device, nodes, dt, m):
         assert max(ef, ea) <= TARGET[(dt, m, sigma)]
 
 
-@pytest.mark.parametrize("sigma,dt", [(2.0, "c64"), (1.25, "c64"), (2.0, "c128")])
+# Default tiles of the 3-D 128^3 workload (M = 2^21): sparse node sets (under a quarter of a
+# node per grid point, sigma = 2) take tiles whose padded spreading tile fills the device's
+# LDS; at sigma = 1.25 the 64 KiB footprint is preferred (complex128 needs the whole LDS).
+TILE_3D = {(2.0, "c64"): (8, 16, 16), (1.25, "c64"): (8, 8, 8), (2.0, "c128"): (8, 8, 8),
+           (1.25, "c128"): (8, 10, 10)}
+SIGMA_DT_3D = [(2.0, "c64"), (1.25, "c64"), (2.0, "c128"), (1.25, "c128")]
+
+
+@pytest.mark.parametrize("sigma,dt", SIGMA_DT_3D)
 def test_3d_128(device, sigma, dt):
     N, m = (128, 128, 128), 4
     x = wl.workload_nodes("3d_n128_m2097152")
@@ -61,9 +70,10 @@ def test_3d_128(device, sigma, dt):
     f = wl.cn01(N, config=2, stream=1)
     fh = wl.cn01((M,), config=2, stream=2)
     p, xs = make_plan(device, x, N, m, sigma, dt)
+    print("case 3d", sigma, dt, p.info(), flush=True)
+    assert p.info()["tile"] == TILE_3D[(sigma, dt)]
     fg = p.forward(to_dev(f, dt, device)).cpu().numpy()
     yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
-    print("case 3d", sigma, dt, p.info(), flush=True)
     tol = e2e_tol(N, sigma, m, dt)
     # forward against the oracle NFFT on a node sample (its grid step is computed in full)
     g = np.random.default_rng(11)
@@ -75,6 +85,63 @@ def test_3d_128(device, sigma, dt):
     gate = NDFT_GATE[(m, sigma)] + tol
     ef, ea = rel2(fg[js2], fe), rel2(yg.reshape(-1)[ks], ye)
     assert ef < gate and ea < gate, (ef, ea, gate)
+
+
+def _box_index(lo, shape, Nt):
+    return np.ix_(*[(lo[d] + np.arange(shape[d])) % Nt[d] for d in range(len(Nt))])
+
+
+def _nodes_reaching_box(xs, Nt, m, lo, shape):
+    """Nodes whose stencil (2m points per axis from its origin, cyclic) meets the box."""
+    origin, _ = na._stencil(xs, Nt, m)
+    sel = np.ones(xs.shape[0], dtype=bool)
+    for d in range(len(Nt)):
+        r = np.mod(origin[:, d] - lo[d], Nt[d])
+        sel &= (r < shape[d]) | (r > Nt[d] - 2 * m)
+    return sel
+
+
+@pytest.mark.parametrize("sigma,dt", SIGMA_DT_3D)
+def test_3d_128_spread_grid_on_boxes(device, sigma, dt):
+    """The full-size adjoint resampling (spreading + halo merge over all 2^21 nodes, in the
+    default tiles bench.py times) element by element on boxes of grid points -- at the
+    origin, across the cyclic end of every axis and at a seeded ragged position -- against
+    the oracle's adjoint resampling of the nodes whose stencils reach each box."""
+    N, m = (128, 128, 128), 4
+    x = wl.workload_nodes("3d_n128_m2097152")
+    M = x.shape[0]
+    fh = wl.cn01((M,), config=2, stream=2)
+    p, xs = make_plan(device, x, N, m, sigma, dt)
+    Nt = p.Ntilde
+    print("spread boxes 3d", sigma, dt, p.info(), flush=True)
+    assert p.info()["tile"] == TILE_3D[(sigma, dt)]
+    grid = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy() * p.window_scale
+    g = np.random.default_rng(17)
+    boxes = [((0, 0, 0), (16, 16, 16)), (tuple(n - 12 for n in Nt), (20, 20, 20)),
+             (tuple(int(v) for v in g.integers(0, Nt[0], size=3)), (9, 17, 23))]
+    tol = C128_VS_ORACLE if dt == "c128" else C64_VS_ORACLE
+    for lo, shape in boxes:
+        sel = _nodes_reaching_box(xs, Nt, m, lo, shape)
+        ref = na.resample_adjoint(xs[sel], fh[sel], N, m, Nt)[_box_index(lo, shape, Nt)]
+        got = grid[_box_index(lo, shape, Nt)]
+        assert rel2(got, ref) < tol, (lo, shape, int(sel.sum()), rel2(got, ref), tol)
+
+
+@pytest.mark.parametrize("sigma,dt", SIGMA_DT_3D)
+def test_3d_128_adjoint_elementwise_on_subset(device, sigma, dt):
+    """The whole 3-D adjoint (spreading, merge, pruned adjoint FFT passes, crop and
+    correction) element by element against the oracle NFFT on a seeded 2^18-node subset of
+    the 128^3 workload, in the tiles the full workload uses."""
+    N, m = (128, 128, 128), 4
+    x = wl.workload_nodes("3d_n128_m2097152")
+    js = np.sort(np.random.default_rng(19).choice(x.shape[0], 1 << 18, replace=False))
+    fh = wl.cn01((x.shape[0],), config=2, stream=2)[js]
+    p, xs = make_plan(device, x[js], N, m, sigma, dt, tile=TILE_3D[(sigma, dt)])
+    print("adjoint subset 3d", sigma, dt, p.info(), flush=True)
+    yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    yo = na.adjoint(xs, fh, N, m, sigma)
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(yg, yo) < tol, (rel2(yg, yo), tol)
 
 
 def test_fp32_matches_fp64_on_gpu(device):

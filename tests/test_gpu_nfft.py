@@ -54,6 +54,21 @@ def e2e_tol(N, sigma, m, dt):
     return (10 * 2.0 ** -24 if dt == "c64" else 100 * 2.0 ** -53) * kappa(N, sigma, m) * lg / 8
 
 
+def direct_fp32_factor(N, m, sigma, window, dt):
+    """Gate multiplier for the window evaluated directly in FP32.  The rounded argument
+    beta s of sinh carries a relative error of about u beta s, which sinh turns into a
+    relative error of coth(beta s) beta s u <= (beta + 1) u; the square root, division and
+    normalisation add a few u more.  Per axis the weight is off by about (beta + 6) u of the
+    window's peak (the tails, where sqrt(1 - u^2) is small and the argument's relative error
+    is larger, are below 1e-3 of the peak), against the few u of the polynomial's Horner
+    evaluation that e2e_tol's constant 10 budgets for."""
+    if window != "direct" or dt != "c64":
+        return 1.0
+    Nt = na.oversampled_size(N, sigma)
+    beta = na.kb_beta(m, Nt[0] / N[0])
+    return 1.0 + len(N) * (beta + 6.0) / 10.0
+
+
 def rel2(a, b):
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()
@@ -109,9 +124,11 @@ def test_resampling_steps_match_oracle(device, dt, N, M, m, sigma):
     ghat = wl.cn01(Nt, config=81, stream=1)
     fh = wl.cn01((M,), config=81, stream=2)
     tol = C128_VS_ORACLE if dt == "c128" else C64_VS_ORACLE
-    got = p.resample_forward(to_dev(ghat, dt, device)).cpu().numpy()
+    # the library's window is the paper's divided by C = prod_d sinh(beta_d)/pi
+    C = p.window_scale
+    got = p.resample_forward(to_dev(ghat, dt, device)).cpu().numpy() * C
     assert rel2(got, na.resample_forward(xs, ghat, N, m, Nt)) < tol
-    spread = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    spread = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy() * C
     assert rel2(spread, na.resample_adjoint(xs, fh, N, m, Nt)) < tol
 
 
@@ -122,7 +139,7 @@ def test_forward_grid_is_F_D_f(device, dt):
     f = wl.cn01(N, config=82, stream=1)
     p, xs = make_plan(device, x, N, m, sigma, dt)
     p.forward(to_dev(f, dt, device))
-    g = p.grid().cpu().numpy()
+    g = p.grid().cpu().numpy() / p.window_scale
     _, st = na.forward(xs, f, m, sigma, return_steps=True)
     assert rel2(g, st["ghat"]) < (1e-13 if dt == "c128" else 2e-6)
 
@@ -155,6 +172,30 @@ def test_end_to_end_against_oracle_and_ndft(device, dt, N, M, m, sigma):
         assert max(rel2(fg, fe), rel2(yg, ye)) <= TARGET[(dt, m, sigma)]
 
 
+# complex64 plans whose raw window peaks, multiplied over the axes, leave the float range
+# (2-D m = 10: (sinh(beta)/pi)^2 ~ 5e39; 4-D m = 5, 6) or come close (3-D m = 5): the
+# library stores the window divided by its peak per axis and the resampling correction
+# multiplied by it, so the FP32 factors stay near 1.
+@pytest.mark.parametrize("N,M,m", [((64, 64), 3000, 10), ((24, 24, 24), 2000, 5),
+                                   ((10, 10, 10, 10), 1500, 5), ((12, 12, 12, 12), 400, 6)])
+def test_c64_large_m_against_oracle(device, N, M, m):
+    sigma, dt = 2.0, "c64"
+    D = len(N)
+    x = wl.uniform_nodes(M, D, config=88, stream=0)
+    f = wl.cn01(N, config=88, stream=1)
+    fh = wl.cn01((M,), config=88, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh)
+    print("c64 large m", N, m, p.info(), p.window_peaks(), flush=True)
+    assert np.all(np.isfinite(fg)) and np.all(np.isfinite(yg))
+    tol = e2e_tol(N, sigma, m, dt)
+    fo = na.forward(xs, f, m, sigma)
+    yo = na.adjoint(xs, fh, N, m, sigma)
+    assert rel2(fg, fo) < tol and rel2(yg, yo) < tol, (rel2(fg, fo), rel2(yg, yo), tol)
+    # the FP32 target against the NDFT
+    assert rel2(fg, ndft.ndft_forward(xs, f)) < TARGET[("c64", 4, 2.0)]
+    assert rel2(yg, ndft.ndft_adjoint(xs, fh, N)) < TARGET[("c64", 4, 2.0)]
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("N,M,m,sigma", [((128,), 300, 4, 2.0), ((64, 64), 4096, 6, 2.0),
                                          ((16, 16, 16), 3000, 4, 1.25)])
@@ -179,7 +220,7 @@ def test_direct_window_mode(device, dt):
     p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh, window="direct")
     fo = na.forward(xs, f, m, sigma, window="direct")
     yo = na.adjoint(xs, fh, N, m, sigma, window="direct")
-    tol = e2e_tol(N, sigma, m, dt)
+    tol = e2e_tol(N, sigma, m, dt) * direct_fp32_factor(N, m, sigma, "direct", dt)
     assert rel2(fg, fo) < tol and rel2(yg, yo) < tol, (rel2(fg, fo), rel2(yg, yo), tol)
 
 

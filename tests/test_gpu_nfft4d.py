@@ -157,9 +157,10 @@ def test_d4_single_steps_match_oracle(device, dt, N, M, m):
     ghat = wl.cn01(Nt, config=129, stream=1)
     fh = wl.cn01((M,), config=129, stream=2)
     tol = C128_VS_ORACLE if dt == "c128" else C64_VS_ORACLE
-    got = p.resample_forward(to_dev(ghat, dt, device)).cpu().numpy()
+    C = p.window_scale  # the library's window is the paper's divided by C
+    got = p.resample_forward(to_dev(ghat, dt, device)).cpu().numpy() * C
     assert rel2(got, na.resample_forward(xs, ghat, N, m, Nt)) < tol
-    spread = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    spread = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy() * C
     assert rel2(spread, na.resample_adjoint(xs, fh, N, m, Nt)) < tol
     ftol = 1e-13 if dt == "c128" else 2e-6
     fw = p.fft_grid(to_dev(ghat, dt, device), -1).cpu().numpy()

@@ -15,7 +15,7 @@ import torch
 import nfft_workloads as wl
 from oracle import ndft
 from oracle import nfft_alg as na
-from test_gpu_nfft import NDFT_GATE, e2e_tol, make_plan, rel2, to_dev
+from test_gpu_nfft import NDFT_GATE, direct_fp32_factor, e2e_tol, make_plan, rel2, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +64,14 @@ def test_linear_matches_oracle(device, N, M, m, sigma, dt):
     yo = na.adjoint(xs, fh, N, m, sigma, window="linear")
     assert rel2(fg.cpu().numpy(), fo) < tol and rel2(yg.cpu().numpy(), yo) < tol
     if (m, sigma) in NDFT_GATE:
-        gate = NDFT_GATE[(m, sigma)] + tol
-        assert rel2(fg.cpu().numpy(), ndft.ndft_forward(xs, f)) < 2 * gate
+        # linear interpolation in a table of spacing h = 1/(S-2) changes the window by at
+        # most h^2/8 max|psi''| <= h^2 beta^2/8 relative to its peak (measured on the CPU for
+        # these cases: the oracle's NDFT error moves by under 1e-10 relative)
+        Nt = na.oversampled_size(N, sigma)
+        beta = na.kb_beta(m, Nt[0] / N[0])
+        h = 1.0 / (na.linear_table_size(m) - 2)
+        gate = NDFT_GATE[(m, sigma)] + tol + len(N) * h * h * beta * beta / 8
+        assert rel2(fg.cpu().numpy(), ndft.ndft_forward(xs, f)) < gate
 
 
 # 3-D: the padded spreading tile (tile + 2m+1 halo, 16 B per cell in c64) must fit in LDS,
@@ -84,10 +90,11 @@ def test_wide_stencil_matches_oracle(device, window, N, M, m, sigma, dt):
     p, xs = make_plan(device, x, N, m, sigma, dt, window=window, wide=True)
     fg = p.forward(to_dev(f, dt, device)).cpu().numpy()
     yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
-    print("wide", window, N, m, dt, flush=True)
-    tol = e2e_tol(N, sigma, m, dt) * (30 if window == "direct" and dt == "c64" else 1)
-    assert rel2(fg, na.forward(xs, f, m, sigma, window=window, wide=True)) < tol
-    assert rel2(yg, na.adjoint(xs, fh, N, m, sigma, window=window, wide=True)) < tol
+    tol = e2e_tol(N, sigma, m, dt) * direct_fp32_factor(N, m, sigma, window, dt)
+    ef = rel2(fg, na.forward(xs, f, m, sigma, window=window, wide=True))
+    ea = rel2(yg, na.adjoint(xs, fh, N, m, sigma, window=window, wide=True))
+    print("wide", window, N, m, dt, "err/tol %.3f %.3f" % (ef / tol, ea / tol), flush=True)
+    assert ef < tol and ea < tol
 
 
 @pytest.mark.parametrize("m", [3, 4])

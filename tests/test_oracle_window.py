@@ -160,3 +160,50 @@ def test_kb_fourier_pair_beyond_the_support(m, sigma):
         # relative to the window's peak: the tail values are ~1/sinh(beta) of it
         assert abs(got - float(val)) <= 1e-13 * peak, (m, sigma, u)
     assert na.window_hat_full(1.0, beta) == beta / np.pi
+
+
+@pytest.mark.parametrize("m", [3, 4])
+def test_poly_fit_samples_the_sinh_limit_at_u_plus_one(m):
+    """Reading of the POLYNOMIAL fit's samples.  Tap 0's last sample lies at zeta = +1/2,
+    i.e. u = +1, just outside the half-open support, where the truncated window is 0.  The
+    oracle samples the continuous sinh form there (its limit beta/pi), so that tap 0's
+    polynomial stays close to the window on [-1/2, 1/2) up to the excluded endpoint.
+    Pinned by the mathematics: the NFFT error against the direct NDFT is lower than with the
+    literal truncated sample (planted here), at m = 3 and m = 4."""
+    import nfft_workloads as wl
+    from oracle import ndft
+    sigma = 2.0
+    N, M = (32, 32), 2000
+    x = wl.uniform_nodes(M, 2, config=90, stream=0)
+    f = wl.cn01(N, config=90, stream=1)
+    exact = ndft.ndft_forward(x, f)
+    beta = na.kb_beta(m, 2.0)
+    mu = na.poly_coeffs(m, beta)
+    # tap 0 at zeta = +1/2 reproduces the sinh limit to within the fit error
+    p0 = np.polynomial.polynomial.polyval(0.5, mu[0])
+    peak = np.sinh(beta) / np.pi
+    assert abs(p0 - beta / np.pi) < 1e-6 * peak
+
+    def err():
+        fh = na.forward(x, f, m, sigma)
+        return np.linalg.norm(fh - exact) / np.linalg.norm(exact)
+
+    ours = err()
+    Z = 2 * m + 1
+    zeta = -0.5 + np.arange(2 * Z) / (2 * Z - 1.0)
+    V = zeta[:, None] ** np.arange(Z)[None, :]
+
+    def literal(mm, b, **kw):
+        out = np.zeros((2 * mm, Z))
+        for t in range(2 * mm):
+            u = (zeta + mm - 0.5 - t) / mm
+            out[t] = np.linalg.lstsq(V, na.window_hat(u, b), rcond=None)[0]
+        return out
+
+    orig = na.poly_coeffs
+    try:
+        na.poly_coeffs = literal
+        planted = err()
+    finally:
+        na.poly_coeffs = orig
+    assert ours < planted, (ours, planted)
