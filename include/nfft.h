@@ -144,6 +144,11 @@ int nfft_forward(nfft_plan_t p, const void *f, void *fhat, void *stream);
 /*
  * Adjoint NFFT (Algorithm 2): y = D^T F^H B^T fhat.  fhat: M complex (device),
  * y: prod(N) complex (device), overwritten.  With M == 0, y is set to zero.
+ * Non-finite input: if any fhat value has a NaN or infinite part, every value of
+ * y is NaN (spreading accumulates in fixed point, where such a value would be
+ * lost; the work items holding one write NaN instead, and the FFT spreads it).
+ * The forward transform propagates a non-finite f value by IEEE arithmetic
+ * through its FFT (every fhat value non-finite).
  */
 int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream);
 

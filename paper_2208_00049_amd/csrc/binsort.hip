@@ -7,15 +7,14 @@
 // the tile that holds its origin, and by a class bit per axis that says whether
 // its stencil runs past the end of that tile into the next one.  Sort key =
 // tile << D | class.  The bin boundaries come from a histogram and an exclusive
-// scan; the order is a stable radix sort of (key, node index) pairs (rocPRIM),
-// so nodes of one bin keep the caller's order and a plan is a deterministic
-// function of its nodes (its work items, and with them every summation order,
-// do not depend on the scheduling of the plan-time kernels).
+// scan; the order is a stable sort of (key, node index) pairs -- least-significant
+// digit first, 8 bits per pass, each pass a stable counting sort -- so nodes of
+// one bin keep the caller's order and a plan is a deterministic function of its
+// nodes (its work items, and with them every summation order, do not depend on
+// the scheduling of the plan-time kernels).
 #include <math.h>
 
 #include <string.h>
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.hpp"
 #include "nfft_internal.hpp"
@@ -200,31 +199,139 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, hipStream_t s) 
     return hipGetLastError();
 }
 
+// ---- stable sort of (key, node index) pairs ----------------------------------
+//
+// Least-significant-digit radix sort, 8 bits per pass; each pass is a stable
+// counting sort of the current sequence by one digit:
+//   k_digit_hist    block b counts the digits of its run of kSortRun consecutive
+//                   items: hist[digit * nblocks + b];
+//   exclusive scan  of hist in (digit, block) order: the first output position of
+//                   every (digit, block) pair;
+//   k_digit_scatter block b walks its run again in order, 256 items at a time, and
+//                   sends each item to its pair's first position plus the number of
+//                   items of its digit before it in the run (a wavefront finds the
+//                   lanes with its digit by ballots over the digit's bits; per-wave
+//                   and running per-digit counts sit in LDS).
+// Items of equal digit keep their order, so after the passes over all key bits the
+// pairs are ordered by key and, within a key, by node index.
+
+constexpr int kSortThreads = 256;
+constexpr int kSortBins = 256;
+
+// Items per block: a multiple of kSortThreads that keeps the histogram (and its
+// single-workgroup scan) at most 2^24 entries.
+static int sort_run(int64_t M) {
+    int64_t chunks = 16;
+    while ((M + chunks * kSortThreads - 1) / (chunks * kSortThreads) * kSortBins > (1 << 24))
+        chunks *= 2;
+    return (int)(chunks * kSortThreads);
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+    k_digit_hist(const int *__restrict__ keys, int M, int shift, int run, int *__restrict__ hist) {
+    __shared__ int cnt[kSortBins];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int b = blockIdx.x;
+    const int end = min(M, (b + 1) * run);
+    for (int i = b * run + threadIdx.x; i < end; i += kSortThreads)
+        atomicAdd(&cnt[(keys[i] >> shift) & (kSortBins - 1)], 1);
+    __syncthreads();
+    hist[threadIdx.x * gridDim.x + b] = cnt[threadIdx.x];
+}
+
+// kout may be NULL (the last pass needs only the permutation).
+__global__ void __launch_bounds__(kSortThreads)
+    k_digit_scatter(const int *__restrict__ kin, const int *__restrict__ iin, int M, int shift,
+                    int run, const int *__restrict__ start, int *__restrict__ kout,
+                    int *__restrict__ iout) {
+    constexpr int W = kSortThreads / 64;
+    __shared__ int base[kSortBins];       // next output position of each digit in this run
+    __shared__ int wcnt[W][kSortBins];    // items of each digit in each wavefront of the round
+    const int b = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    base[threadIdx.x] = start[threadIdx.x * gridDim.x + b];
+    const int end = min(M, (b + 1) * run);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r0 = b * run; r0 < end; r0 += kSortThreads) {
+        for (int w = 0; w < W; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();  // also orders the base update of the previous round
+        const int i = r0 + threadIdx.x;
+        const bool live = i < end;
+        const int key = live ? kin[i] : 0;
+        const int val = live ? iin[i] : 0;
+        // digit, with bit 8 set for lanes past the end so that they match no item
+        const int dig = live ? (key >> shift) & (kSortBins - 1) : kSortBins;
+        unsigned long long peers = ~0ull;
+#pragma unroll
+        for (int bit = 0; bit < 9; ++bit) {
+            const unsigned long long bal = __ballot((dig >> bit) & 1);
+            peers &= ((dig >> bit) & 1) ? bal : ~bal;
+        }
+        const int rank = __popcll(peers & below);
+        // the lowest lane of each digit group records the group's size
+        if (live && rank == 0) wcnt[wave][dig] = __popcll(peers);
+        __syncthreads();
+        if (live) {
+            int pos = base[dig] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
+            if (kout) kout[pos] = key;
+            iout[pos] = val;
+        }
+        __syncthreads();  // every position of the round is taken before base moves on
+        int tot = 0;
+        for (int w = 0; w < W; ++w) tot += wcnt[w][threadIdx.x];
+        base[threadIdx.x] += tot;
+    }
+}
+
 static unsigned key_bits(int nkeys) {
     unsigned b = 1;
     while (b < 31 && (1u << b) < (unsigned)nkeys) ++b;
     return b;
 }
 
+// Scratch of the sort: a second key and index sequence, and the histogram with its scan.
 hipError_t node_sort_bytes(const nfft_plan_s &p, size_t *bytes) {
     *bytes = 0;
     if (p.M == 0) return hipSuccess;
-    return rocprim::radix_sort_pairs(nullptr, *bytes, (const int *)nullptr, (int *)nullptr,
-                                     (const int *)nullptr, (int *)nullptr, (int)p.M, 0,
-                                     key_bits(p.nkeys), (hipStream_t)0);
+    const int64_t nb = (p.M + sort_run(p.M) - 1) / sort_run(p.M);
+    *bytes = sizeof(int) * (2 * (size_t)p.M + 2 * ((size_t)kSortBins * nb + 1));
+    return hipSuccess;
 }
 
 hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int *keys_sorted,
                             int *idx, void *tmp, size_t tmp_bytes, hipStream_t s) {
     if (p.M == 0) return hipSuccess;
     const int M = (int)p.M;
+    const int run = sort_run(M);
+    const int nb = (M + run - 1) / run;
+    const int nh = kSortBins * nb;
+    size_t need = 0;
+    (void)node_sort_bytes(p, &need);
+    if (tmp_bytes < need) return hipErrorInvalidValue;
+    int *kb = (int *)tmp, *ib = kb + M, *hist = ib + M, *start = hist + nh + 1;
     hipLaunchKernelGGL(k_iota, grid1d(M, 256), dim3(256), 0, s, idx, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t bytes = tmp_bytes;
-    e = rocprim::radix_sort_pairs(tmp, bytes, keys, keys_sorted, (const int *)idx, p.perm, M, 0,
-                                  key_bits(p.nkeys), s);
-    if (e != hipSuccess) return e;
+    const int passes = (int)(key_bits(p.nkeys) + 7) / 8;
+    const int *kin = keys, *iin = idx;
+    for (int pass = 0; pass < passes; ++pass) {
+        const bool last = pass == passes - 1;
+        // intermediate sequences alternate between (kb, ib) and (keys_sorted, idx)
+        int *kout = last ? nullptr : (pass % 2 == 0 ? kb : keys_sorted);
+        int *iout = last ? p.perm : (pass % 2 == 0 ? ib : idx);
+        hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortThreads), 0, s, kin, M, 8 * pass, run,
+                           hist);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_exclusive_scan(hist, start, nh, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, kin, iin, M,
+                           8 * pass, run, start, kout, iout);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        kin = kout;
+        iin = iout;
+    }
     const bool f = p.dtype == NFFT_C64;
     switch (p.D) {
         case 1: f ? gather_t<float, 1>(p, x, s) : gather_t<double, 1>(p, x, s); break;

@@ -406,16 +406,18 @@ __global__ void __launch_bounds__(kOwnerThreads)
         for (int q = threadIdx.x; q < total; q += blockDim.x) {
             while (nb_pre[i + 1] <= q) ++i;
             const C v = fhat[perm[nb_begin[i] + (q - nb_pre[i])]];
-            amax = fmax(amax, fmax(fabs(v.x), fabs(v.y)));
+            amax = fmax(amax, scale_mag(v.x, v.y));
         }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
     if (lane == 0) atomicMax(&amax_bits, (unsigned long long)__double_as_longlong((double)amax));
     __syncthreads();
-    const double bound = __longlong_as_double((long long)amax_bits) * (double)wmax_prod;
+    const double amax_d = __longlong_as_double((long long)amax_bits);
+    const bool poisoned = isinf(amax_d);  // a non-finite candidate value (same in every thread)
+    const double bound = amax_d * (double)wmax_prod;
     T scale = (T)1;
-    if (bound > 0.0) {
+    if (bound > 0.0 && !poisoned) {
         int e;
         (void)frexp(FP::kLimit / bound, &e);
         scale = (T)ldexp(1.0, e - 1);
@@ -424,7 +426,7 @@ __global__ void __launch_bounds__(kOwnerThreads)
     const TapCoef<T, M2> tc = owner_coef<T, D, M2>(coef, window, wp.m);
     constexpr int CH = OwnerStage<T, D, M2>::CH;
     int parity = 0;
-    for (int c0 = 0; c0 < total; c0 += CH, parity ^= 1) {
+    for (int c0 = 0; c0 < (poisoned ? 0 : total); c0 += CH, parity ^= 1) {
         const int n = min(CH, total - c0);
         owner_stage<T, D, M2>(st, c0, n, ot, g, nb_begin, nb_pre, nodes, perm, fhat, tc, window,
                               wp);
@@ -448,11 +450,13 @@ __global__ void __launch_bounds__(kOwnerThreads)
         __syncthreads();
     }
     const T inv = (T)(1.0 / (double)scale);
+    const T nan = (T)__builtin_nan("");
     for (int c = threadIdx.x; c < ot.cells; c += blockDim.x) {
         int li;
         const long long gi = owner_global<D>(ot, g, lay, c, &li);
-        grid[gi] = cmake<C>((T)FP::read(acc + li, lay.cells, 0) * inv,
-                            (T)FP::read(acc + li, lay.cells, 1) * inv);
+        grid[gi] = poisoned ? cmake<C>(nan, nan)
+                            : cmake<C>((T)FP::read(acc + li, lay.cells, 0) * inv,
+                                       (T)FP::read(acc + li, lay.cells, 1) * inv);
     }
 }
 

@@ -531,6 +531,15 @@ __global__ void __launch_bounds__(NT)
 // lo][Im hi][Im lo].
 template <typename T> struct FixedPoint;
 
+// Magnitude a value contributes to the fixed-point scale: max(|Re|, |Im|), or +infinity
+// when either part is NaN or infinite (fmax alone would skip a NaN).  A work item whose
+// maximum is infinite holds a non-finite value: it skips the accumulation (whose integer
+// conversion would drop a NaN and saturate on an infinity) and writes NaN instead, which
+// the halo merge and the FFT carry to every output of the adjoint.
+template <typename T> __device__ inline T scale_mag(T re, T im) {
+    return (isfinite(re) && isfinite(im)) ? fmax(fabs(re), fabs(im)) : (T)INFINITY;
+}
+
 template <> struct FixedPoint<float> {
     static constexpr int kSlots = 1;  // int64 slots per component
     static constexpr double kLimit = 1073741824.0;  // 2^30
@@ -638,7 +647,7 @@ __global__ void __launch_bounds__(NT)
                 }
                 st.vr[k] = val[j].x;
                 st.vi[k] = val[j].y;
-                mx = fmax(mx, fmax(fabs(val[j].x), fabs(val[j].y)));
+                mx = fmax(mx, scale_mag(val[j].x, val[j].y));
             }
         }
         return mx;
@@ -649,7 +658,7 @@ __global__ void __launch_bounds__(NT)
     T amax = stage_chunk_nodes(sp.y, min(CH, nitem));
     for (int v = CH + threadIdx.x; v < nitem; v += NT) {
         const C val = fhat[perm[sp.y + v]];
-        amax = fmax(amax, fmax(fabs(val.x), fabs(val.y)));
+        amax = fmax(amax, scale_mag(val.x, val.y));
     }
     // wavefront maximum, then one LDS atomic per wavefront (non-negative values
     // order like their bit patterns)
@@ -660,15 +669,17 @@ __global__ void __launch_bounds__(NT)
     __syncthreads();
     // power-of-two scale: every |contribution| * scale stays below the limit;
     // with limit/bound = f 2^e, f in [0.5, 1): scale = 2^(e-1)
-    const double bound = __longlong_as_double((long long)amax_bits) * (double)wmax_prod;
+    const double amax_d = __longlong_as_double((long long)amax_bits);
+    const bool poisoned = isinf(amax_d);  // a non-finite value in the item (same in every thread)
+    const double bound = amax_d * (double)wmax_prod;
     T scale = (T)1;
-    if (bound > 0.0) {
+    if (bound > 0.0 && !poisoned) {
         int e;
         (void)frexp(FP::kLimit / bound, &e);
         scale = (T)ldexp(1.0, e - 1);
     }
 
-    for (int c0 = sp.y; c0 < sp.z; c0 += CH) {
+    for (int c0 = sp.y; c0 < (poisoned ? sp.y : sp.z); c0 += CH) {
         const int n = min(CH, sp.z - c0);
         if (c0 > sp.y) {
             (void)stage_chunk_nodes(c0, n);
@@ -717,12 +728,14 @@ __global__ void __launch_bounds__(NT)
         __syncthreads();
     }
 
-    // the padded tile goes to the item's scratch slot, unscaled
+    // the padded tile goes to the item's scratch slot, unscaled (NaN for a non-finite item)
     const T inv = (T)(1.0 / (double)scale);
+    const T nan = (T)__builtin_nan("");
     C *out = pad + (size_t)blockIdx.x * ptot;
     for (int idx = threadIdx.x; idx < ptot; idx += NT) {
         const unsigned long long *ap = acc + idx;
-        out[idx] = cmake<C>((T)FP::read(ap, ptot, 0) * inv, (T)FP::read(ap, ptot, 1) * inv);
+        out[idx] = poisoned ? cmake<C>(nan, nan)
+                            : cmake<C>((T)FP::read(ap, ptot, 0) * inv, (T)FP::read(ap, ptot, 1) * inv);
     }
 }
 

@@ -266,6 +266,33 @@ def test_edge_node_sets(device, dt, kind):
     assert rel2(fg, fo) < tol and rel2(yg, yo) < tol, (rel2(fg, fo), rel2(yg, yo), tol)
 
 
+@pytest.mark.parametrize("bad", ["nan", "inf"])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M", [((64,), 300), ((32, 32), 2000), ((16, 16, 16), 3000),
+                                 ((8, 8, 8, 8), 1500)])
+def test_non_finite_values(device, N, M, dt, bad):
+    """One NaN or infinite part in fhat makes every value of the adjoint NaN (the
+    fixed-point spreading would otherwise drop a NaN and saturate on an infinity); one in
+    f makes every forward value non-finite.  The plan is left intact for finite inputs."""
+    D = len(N)
+    x = wl.uniform_nodes(M, D, config=89, stream=0)
+    f = wl.cn01(N, config=89, stream=1)
+    fh = wl.cn01((M,), config=89, stream=2)
+    v = np.nan if bad == "nan" else np.inf
+    fb, fhb = f.copy(), fh.copy()
+    fb.flat[f.size // 3] = complex(0.25, v)
+    fhb[M // 2] = complex(v, -0.5)
+    p, xs, fg, yg = run_pair(device, x, N, 4, 2.0, dt, fb, fhb)
+    print("non-finite", N, dt, bad, flush=True)
+    assert np.isnan(yg).all()
+    assert not np.isfinite(fg).any()
+    tol = e2e_tol(N, 2.0, 4, dt)
+    fg = p.forward(to_dev(f, dt, device)).cpu().numpy()
+    yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
+    assert rel2(fg, na.forward(xs, f, 4, 2.0)) < tol
+    assert rel2(yg, na.adjoint(xs, fh, N, 4, 2.0)) < tol
+
+
 def test_nan_node_is_rejected(device):
     from paper_2208_00049_amd import NfftError, Plan
     x = torch.zeros((10, 2), dtype=torch.float64, device=device)
