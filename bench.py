@@ -116,7 +116,25 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run --steps device-to-device copies of this many bytes (a "
                          "reference kernel for calibrating HBM traffic counters)")
+    ap.add_argument("--lds-calibrate", action="store_true",
+                    help="only measure the LDS operation rates of the device (the roof of the "
+                         "spreading kernels' LDS atomics) and print them as one JSON line")
     return ap.parse_args()
+
+
+def lds_calibration(reps=20):
+    """Rates of the LDS operations spreading relies on, in lane operations per clock per
+    compute unit (clock 2.4 GHz, 256 CUs) and in T lane-ops/s for the chip."""
+    import torch
+    from paper_2208_00049_amd import calibrate_lds
+    from paper_2208_00049_amd._lib import LDS_OPS
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = {"cus": cus, "clock_ghz": 2.4, "patterns": ["consecutive", "random", "rows_of_8"],
+           "unit": "lane ops per clock per CU", "rates": {}}
+    for op in LDS_OPS:
+        out["rates"][op] = [round(calibrate_lds(op, pat, reps) / (cus * 2.4e9), 3)
+                            for pat in range(3)]
+    return out
 
 
 def copy_reference(nbytes, steps):
@@ -460,6 +478,9 @@ def main():
     if args.copy_bytes:
         copy_reference(args.copy_bytes, args.steps)
         return
+    if args.lds_calibrate:
+        print(json.dumps(lds_calibration()), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path; a plan runs on one device "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -569,16 +590,20 @@ def main():
                 "algorithmic_bytes": algo[dominant], "launch_ms": round(dom_ms, 5)}
 
     # spreading's own roof: its 64-bit LDS atomics (one per component and tap for c64,
-    # two for c128), against the rate a microbenchmark measured for ds_add_u64 on
-    # consecutive addresses (9.5 lane operations per clock per CU)
+    # two for c128), against the ds_add_u64 rate the library's calibration kernel
+    # measures in this run for the access shape of one spreading instruction (eight
+    # rows of eight consecutive words at random starts)
+    from paper_2208_00049_amd import calibrate_lds
     taps = 2 * args.m + (2 if args.wide else 0)
     atomics = w["M"] * taps ** w["D"] * (2 if args.dtype == "c64" else 4)
-    lds_peak = 9.5 * 256 * 2.4e9
+    lds_peak = calibrate_lds("ds_add_u64", 2)
     spread_ms = b2b.get("spread", avg_ms.get("spread"))
     lds_roof = None
     if spread_ms:
         rate = atomics / (spread_ms * 1e-3)
         lds_roof = {"kernel": "spread", "bound": "lds_atomic", "atomic_lane_ops": atomics,
+                    "peak_source": "ds_add_u64, rows of 8 consecutive words, measured in this run "
+                                   "(python bench.py --lds-calibrate)",
                     "achieved": round(rate / 1e12, 4), "peak": round(lds_peak / 1e12, 4),
                     "unit": "T lane-ops/s", "frac": round(rate / lds_peak, 4)}
     fwd_fft_ms = sum(v for k, v in avg_ms.items() if k.startswith("fwd_"))

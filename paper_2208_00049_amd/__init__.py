@@ -4,4 +4,4 @@
 ``Plan.adjoint`` run the transforms in the library's HIP kernels.
 """
 from ._lib import NfftError, load  # noqa: F401
-from .nfft import Batch, Plan, nfft, nfft_adjoint  # noqa: F401
+from .nfft import Batch, Plan, calibrate_lds, nfft, nfft_adjoint  # noqa: F401

@@ -32,8 +32,10 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
            "nfft_plan_bench_stage", "nfft_forward_many", "nfft_adjoint_many",
            "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
            "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror",
-           "nfft_plan_window_peak"]
+           "nfft_plan_window_peak", "nfft_calibrate_lds"]
 NFFT_NUM_STAGES = 8
+LDS_OPS = {"ds_add_u32": 0, "ds_add_u64": 1, "ds_add_f32": 2, "ds_add_f64": 3,
+           "ds_write_b64": 4, "rmw_b64": 5}
 STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
           "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]
 
@@ -98,6 +100,8 @@ def load():
                                            ctypes.POINTER(ctypes.c_double)]
     lib.nfft_forward_deriv.argtypes = [vp, vp, vp, vp]
     lib.nfft_node_grad.argtypes = [vp, vp, vp, vp, vp]
+    lib.nfft_calibrate_lds.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                       ctypes.POINTER(ctypes.c_double)]
     lib.nfft_strerror.argtypes = [ctypes.c_int]
     lib.nfft_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:

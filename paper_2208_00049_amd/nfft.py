@@ -346,3 +346,15 @@ def nfft(x, f, m=4, sigma=2.0, **kw):
 def nfft_adjoint(x, N, fhat, m=4, sigma=2.0, **kw):
     """One-shot adjoint NFFT: y_n ~= sum_j fhat_j exp(+2 pi i n.x_j)."""
     return Plan(x, tuple(N), m=m, sigma=sigma, **kw).adjoint(fhat)
+
+def calibrate_lds(op, pattern=0, reps=20, device=None):
+    """Lane operations per second of one LDS operation on the current device
+    (``op``: a key of ``_lib.LDS_OPS``; ``pattern``: 0 consecutive, 1 random,
+    2 eight-lane rows at random starts), measured by the library's kernel."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    out = ctypes.c_double()
+    _lib.check(_lib.load().nfft_calibrate_lds(_lib.LDS_OPS[op], int(pattern), int(reps),
+                                              _stream_handle(device), ctypes.byref(out)),
+               "nfft_calibrate_lds")
+    return out.value
+
