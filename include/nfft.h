@@ -63,7 +63,8 @@ enum {
     NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (D > 4, ...) */
     NFFT_ERR_NOMEM = -3,       /* device allocation failed */
     NFFT_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch failure, ...) */
-    NFFT_ERR_NODES = -5        /* a node coordinate is NaN or infinite */
+    NFFT_ERR_NODES = -5,       /* a node coordinate is NaN or infinite */
+    NFFT_ERR_SCRATCH = -6      /* request larger than the static scratch (no-allocation call) */
 };
 
 /* Window evaluation inside the resampling kernels. */
@@ -165,6 +166,23 @@ int nfft_adjoint(nfft_plan_t p, const void *fhat, void *y, void *stream);
  */
 int nfft_forward_many(nfft_plan_t p, int K, const void *f, void *fhat, void *stream);
 int nfft_adjoint_many(nfft_plan_t p, int K, const void *fhat, void *y, void *stream);
+
+/*
+ * Multi-channel forward transform that allocates nothing, for callers that
+ * cannot call hipMalloc (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Arguments, layouts and results are those
+ * of nfft_forward_many (bit for bit: the same kernels), but the K oversampled
+ * grids live in a static device array of NFFT_NOALLOC_SCRATCH_BYTES bytes that
+ * the library holds on every GPU it runs on until the process ends, instead of
+ * the plan's multi-channel buffers.  Requires K * prod(Ntilde) * (8 for
+ * NFFT_C64, 16 for NFFT_C128) <= NFFT_NOALLOC_SCRATCH_BYTES, else returns
+ * NFFT_ERR_SCRATCH without touching the GPU.  The array is shared by every
+ * plan on a GPU: calls on one GPU whose executions overlap (other streams,
+ * other threads) race on it and must be ordered by the caller.  Its contents
+ * after a call are those of that call's grids; nothing needs to be cleared.
+ */
+#define NFFT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nfft_forward_many_noalloc(nfft_plan_t p, int K, const void *f, void *fhat, void *stream);
 
 /*
  * Derivatives with respect to the nodes (for differentiable use).

@@ -16,6 +16,8 @@ NFFT_ERR_UNSUPPORTED = -2
 NFFT_ERR_NOMEM = -3
 NFFT_ERR_HIP = -4
 NFFT_ERR_NODES = -5
+NFFT_ERR_SCRATCH = -6
+NOALLOC_SCRATCH_BYTES = 64 << 20  # NFFT_NOALLOC_SCRATCH_BYTES
 NFFT_C64 = 0
 NFFT_C128 = 1
 NFFT_WINDOW_POLY = 0
@@ -32,7 +34,7 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
            "nfft_plan_bench_stage", "nfft_forward_many", "nfft_adjoint_many",
            "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
            "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror",
-           "nfft_plan_window_peak", "nfft_calibrate_lds"]
+           "nfft_plan_window_peak", "nfft_calibrate_lds", "nfft_forward_many_noalloc"]
 NFFT_NUM_STAGES = 8
 LDS_OPS = {"ds_add_u32": 0, "ds_add_u64": 1, "ds_add_f32": 2, "ds_add_f64": 3,
            "ds_write_b64": 4, "rmw_b64": 5}
@@ -87,6 +89,7 @@ def load():
                                           ctypes.POINTER(ctypes.c_double)]
     lib.nfft_forward_many.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.nfft_adjoint_many.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.nfft_forward_many_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.nfft_batch_create.argtypes = [plan_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                       ctypes.c_int]
     lib.nfft_batch_forward.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p),

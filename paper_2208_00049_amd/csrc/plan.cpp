@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "nfft_internal.hpp"
@@ -389,6 +390,7 @@ const char *nfft_strerror(int code) {
         case NFFT_ERR_NOMEM: return "device memory allocation failed";
         case NFFT_ERR_HIP: return "HIP runtime error";
         case NFFT_ERR_NODES: return "node coordinate is NaN or infinite";
+        case NFFT_ERR_SCRATCH: return "request exceeds the library's static device scratch";
         default: return "unknown error";
     }
 }
@@ -953,3 +955,54 @@ int nfft_fft_grid(nfft_plan_t p, void *grid, int direction, void *stream) {
 }
 
 }  // extern "C"
+
+// ---- multi-channel forward without allocation -----------------------------
+
+namespace {
+
+// Device scratch of nfft_forward_many_noalloc: the K oversampled grids of a
+// call, in a file-scope device array so that the call allocates nothing.  Each
+// GPU the library runs on holds its own copy of it until the process ends.
+static __device__ __align__(256) unsigned char scratch[NFFT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+// Device address of device dev's copy of `scratch`, resolved once per device with
+// that device current (in host code the array's name is a stand-in, not a device
+// address: only the resolved pointer may be passed to kernels).
+hipError_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = ptr;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int nfft_forward_many_noalloc(nfft_plan_t p, int K, const void *f, void *fhat,
+                                         void *stream) {
+    if (!p || K < 1 || K > kMaxChannels || !f || (p->M > 0 && !fhat)) return NFFT_ERR_ARG;
+    if ((uint64_t)K * (uint64_t)p->G * csize(p->dtype) > (uint64_t)NFFT_NOALLOC_SCRATCH_BYTES)
+        return NFFT_ERR_SCRATCH;
+    if (p->M == 0) return NFFT_OK;
+    // every grid value the forward passes read is written first in the same call (the
+    // first pass writes whole lines of the band rows, later passes read only those),
+    // so the scratch needs no clearing between calls
+    void *grids = nullptr;
+    hipError_t e = scratch_address(p->device, &grids);
+    if (e == hipSuccess) e = run_forward(*p, f, fhat, K, grids, (hipStream_t)stream);
+    return hip_rc(e);
+}

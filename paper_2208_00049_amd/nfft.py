@@ -183,16 +183,21 @@ class Plan:
         return out
 
     # -- multi-channel ---------------------------------------------------------
-    def forward_many(self, f, out=None):
-        """K channels at once: f has shape (K, *N), the result (K, M)."""
+    def forward_many(self, f, out=None, noalloc=False):
+        """K channels at once: f has shape (K, *N), the result (K, M).  With noalloc, the
+        library's no-allocation variant (its K grids in the library's static device
+        scratch; ``out`` must then be given, since allocating it would defeat the point)."""
         K = int(f.shape[0]) if f.dim() == self.D + 1 else -1
         self._check(f, (K,) + self.N, "f")
         if out is None:
+            if noalloc:
+                raise ValueError("forward_many(noalloc=True) needs an output buffer")
             out = torch.empty((K, self.M), dtype=self.cdtype, device=self.device)
         self._check(out, (K, self.M), "out")
-        rc = self._lib.nfft_forward_many(self._h, K, ctypes.c_void_p(f.data_ptr()),
-                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(self.device))
-        _lib.check(rc, "nfft_forward_many")
+        fn = self._lib.nfft_forward_many_noalloc if noalloc else self._lib.nfft_forward_many
+        rc = fn(self._h, K, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                _stream_handle(self.device))
+        _lib.check(rc, "nfft_forward_many_noalloc" if noalloc else "nfft_forward_many")
         return out
 
     def adjoint_many(self, fhat, out=None):
@@ -346,6 +351,7 @@ def nfft(x, f, m=4, sigma=2.0, **kw):
 def nfft_adjoint(x, N, fhat, m=4, sigma=2.0, **kw):
     """One-shot adjoint NFFT: y_n ~= sum_j fhat_j exp(+2 pi i n.x_j)."""
     return Plan(x, tuple(N), m=m, sigma=sigma, **kw).adjoint(fhat)
+
 
 def calibrate_lds(op, pattern=0, reps=20, device=None):
     """Lane operations per second of one LDS operation on the current device
