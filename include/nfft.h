@@ -101,8 +101,20 @@ typedef struct {
                              beyond its truncation interval (the alternative of subsection
                              "Window Size Considerations"); 0 (default): 2m points.  Not
                              available with NFFT_WINDOW_LINEAR. */
-    int reserved[3];      /* must be zero */
+    int spread;           /* 3-D spreading scheme: NFFT_SPREAD_AUTO (0, default): column
+                             sweeps where available, else padded tiles; NFFT_SPREAD_TILED:
+                             padded tiles merged afterwards, exact fixed-point sums in both
+                             types (bitwise reproducible); NFFT_SPREAD_SWEEP: column sweeps,
+                             NFFT_ERR_UNSUPPORTED where not available.  Column sweeps need
+                             D = 3, Ntilde_1 and Ntilde_2 multiples of 16 (>= 32), 2m <= 10,
+                             the 2m-point stencil and tiles of 16 along axes 1 and 2;
+                             complex64 sums stay exact, complex128 sums use FP64 LDS
+                             atomics (correct to rounding; the last bits can differ between
+                             calls).  Ignored for D != 3. */
+    int reserved[2];      /* must be zero */
 } nfft_options;
+
+enum { NFFT_SPREAD_AUTO = 0, NFFT_SPREAD_TILED = 1, NFFT_SPREAD_SWEEP = 2 };
 
 /*
  * Create a plan (Algorithm 1/2 inputs D, m, N, Ntilde and the nodes).
@@ -276,6 +288,12 @@ int nfft_plan_grid(nfft_plan_t p, void **grid);
  * single steps above).  peak: host array of D doubles.  An extension of the
  * introspection calls; NFFT_ERR_ARG for a NULL argument. */
 int nfft_plan_window_peak(nfft_plan_t p, double *peak);
+
+/* The spreading scheme the plan uses (an extension of the introspection calls):
+ * *scheme = NFFT_SPREAD_SWEEP for 3-D plans that spread by column sweeps,
+ * NFFT_SPREAD_TILED otherwise (padded tiles, or for D = 4 tile owners).
+ * NFFT_ERR_ARG for a NULL argument. */
+int nfft_plan_spread(nfft_plan_t p, int *scheme);
 
 /*
  * Per-kernel timing.  With timing enabled, nfft_forward and nfft_adjoint

@@ -34,7 +34,9 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
            "nfft_plan_bench_stage", "nfft_forward_many", "nfft_adjoint_many",
            "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
            "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror",
-           "nfft_plan_window_peak", "nfft_calibrate_lds", "nfft_forward_many_noalloc"]
+           "nfft_plan_window_peak", "nfft_calibrate_lds", "nfft_forward_many_noalloc",
+           "nfft_plan_spread"]
+SPREAD = {"auto": 0, "tiled": 1, "sweep": 2}
 NFFT_NUM_STAGES = 8
 LDS_OPS = {"ds_add_u32": 0, "ds_add_u64": 1, "ds_add_f32": 2, "ds_add_f64": 3,
            "ds_write_b64": 4, "rmw_b64": 5}
@@ -45,7 +47,7 @@ STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "sp
 class Options(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int * 4), ("window", ctypes.c_int),
                 ("max_block_nodes", ctypes.c_int), ("wide", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("spread", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class NfftError(RuntimeError):
@@ -83,6 +85,7 @@ def load():
                                    ctypes.POINTER(ctypes.c_int)]
     lib.nfft_plan_grid.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p)]
     lib.nfft_plan_window_peak.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.nfft_plan_spread.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.nfft_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.nfft_plan_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.nfft_plan_bench_stage.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp,

@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "runtime.cpp", "precompute.hip", "binsort.hip", "fft.hip", "resample.hip",
-           "calibrate.hip"]
+           "calibrate.hip", "spread_sweep.hip"]
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -108,6 +108,23 @@ template <typename T, int D> struct NodeRec {
     T fr[D];
 };
 
+// Three-dimensional column-sweep spreading (spread_sweep.hip): columns of
+// kSweepQ x kSweepQ grid points along axes 1 and 2, each cut into nsc segments
+// of L tiles along axis 0; a segment's workgroup keeps a ring of R = Q_0 + taps - 1
+// padded planes in LDS.  Scratch per channel: main_cells values (every grid plane
+// of every column, padded to (kSweepQ + taps - 1)^2 points), then per segment its
+// taps - 1 trailing halo planes.
+constexpr int kSweepQ = 16;
+constexpr int kSweepMaxSegTiles = 64;
+struct SweepGeom {
+    int on;              // 1: the plan spreads by column sweeps
+    int ncols;           // columns (T_1 T_2)
+    int nsc;             // segments per column
+    int L;               // tiles per segment (divides T_0)
+    int R;               // ring planes
+    long long main_cells;
+};
+
 // Factorisation of one FFT line length and its twiddle table exp(-2 pi i t / L).
 struct FftLine {
     int L;
@@ -204,6 +221,7 @@ struct nfft_plan_s {
     int many_cap = 0;              // channels the two buffers hold
     void *twiddle[nfft::kMaxD] = {};
     nfft::FftLine line[nfft::kMaxD];
+    nfft::SweepGeom sweep{};       // 3-D column-sweep spreading (sweep.on)
 
     // optional per-stage timing (events recorded around each kernel launch)
     bool timing = false;
@@ -281,5 +299,21 @@ hipError_t launch_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfh
 // merge = false: only the padded tiles are produced (the next pass merges them)
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                          bool merge = true, int K = 1, void *pad = nullptr);
+
+// spread_sweep.hip: column-sweep spreading and its merge into grid (K channels)
+hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                               int K, void *pad);
+// static LDS of the sweep kernel (staged chunk, segment tables)
+size_t sweep_static_lds(int dtype);
+// points of one padded column plane
+inline int sweep_plane_cells(int taps) { return (kSweepQ + taps - 1) * (kSweepQ + taps - 1); }
+// dynamic LDS of the sweep kernel: R planes, two 8-byte words per point
+inline size_t sweep_ring_bytes(int R, int taps) { return (size_t)R * 2 * sweep_plane_cells(taps) * 8; }
+inline size_t sweep_ring_bytes(const nfft_plan_s &p) { return sweep_ring_bytes(p.sweep.R, p.geom.taps); }
+// scratch values per channel: the column planes and the segments' halo planes
+inline size_t sweep_scratch_cells(const nfft_plan_s &p) {
+    return (size_t)p.sweep.main_cells + (size_t)p.sweep.ncols * p.sweep.nsc * (p.geom.taps - 1) *
+                                            sweep_plane_cells(p.geom.taps);
+}
 
 }  // namespace nfft

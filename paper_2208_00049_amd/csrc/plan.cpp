@@ -53,6 +53,7 @@ size_t csize(nfft_dtype t) { return t == NFFT_C64 ? 8 : 16; }
 // Complex values of spreading scratch per channel: the work items' padded tiles
 // (D <= 3; D = 4 spreads straight into the grid).
 size_t scratch_cells(const nfft_plan_s &p) {
+    if (p.sweep.on) return p.M > 0 ? sweep_scratch_cells(p) : 0;
     if (p.nsub == 0 || p.D > 3) return 0;
     return (size_t)p.nsub * padded_cells(p.geom, p.D);
 }
@@ -285,6 +286,67 @@ void vandermonde_qr(int Z, int Theta, std::vector<double> &qt, std::vector<doubl
         for (int j = 0; j < Z; ++j) qt[(size_t)j * Theta + i] = E[(size_t)i * Z + j];
 }
 
+// Compute units of a device (segments of the column sweep are sized to fill them).
+int cus_of(int dev) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus;
+}
+
+// Column-sweep spreading for a 3-D plan (see spread_sweep.hip): tiles (Q_0, 16, 16)
+// with the largest Q_0 in {8, 4, 2, 1} (or the requested one) whose ring of
+// Q_0 + taps - 1 planes fits the LDS beside the staged nodes, and whose
+// interpolation tile fits too; segments of L tiles along axis 0, L the smallest
+// divisor of T_0 that gives at most about four segments per compute unit and
+// spans >= taps - 1 planes.  Fills p.sweep and Q; false if the plan cannot sweep.
+bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q) {
+    const int taps = 2 * p.m + (p.wide ? 2 : 0);
+    if (p.D != 3 || p.wide || taps > 10) return false;
+    for (int d = 1; d < 3; ++d)
+        if (p.Nt[d] % kSweepQ || p.Nt[d] < 2 * kSweepQ) return false;
+    const size_t cs = csize(p.dtype);
+    const size_t budget = dev_lds - 1024;
+    auto fits = [&](int q0) {
+        if (q0 < 1 || p.Nt[0] % q0 || p.Nt[0] / q0 < 2) return false;
+        const int q[3] = {q0, kSweepQ, kSweepQ};
+        return sweep_ring_bytes(q0 + taps - 1, taps) + sweep_static_lds(p.dtype) <= budget &&
+               interp_lds(q, 3, taps, cs) <= budget;
+    };
+    int q0 = 0;
+    if (req && (req[0] || req[1] || req[2])) {
+        if (req[1] != kSweepQ || req[2] != kSweepQ || !fits(req[0])) return false;
+        q0 = req[0];
+    } else {
+        for (int c : {8, 4, 2, 1})
+            if (fits(c)) {
+                q0 = c;
+                break;
+            }
+        if (!q0) return false;
+    }
+    const int T0 = (int)(p.Nt[0] / q0);
+    const int ncols = (int)(p.Nt[1] / kSweepQ) * (int)(p.Nt[2] / kSweepQ);
+    const int lmin = std::max(1, (taps - 1 + q0 - 1) / q0);
+    const int target = std::max(1, 4 * cus / ncols);  // segments per column
+    int L = 0;
+    for (int l = lmin; l <= std::min(T0, kSweepMaxSegTiles); ++l)
+        if (T0 % l == 0) {
+            L = l;  // the largest valid one so far
+            if (T0 / l <= target) break;
+        }
+    if (!L) return false;
+    p.sweep.on = 1;
+    p.sweep.ncols = ncols;
+    p.sweep.L = L;
+    p.sweep.nsc = T0 / L;
+    p.sweep.R = q0 + taps - 1;
+    p.sweep.main_cells = (long long)p.Nt[0] * ncols * sweep_plane_cells(taps);
+    Q[0] = q0;
+    Q[1] = Q[2] = kSweepQ;
+    return true;
+}
+
 int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double sigma, int dtype,
              const nfft_options *opts) {
     if (D < 1) return NFFT_ERR_ARG;
@@ -311,7 +373,8 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
         if (opts->wide != 0 && opts->wide != 1) return NFFT_ERR_ARG;
         if (opts->wide && opts->window == NFFT_WINDOW_LINEAR) return NFFT_ERR_UNSUPPORTED;
         if (opts->max_block_nodes < 0) return NFFT_ERR_ARG;
-        for (int i = 0; i < 3; ++i)
+        if (opts->spread < NFFT_SPREAD_AUTO || opts->spread > NFFT_SPREAD_SWEEP) return NFFT_ERR_ARG;
+        for (int i = 0; i < 2; ++i)
             if (opts->reserved[i]) return NFFT_ERR_ARG;
         for (int d = 0; d < kMaxD; ++d)
             if (opts->tile[d] < 0 || (d >= D && opts->tile[d] != 0)) return NFFT_ERR_ARG;
@@ -449,7 +512,13 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         int Q[kMaxD] = {1, 1, 1, 1};
         const int *req = opts ? opts->tile : nullptr;
         int trc;
-        if (D == 4) {
+        const int smode = opts ? opts->spread : NFFT_SPREAD_AUTO;
+        if (D == 3 && smode != NFFT_SPREAD_TILED &&
+            plan_sweep(*p, req, (size_t)dev_lds, cus_of(p->device), Q)) {
+            trc = NFFT_OK;
+        } else if (D == 3 && smode == NFFT_SPREAD_SWEEP) {
+            trc = NFFT_ERR_UNSUPPORTED;
+        } else if (D == 4) {
             trc = choose_tiles_4d(p->Nt, taps, dtype, req, (size_t)dev_lds, Q);
         } else {
             // sparse 3-D node sets (under 1/4 node per grid point, e.g. sigma = 2 with
@@ -604,6 +673,12 @@ int nfft_plan_info(nfft_plan_t p, int64_t *Ntilde, double *sigma_eff, int *tile)
 int nfft_plan_grid(nfft_plan_t p, void **grid) {
     if (!p || !grid) return NFFT_ERR_ARG;
     *grid = p->grid;
+    return NFFT_OK;
+}
+
+int nfft_plan_spread(nfft_plan_t p, int *scheme) {
+    if (!p || !scheme) return NFFT_ERR_ARG;
+    *scheme = p->sweep.on ? NFFT_SPREAD_SWEEP : NFFT_SPREAD_TILED;
     return NFFT_OK;
 }
 

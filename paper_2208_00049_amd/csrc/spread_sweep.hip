@@ -1,0 +1,315 @@
+// Three-dimensional spreading by column sweeps (paper, step 1 of Algorithm 2;
+// subsection "Block-Partitioned Adjoint Resampling").
+//
+// The oversampled grid is cut into columns of 16 x 16 points along axes 1 and
+// 2 that run through axis 0, and each column into segments of consecutive
+// tiles along axis 0.  One workgroup sweeps one segment tile by tile, in
+// increasing axis-0 order.  It keeps a ring of R = Q_0 + 2m - 1 padded planes
+// in LDS, each (16 + 2m - 1)^2 points: a node binned in tile t_0 adds its
+// stencil to planes o_0 .. o_0 + 2m - 1, all of which are in the ring, and after
+// the tile's nodes the tile's Q_0 planes receive nothing more from this segment.
+// Those planes go to the scratch once (axis-1/2 halo included) and their ring
+// slots are cleared for the next planes.  The axis-0 halo thus stays in LDS;
+// only the segment's last 2m - 1 planes (which belong to the next segment) go
+// to a small halo slot of their own.
+//
+// A merge then sums, for every grid point, the scratch planes of the columns
+// that cover it (its own column and, within 2m - 1 of its leading edges along
+// axes 1 and 2, the columns before it) and, within 2m - 1 planes of a segment
+// start, the halo slots of the segments before.  Every grid value has one
+// writer, in a fixed order of summation; no global atomics are used.
+//
+// Accumulation in LDS:
+//   complex64:  64-bit fixed point per component with a power-of-two scale of
+//               the segment (as in the tiled kernel): exact, order independent.
+//   complex128: FP64 LDS atomic additions (ds_add_f64), two per tap instead of
+//               the four 64-bit integer ones an exact 96-bit sum takes, and 16
+//               bytes per point instead of 32, so that the 16 x 16 columns fit.
+//               Sums are correct to FP64 rounding; their order, and so the last
+//               bits of the result, can differ between calls.
+#include "resample_impl.hpp"
+
+namespace nfft {
+
+template <typename T> struct SweepAcc;
+
+template <> struct SweepAcc<float> {
+    using W = unsigned long long;
+    static constexpr bool kFixed = true;
+    // a: the point's Re word; the Im word is `im` words further; |cr|, |ci| < 2^30
+    __device__ static inline void add(W *a, int im, float cr, float ci) {
+        atomicAdd(a, (W)(long long)(int)cr);
+        atomicAdd(a + im, (W)(long long)(int)ci);
+    }
+    __device__ static inline float get(const W *a, double inv) {
+        return (float)((double)(long long)*a * inv);
+    }
+};
+
+template <> struct SweepAcc<double> {
+    using W = double;
+    static constexpr bool kFixed = false;
+    __device__ static inline void add(W *a, int im, double cr, double ci) {
+        atomicAdd(a, cr);
+        atomicAdd(a + im, ci);
+    }
+    __device__ static inline double get(const W *a, double) { return *a; }
+};
+
+// Staged nodes of one chunk: ring slot and in-column offsets packed into one
+// word (slot | l1 << 8 | l2 << 16), the fractions and the value.
+template <typename T, int CH> struct SweepStage {
+    int pk[CH];
+    T fr[3][CH];
+    T vr[CH];
+    T vi[CH];
+};
+
+template <typename T> constexpr int sweep_chunk() { return sizeof(T) == 4 ? 1024 : 512; }
+template <typename T> constexpr int sweep_threads() { return 1024; }
+
+template <typename T, int M2, bool GW>
+__global__ void __launch_bounds__(sweep_threads<T>())
+    k_spread_sweep(cplx<T> *__restrict__ scr, Geom g, SweepGeom sg,
+                   const NodeRec<T, 3> *__restrict__ nodes, const int *__restrict__ perm,
+                   const int *__restrict__ key_start, const T *__restrict__ coef, int window,
+                   WinParams<T> wp, T wmax_prod, const cplx<T> *__restrict__ fhat,
+                   long long sstride, long long fstride) {
+    using C = cplx<T>;
+    using A = SweepAcc<T>;
+    using W = typename A::W;
+    constexpr int NT = sweep_threads<T>();
+    constexpr int CH = sweep_chunk<T>();
+    constexpr int P = kSweepQ + M2 - 1, PP = P * P;
+    constexpr int NPW = 64 / M2;
+    constexpr double kLimit = 1073741824.0;  // 2^30: bound of a scaled c64 contribution
+    scr += blockIdx.y * sstride;              // channel
+    fhat += blockIdx.y * fstride;
+    extern __shared__ unsigned char smem_raw[];
+    W *acc = reinterpret_cast<W *>(smem_raw);  // [R][Re, Im][PP]
+    __shared__ SweepStage<T, CH> st;
+    __shared__ int seg_off[kSweepMaxSegTiles + 1];  // node offsets of the segment's tiles
+    __shared__ int seg_beg[kSweepMaxSegTiles];      // first sorted node of each tile
+    __shared__ unsigned long long amax_bits;
+
+    const int seg = blockIdx.x;
+    const int col = seg / sg.nsc, kseg = seg - col * sg.nsc;
+    const int t1 = col / g.T[2], t2 = col - t1 * g.T[2];
+    const int tb = kseg * sg.L, nt = sg.L;  // segments are L tiles long (L divides T_0)
+    const int R = sg.R, Q0 = g.Q[0];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // node ranges of the segment's tiles, then a pass over its values for the
+    // fixed-point scale (and the detection of a non-finite value)
+    if (tid < nt) {
+        const int tile = ((tb + tid) * g.T[1] + t1) * g.T[2] + t2;
+        seg_beg[tid] = key_start[tile << 3];
+        seg_off[tid + 1] = key_start[(tile + 1) << 3] - key_start[tile << 3];
+    }
+    if (tid == 0) {
+        seg_off[0] = 0;
+        amax_bits = 0ull;
+    }
+    for (int i = tid; i < R * 2 * PP; i += NT) acc[i] = (W)0;
+    __syncthreads();
+    if (tid == 0)
+        for (int t = 0; t < nt; ++t) seg_off[t + 1] += seg_off[t];
+    __syncthreads();
+    const int total = seg_off[nt];
+    {
+        T mx = (T)0;
+        for (int j = tid; j < total; j += NT) {
+            int t = 0;
+            while (seg_off[t + 1] <= j) ++t;
+            const C v = fhat[perm[seg_beg[t] + j - seg_off[t]]];
+            mx = fmax(mx, scale_mag(v.x, v.y));
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if (lane == 0) atomicMax(&amax_bits, (unsigned long long)__double_as_longlong((double)mx));
+    }
+    __syncthreads();
+    const double amax_d = __longlong_as_double((long long)amax_bits);
+    const bool poisoned = isinf(amax_d);  // a non-finite value in the segment
+    T scale = (T)1;
+    if (A::kFixed && amax_d > 0.0 && !poisoned) {
+        int e;
+        (void)frexp(kLimit / (amax_d * (double)wmax_prod), &e);
+        scale = (T)ldexp(1.0, e - 1);
+    }
+    const double inv = 1.0 / (double)scale;
+
+    const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
+    LaneWindow<T, 3, M2> lw;
+    lw.load(coef, li, wp.m);
+    const T nan = (T)__builtin_nan("");
+
+    for (int t = 0; t < nt; ++t) {
+        const int t0 = tb + t;
+        const int nb = seg_beg[t], ne = nb + seg_off[t + 1] - seg_off[t];
+        for (int c0 = nb; c0 < (poisoned ? nb : ne); c0 += CH) {
+            const int n = min(CH, ne - c0);
+            {
+                // every load of the thread's node first, then the LDS writes
+                const int k = tid < n ? tid : n - 1;
+                const NodeRec<T, 3> rec = nodes[c0 + k];
+                const C v = fhat[perm[c0 + k]];
+                if (tid < n) {
+                    int r0 = rec.o[0] % R;
+                    st.pk[tid] = r0 | ((rec.o[1] - t1 * kSweepQ) << 8) | ((rec.o[2] - t2 * kSweepQ) << 16);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) st.fr[d][tid] = rec.fr[d];
+                    st.vr[tid] = v.x;
+                    st.vi[tid] = v.y;
+                }
+            }
+            __syncthreads();
+            for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
+                const int k = base + grp;
+                const bool valid = grp < NPW && k < n;
+                const int ks = valid ? k : 0;
+                const int pk = st.pk[ks];
+                const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
+                T fr[3], w[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fr[d] = st.fr[d][ks];
+                node_weights<GW, T, 3, M2>(w, lw, fr, (long long)(c0 + ks), li, window, wp);
+                const T ws = valid ? w[2] * scale : (T)0;
+                const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
+                T w0[M2], w1[M2];
+                BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                BcastAll<M2, 0, T>::run(w1, w[1], gbase);
+                W *cell = acc + (l1 * P + l2 + li);
+#pragma unroll
+                for (int a = 0; a < M2; ++a) {
+                    int r = r0 + a;
+                    if (r >= R) r -= R;
+                    W *pl = cell + r * (2 * PP);
+                    const T ar = w0[a] * pr, ai = w0[a] * pi;
+#pragma unroll
+                    for (int b = 0; b < M2; ++b) A::add(pl + b * P, PP, w1[b] * ar, w1[b] * ai);
+                }
+            }
+            __syncthreads();
+        }
+        // the tile's Q_0 planes are complete: write them out, clear their slots
+        const int p0 = t0 * Q0;
+        const int rb = p0 % R;
+        for (int idx = tid; idx < Q0 * PP; idx += NT) {
+            const int kk = idx / PP, cell = idx - kk * PP;
+            int r = rb + kk;
+            if (r >= R) r -= R;
+            W *a = acc + r * (2 * PP) + cell;
+            const C v = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv), A::get(a + PP, inv));
+            a[0] = (W)0;
+            a[PP] = (W)0;
+            scr[((size_t)(p0 + kk) * sg.ncols + col) * PP + cell] = v;
+        }
+        __syncthreads();
+    }
+    // the last 2m - 1 planes (the next segment's first ones) go to the halo slot
+    const int ph = (tb + nt) * Q0;
+    const int rh = ph % R;
+    C *halo = scr + sg.main_cells + (size_t)seg * (M2 - 1) * PP;
+    for (int idx = tid; idx < (M2 - 1) * PP; idx += NT) {
+        const int kk = idx / PP, cell = idx - kk * PP;
+        int r = rh + kk;
+        if (r >= R) r -= R;
+        const W *a = acc + r * (2 * PP) + cell;
+        halo[idx] = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv), A::get(a + PP, inv));
+    }
+}
+
+// Merge of the column sweeps: one workgroup per (plane, column), one thread per
+// grid point of the column's 16 x 16 cross-section.
+template <typename T, int M2>
+__global__ void __launch_bounds__(256)
+    k_sweep_merge(cplx<T> *__restrict__ grid, Geom g, SweepGeom sg, const cplx<T> *__restrict__ scr,
+                  long long gstride, long long sstride) {
+    using C = cplx<T>;
+    constexpr int P = kSweepQ + M2 - 1, PP = P * P;
+    grid += blockIdx.y * gstride;  // channel
+    scr += blockIdx.y * sstride;
+    // neighbouring columns on one XCD: they read each other's halo rows
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int p = b / sg.ncols, col = b - p * sg.ncols;
+    const int t1 = col / g.T[2], t2 = col - t1 * g.T[2];
+    const int a1 = threadIdx.x >> 4, a2 = threadIdx.x & 15;
+    const int t0 = p / g.Q[0];
+    const int kseg = t0 / sg.L;
+    const int j = p - kseg * sg.L * g.Q[0];  // plane within its segment
+    const int kpred = kseg == 0 ? sg.nsc - 1 : kseg - 1;
+    const C *halo = scr + sg.main_cells;
+    T sr = (T)0, si = (T)0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int e1 = e >> 1, e2 = e & 1;  // the source column precedes along axis 1 / 2
+        if ((e1 && a1 >= M2 - 1) || (e2 && a2 >= M2 - 1)) continue;
+        int c1 = t1 - e1, c2 = t2 - e2;
+        if (c1 < 0) c1 += g.T[1];
+        if (c2 < 0) c2 += g.T[2];
+        const int cc = c1 * g.T[2] + c2;
+        const int off = (a1 + (e1 ? kSweepQ : 0)) * P + a2 + (e2 ? kSweepQ : 0);
+        const C v = scr[((size_t)p * sg.ncols + cc) * PP + off];
+        sr += v.x;
+        si += v.y;
+        if (j < M2 - 1) {
+            const C h = halo[((size_t)(cc * sg.nsc + kpred) * (M2 - 1) + j) * PP + off];
+            sr += h.x;
+            si += h.y;
+        }
+    }
+    const long long gi = ((long long)p * g.Nt[1] + t1 * kSweepQ + a1) * g.Nt[2] + t2 * kSweepQ + a2;
+    grid[gi] = cmake<C>(sr, si);
+}
+
+template <typename T, int M2>
+hipError_t run_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                            int K, void *pad) {
+    const long long sstride = (long long)sweep_scratch_cells(p);
+    const SweepGeom &sg = p.sweep;
+    if (p.M > 0) {
+        const size_t shm = sweep_ring_bytes(p);
+        const bool gw = p.window != NFFT_WINDOW_POLY;
+        auto kern = gw ? k_spread_sweep<T, M2, true> : k_spread_sweep<T, M2, false>;
+        hipError_t e = allow_lds(kern, shm, sizeof(SweepStage<T, sweep_chunk<T>()>) + 1024);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(sg.ncols * sg.nsc, K), dim3(sweep_threads<T>()), shm, s,
+                           (cplx<T> *)pad, p.geom, sg, (const NodeRec<T, 3> *)p.nodes, p.perm,
+                           p.key_start, (const T *)p.coef, p.window, win_params<T>(p),
+                           (T)window_bound(3), (const cplx<T> *)fhat, sstride, (long long)p.M);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    } else {
+        return launch_fill_zero_complex(grid, (int64_t)K * p.G, sizeof(T) == 8, s);
+    }
+    hipLaunchKernelGGL((k_sweep_merge<T, M2>), dim3(p.geom.Nt[0] * sg.ncols, K), dim3(256), 0, s,
+                       (cplx<T> *)grid, p.geom, sg, (const cplx<T> *)pad, (long long)p.G, sstride);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sweep_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s, int K,
+                          void *pad) {
+    switch (p.geom.taps) {
+        case 2: return run_spread_sweep<T, 2>(p, fhat, grid, s, K, pad);
+        case 4: return run_spread_sweep<T, 4>(p, fhat, grid, s, K, pad);
+        case 6: return run_spread_sweep<T, 6>(p, fhat, grid, s, K, pad);
+        case 8: return run_spread_sweep<T, 8>(p, fhat, grid, s, K, pad);
+        case 10: return run_spread_sweep<T, 10>(p, fhat, grid, s, K, pad);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                               int K, void *pad) {
+    return p.dtype == NFFT_C64 ? sweep_t<float>(p, fhat, grid, s, K, pad)
+                               : sweep_t<double>(p, fhat, grid, s, K, pad);
+}
+
+size_t sweep_static_lds(int dtype) {
+    return dtype == NFFT_C64 ? sizeof(SweepStage<float, sweep_chunk<float>()>) + 1024
+                             : sizeof(SweepStage<double, sweep_chunk<double>()>) + 1024;
+}
+
+}  // namespace nfft

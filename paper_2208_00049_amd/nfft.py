@@ -30,11 +30,13 @@ class Plan:
     work item; ``tune``: if > 0 (and no tile is given), the library's autotuner
     picks the tiles, timing each candidate ``tune`` times (``tuned_ms`` then
     holds the chosen plan's forward + adjoint milliseconds); ``wide``: the (2m+2)-point
-    stencil with the untruncated window.
+    stencil with the untruncated window; ``spread``: the 3-D spreading scheme, "auto"
+    (column sweeps where available), "tiled" (padded tiles, exact fixed-point sums in
+    both types) or "sweep".
     """
 
     def __init__(self, x, N, m=4, sigma=2.0, tile=None, window="poly", max_block_nodes=0, tune=0,
-                 wide=False):
+                 wide=False, spread="auto"):
         if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
             raise TypeError("x must be a CUDA (HIP) tensor")
         N = tuple(int(v) for v in N)
@@ -64,6 +66,7 @@ class Plan:
         opts.window = _lib.WINDOWS[window]
         opts.max_block_nodes = int(max_block_nodes)
         opts.wide = int(bool(wide))
+        opts.spread = _lib.SPREAD[spread]
         Narr = (ctypes.c_int64 * self.D)(*N)
         handle = ctypes.c_void_p()
         self.tuned_ms = None
@@ -90,7 +93,10 @@ class Plan:
         se = ctypes.c_double()
         tl = (ctypes.c_int * self.D)()
         _lib.check(self._lib.nfft_plan_info(self._h, nt, ctypes.byref(se), tl), "nfft_plan_info")
-        return {"Ntilde": tuple(nt), "sigma_eff": se.value, "tile": tuple(tl)}
+        sp = ctypes.c_int()
+        _lib.check(self._lib.nfft_plan_spread(self._h, ctypes.byref(sp)), "nfft_plan_spread")
+        return {"Ntilde": tuple(nt), "sigma_eff": se.value, "tile": tuple(tl),
+                "spread": {v: k for k, v in _lib.SPREAD.items()}[sp.value]}
 
     @property
     def Ntilde(self):

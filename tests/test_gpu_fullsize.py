@@ -54,24 +54,27 @@ def test_2d_512(device, nodes, dt, m):
         assert max(ef, ea) <= TARGET[(dt, m, sigma)]
 
 
-# Default tiles of the 3-D 128^3 workload (M = 2^21): sparse node sets (under a quarter of a
-# node per grid point, sigma = 2) take tiles whose padded spreading tile fills the device's
-# LDS; at sigma = 1.25 the 64 KiB footprint is preferred (complex128 needs the whole LDS).
-TILE_3D = {(2.0, "c64"): (8, 16, 16), (1.25, "c64"): (8, 8, 8), (2.0, "c128"): (8, 8, 8),
-           (1.25, "c128"): (8, 10, 10)}
-SIGMA_DT_3D = [(2.0, "c64"), (1.25, "c64"), (2.0, "c128"), (1.25, "c128")]
+# Default tiles of the 3-D 128^3 workload (M = 2^21): the column sweeps' (8, 16, 16) for both
+# sigma (oversampled 256^3 and 160^3) and both types; the padded-tile scheme (spread="tiled",
+# exact fixed-point sums in complex128 too) takes 8^3 tiles for complex128 at sigma = 2.
+TILE_3D = {(2.0, "c64", "auto"): (8, 16, 16), (1.25, "c64", "auto"): (8, 16, 16),
+           (2.0, "c128", "auto"): (8, 16, 16), (1.25, "c128", "auto"): (8, 16, 16),
+           (2.0, "c128", "tiled"): (8, 8, 8)}
+SIGMA_DT_3D = [(2.0, "c64", "auto"), (1.25, "c64", "auto"), (2.0, "c128", "auto"),
+               (1.25, "c128", "auto"), (2.0, "c128", "tiled")]
 
 
-@pytest.mark.parametrize("sigma,dt", SIGMA_DT_3D)
-def test_3d_128(device, sigma, dt):
+@pytest.mark.parametrize("sigma,dt,spread", SIGMA_DT_3D)
+def test_3d_128(device, sigma, dt, spread):
     N, m = (128, 128, 128), 4
     x = wl.workload_nodes("3d_n128_m2097152")
     M = x.shape[0]
     f = wl.cn01(N, config=2, stream=1)
     fh = wl.cn01((M,), config=2, stream=2)
-    p, xs = make_plan(device, x, N, m, sigma, dt)
+    p, xs = make_plan(device, x, N, m, sigma, dt, spread=spread)
     print("case 3d", sigma, dt, p.info(), flush=True)
-    assert p.info()["tile"] == TILE_3D[(sigma, dt)]
+    assert p.info()["tile"] == TILE_3D[(sigma, dt, spread)]
+    assert p.info()["spread"] == ("sweep" if spread == "auto" else spread)
     fg = p.forward(to_dev(f, dt, device)).cpu().numpy()
     yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
     tol = e2e_tol(N, sigma, m, dt)
@@ -101,8 +104,8 @@ def _nodes_reaching_box(xs, Nt, m, lo, shape):
     return sel
 
 
-@pytest.mark.parametrize("sigma,dt", SIGMA_DT_3D)
-def test_3d_128_spread_grid_on_boxes(device, sigma, dt):
+@pytest.mark.parametrize("sigma,dt,spread", SIGMA_DT_3D)
+def test_3d_128_spread_grid_on_boxes(device, sigma, dt, spread):
     """The full-size adjoint resampling (spreading + halo merge over all 2^21 nodes, in the
     default tiles bench.py times) element by element on boxes of grid points -- at the
     origin, across the cyclic end of every axis and at a seeded ragged position -- against
@@ -111,10 +114,10 @@ def test_3d_128_spread_grid_on_boxes(device, sigma, dt):
     x = wl.workload_nodes("3d_n128_m2097152")
     M = x.shape[0]
     fh = wl.cn01((M,), config=2, stream=2)
-    p, xs = make_plan(device, x, N, m, sigma, dt)
+    p, xs = make_plan(device, x, N, m, sigma, dt, spread=spread)
     Nt = p.Ntilde
     print("spread boxes 3d", sigma, dt, p.info(), flush=True)
-    assert p.info()["tile"] == TILE_3D[(sigma, dt)]
+    assert p.info()["tile"] == TILE_3D[(sigma, dt, spread)]
     grid = p.resample_adjoint(to_dev(fh, dt, device)).cpu().numpy() * p.window_scale
     g = np.random.default_rng(17)
     boxes = [((0, 0, 0), (16, 16, 16)), (tuple(n - 12 for n in Nt), (20, 20, 20)),
@@ -127,8 +130,8 @@ def test_3d_128_spread_grid_on_boxes(device, sigma, dt):
         assert rel2(got, ref) < tol, (lo, shape, int(sel.sum()), rel2(got, ref), tol)
 
 
-@pytest.mark.parametrize("sigma,dt", SIGMA_DT_3D)
-def test_3d_128_adjoint_elementwise_on_subset(device, sigma, dt):
+@pytest.mark.parametrize("sigma,dt,spread", SIGMA_DT_3D)
+def test_3d_128_adjoint_elementwise_on_subset(device, sigma, dt, spread):
     """The whole 3-D adjoint (spreading, merge, pruned adjoint FFT passes, crop and
     correction) element by element against the oracle NFFT on a seeded 2^18-node subset of
     the 128^3 workload, in the tiles the full workload uses."""
@@ -136,7 +139,8 @@ def test_3d_128_adjoint_elementwise_on_subset(device, sigma, dt):
     x = wl.workload_nodes("3d_n128_m2097152")
     js = np.sort(np.random.default_rng(19).choice(x.shape[0], 1 << 18, replace=False))
     fh = wl.cn01((x.shape[0],), config=2, stream=2)[js]
-    p, xs = make_plan(device, x[js], N, m, sigma, dt, tile=TILE_3D[(sigma, dt)])
+    p, xs = make_plan(device, x[js], N, m, sigma, dt, tile=TILE_3D[(sigma, dt, spread)],
+                      spread=spread)
     print("adjoint subset 3d", sigma, dt, p.info(), flush=True)
     yg = p.adjoint(to_dev(fh, dt, device)).cpu().numpy()
     yo = na.adjoint(xs, fh, N, m, sigma)
