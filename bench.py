@@ -5,13 +5,15 @@ oversampled FFT, interpolation; spreading, adjoint FFT, resampling correction)
 over the workload's synthetic node set, with inputs resident in HBM.  The
 metric is nonuniform points per second for the pair, M / (t_fwd + t_adj).
 
-Default workload: 2-D, N = 512 x 512 complex64 coefficients ~ CN(0, 1),
-M = 262144 nodes iid uniform in [-1/2, 1/2)^2, Kaiser-Bessel window m = 4,
-sigma = 2 (the paper's 2-D benchmark shape: J = |I_N| random nodes).
+Default workload: 3-D, N = 128^3 complex128 coefficients ~ CN(0, 1),
+M = 2097152 nodes iid uniform in [-1/2, 1/2)^3, Kaiser-Bessel window m = 4,
+sigma = 2, in FP64 (the paper's precision) -- the largest plain configuration.
 
 Printed: one JSON line with the throughput, a roofline entry for the
 dominant kernel (per-kernel HIP-event durations measured in this run), the
-FP32-vs-FP64 accuracy on the same GPU and a timed CPU-oracle baseline.
+errors of the GPU results against the FP64 NDFT on a sample of outputs, the
+complex64 (FP32) transform of the same nodes beside it (time, error against
+FP64 and against the NDFT), a timed CPU-oracle baseline and a plain CPU NFFT.
 """
 import argparse
 import hashlib
@@ -81,6 +83,7 @@ def stored_traffic(workload, dtype, kernel_names):
 # profile summary file tag per (workload, dtype)
 PROFILE_TAG = {("2d_n512_m262144_uniform", "c64"): "n512_m262144_c64_uniform",
                ("3d_n128_m2097152_uniform", "c64"): "n128_m2097152_c64_uniform",
+               ("3d_n128_m2097152_uniform", "c128"): "n128_m2097152_c128_uniform",
                ("4d_n16_m65536_uniform", "c64"): "n16_m65536_c64_uniform"}
 
 # stage name -> the kernels one back-to-back launch of the stage runs (in 3-D spreading
@@ -88,8 +91,11 @@ PROFILE_TAG = {("2d_n512_m262144_uniform", "c64"): "n512_m262144_c64_uniform",
 STAGE_KERNEL = {
     (2, "c64"): {"spread": ["nfft::k_spread<float, 2, 8, false, 256>"],
                  "interp": ["nfft::k_interp<float, 2, 8, false, false, 256>"]},
-    (3, "c64"): {"spread": ["nfft::k_spread<float, 3, 8, false, 512>", "nfft::k_spread_merge<float, 3>"],
+    (3, "c64"): {"spread": ["nfft::k_spread_sweep<float, 8, false>", "nfft::k_sweep_merge<float, 8>"],
                  "interp": ["nfft::k_interp<float, 3, 8, false, false, 512>"]},
+    (3, "c128"): {"spread": ["nfft::k_spread_sweep<double, 8, false>",
+                             "nfft::k_sweep_merge<double, 8>"],
+                  "interp": ["nfft::k_interp<double, 3, 8, false, false, 512>"]},
     (4, "c64"): {"spread": ["nfft::k_spread_owner<float, 4, 8>"],
                  "interp": ["nfft::k_interp_node<float, 4, 8>"]},
 }
@@ -100,8 +106,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="2d_n512_m262144_uniform", choices=sorted(WORKLOADS))
-    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--workload", default="3d_n128_m2097152_uniform", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="c128", choices=["c64", "c128"])
     ap.add_argument("--m", type=int, default=4)
     ap.add_argument("--sigma", type=float, default=2.0)
     ap.add_argument("--window", default="poly", choices=["poly", "direct", "tensor", "linear", "full"],
@@ -191,7 +197,9 @@ def algorithmic_bytes(w, Nt, dtype):
 
 
 def cpu_baseline(x, f, fh, N, seconds):
-    """Time the FP64 NDFT oracle on a bounded sample of the same workload (host cores)."""
+    """Time the FP64 NDFT oracle on a bounded sample of the same workload (host cores).
+    Returns the baseline record and the sample: node indices with their NDFT values
+    (forward) and coefficient indices with theirs (adjoint)."""
     from oracle import ndft
     M = x.shape[0]
     nprod = int(np.prod(N))
@@ -206,50 +214,81 @@ def cpu_baseline(x, f, fh, N, seconds):
     per_node, per_coef = (t1 - t0) / sf, (t2 - t1) / sa
     sf = int(min(M, max(sf, 0.5 * seconds / per_node)))
     sa = int(min(nprod, max(sa, 0.5 * seconds / per_coef)))
+    js = np.sort(g.choice(M, sf, replace=False))
+    ks = np.sort(g.choice(nprod, sa, replace=False))
     t0 = time.perf_counter()
-    ndft.ndft_forward(x[:sf], f)
+    fe = ndft.ndft_forward(x[js], f)
     t1 = time.perf_counter()
-    ndft.ndft_adjoint(x, fh, N, idx=g.choice(nprod, sa, replace=False))
+    ye = ndft.ndft_adjoint(x, fh, N, idx=ks)
     t2 = time.perf_counter()
     t_fwd = (t1 - t0) * M / sf
     t_adj = (t2 - t1) * nprod / sa
-    return {"value": M / (t_fwd + t_adj), "unit": "pts/s", "cores": ndft.threads(),
-            "kind": "oracle", "host": host_cpu(),
-            "sample": "FP64 direct NDFT: forward at %d of %d nodes (%.2f s), adjoint at %d of %d "
-                      "coefficients (%.2f s), scaled to the full transform pair"
-                      % (sf, M, t1 - t0, sa, nprod, t2 - t1)}
+    rec = {"value": M / (t_fwd + t_adj), "unit": "pts/s", "cores": ndft.threads(),
+           "kind": "oracle", "host": host_cpu(),
+           "sample": "FP64 direct NDFT: forward at %d of %d nodes (%.2f s), adjoint at %d of %d "
+                     "coefficients (%.2f s), scaled to the full transform pair"
+                     % (sf, M, t1 - t0, sa, nprod, t2 - t1)}
+    return rec, (js, fe, ks, ye)
 
 
-def cpu_nfft(x, f, fh, N, m, sigma, seconds):
-    """Time the plain FP64 NFFT of the oracle (numpy, Algorithms 1 and 2, one host thread)
-    on the same workload.  When the full node set would take too long, the forward and the
-    adjoint are each timed at two node-sample sizes and extrapolated linearly in M (the
-    FFT part is the intercept)."""
-    from oracle import nfft_alg as na
+def ndft_sample(x, f, fh, N, nf, na_, seed):
+    """FP64 NDFT at nf seeded nodes and na_ seeded coefficient indices (no timing)."""
+    from oracle import ndft
+    g = np.random.default_rng(seed)
+    js = np.sort(g.choice(x.shape[0], min(nf, x.shape[0]), replace=False))
+    ks = np.sort(g.choice(int(np.prod(N)), min(na_, int(np.prod(N))), replace=False))
+    return js, ndft.ndft_forward(x[js], f), ks, ndft.ndft_adjoint(x, fh, N, idx=ks)
+
+
+def errors_vs_ndft(fout, yout, sample):
+    """Relative l2 and l-infinity (the paper's measure) errors of the GPU outputs against
+    the NDFT on the sampled outputs."""
+    js, fe, ks, ye = sample
+    fg = fout.cpu().numpy().astype(np.complex128)[js]
+    yg = yout.cpu().numpy().astype(np.complex128).reshape(-1)[ks]
+    r2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    ri = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    return {"fwd_rel_l2": r2(fg, fe), "fwd_rel_linf": ri(fg, fe), "adj_rel_l2": r2(yg, ye),
+            "adj_rel_linf": ri(yg, ye),
+            "sample": "%d nodes (forward), %d coefficients (adjoint)" % (len(js), len(ks))}
+
+
+def cpu_nfft(x, f, fh, N, m, sigma, sample=None):
+    """Time a plain CPU NFFT on all host cores (baseline/: C++/OpenMP resampling with
+    precomputed per-node window values, scipy.fft with one worker per core) on the full
+    workload, in FP64 and in FP32, plan creation excluded (as for the GPU); the FP64
+    results' error against the NDFT sample is reported too."""
+    from baseline.cpu_nfft import CpuNfft, threads
     M = x.shape[0]
-
-    def pair(ms):
+    out = {"unit": "pts/s", "cores": threads(), "kind": "plain CPU NFFT (C++/OpenMP + scipy.fft)",
+           "host": host_cpu(), "sample": "full workload, best of 2 forward + adjoint pairs"}
+    for dt in ("c128", "c64"):
+        xs = x if dt == "c128" else x.astype(np.float32).astype(np.float64)
         t0 = time.perf_counter()
-        na.forward(x[:ms], f, m, sigma)
-        t1 = time.perf_counter()
-        na.adjoint(x[:ms], fh[:ms], N, m, sigma)
-        t2 = time.perf_counter()
-        return t1 - t0, t2 - t1
-    s1 = min(M, 4096)
-    a1 = pair(s1)
-    per_node = max(sum(a1), 1e-9) / s1
-    if M == s1 or per_node * M < seconds:
-        tf, ta = pair(M) if M > s1 else a1
-        sample = "full workload, %d nodes" % M
-    else:
-        s2 = int(min(M, max(2 * s1, 0.5 * seconds / per_node)))
-        a2 = pair(s2)
-        slope = [(b - a) / (s2 - s1) for a, b in zip(a1, a2)]
-        tf, ta = [b + k * (M - s2) for b, k in zip(a2, slope)]
-        sample = ("timed at %d and %d of %d nodes, extrapolated linearly in the node count"
-                  % (s1, s2, M))
-    return {"value": M / (tf + ta), "unit": "pts/s", "cores": 1, "kind": "oracle NFFT (numpy)",
-            "fwd_s": round(tf, 3), "adj_s": round(ta, 3), "sample": sample}
+        c = CpuNfft(xs, N, m, sigma, dt)
+        plan_s = time.perf_counter() - t0
+        best = None
+        for _ in range(2):
+            t0 = time.perf_counter()
+            fo = c.forward(f)
+            t1 = time.perf_counter()
+            yo = c.adjoint(fh)
+            t2 = time.perf_counter()
+            if best is None or t2 - t0 < best[0] + best[1]:
+                best = (t1 - t0, t2 - t1)
+        rec = {"value": round(M / sum(best), 1), "fwd_s": round(best[0], 4),
+               "adj_s": round(best[1], 4), "plan_s": round(plan_s, 3)}
+        if sample is not None and dt == "c128":
+            js, fe, ks, ye = sample
+            r2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            rec["fwd_rel_l2_vs_ndft"] = r2(fo[js].astype(np.complex128), fe)
+            rec["adj_rel_l2_vs_ndft"] = r2(yo.reshape(-1)[ks].astype(np.complex128), ye)
+        c.close()
+        if dt == "c128":
+            out.update(rec)
+        else:
+            out["fp32"] = rec
+    return out
 
 
 def rocfft_reference(Nt, cdt, reps=20):
@@ -473,6 +512,56 @@ def bench_batch(args, w):
     }
 
 
+def other_precision(args, w, plan, xt, ft, fht, fout, yout, sample):
+    """The transform pair in the other precision on the same GPU: complex64 (FP32 bulk
+    arithmetic) beside a complex128 headline, or complex128 beside a complex64 one.  Both
+    precisions are compared on the FP32-rounded nodes and inputs, so that they differ only
+    by their arithmetic; the other precision's pair time and its error against the NDFT
+    (on the FP32-rounded nodes) are reported too."""
+    import torch
+    from paper_2208_00049_amd import Plan
+    kw = dict(m=args.m, sigma=args.sigma, window=args.window, wide=args.wide)
+    x32 = xt.float()
+    f32, fh32 = ft.to(torch.complex64), fht.to(torch.complex64)
+    f64, fh64 = f32.to(torch.complex128), fh32.to(torch.complex128)
+    if args.dtype == "c64":
+        p32, o32f, o32y = plan, fout, yout
+        p64 = Plan(x32.double(), w["N"], **kw)
+        other, fo, yo, fi, fhi = p64, torch.empty_like(fout, dtype=torch.complex128), \
+            torch.empty_like(yout, dtype=torch.complex128), f64, fh64
+    else:
+        p32 = Plan(x32, w["N"], **kw)
+        o32f, o32y = p32.forward(f32), p32.adjoint(fh32)
+        p64 = Plan(x32.double(), w["N"], **kw)
+        other, fo, yo, fi, fhi = p32, torch.empty_like(o32f), torch.empty_like(o32y), f32, fh32
+    r64f, r64y = p64.forward(f64), p64.adjoint(fh64)
+    rel = lambda a, b: (torch.linalg.norm(a.to(torch.complex128) - b) / torch.linalg.norm(b)).item()
+    out = {"dtype": "f32" if args.dtype == "c128" else "f64",
+           "fwd_rel_l2_fp32_vs_fp64": rel(o32f, r64f), "adj_rel_l2_fp32_vs_fp64": rel(o32y, r64y)}
+
+    def pair():
+        other.forward(fi, out=fo)
+        other.adjoint(fhi, out=yo)
+    for _ in range(3):
+        pair()
+    reps = max(5, min(100, int(1000.0 / max(1e-3, call_stats([pair], 3)[0]["mean"]))))
+    st = call_stats([pair], reps)[0]
+    out["pair_us"] = {k: round(v * 1e3, 3) for k, v in st.items()}
+    out["pts_s"] = round(w["M"] / (st["mean"] * 1e-3), 1)
+    if sample is not None:
+        if args.dtype == "c64":
+            out["error_vs_ndft"] = errors_vs_ndft(fo, yo, sample)
+        else:
+            xs32 = x32.double().cpu().numpy()
+            s32 = ndft_sample(xs32, f64.cpu().numpy(), fh64.cpu().numpy(), w["N"], 1024, 16, 4321)
+            out["error_vs_ndft"] = errors_vs_ndft(o32f, o32y, s32)
+    if p64 is not plan:
+        p64.close()
+    if p32 is not plan:
+        p32.close()
+    return out
+
+
 def main():
     args = parse()
     if args.copy_bytes:
@@ -589,21 +678,26 @@ def main():
                 "traffic": round(traffic) if traffic is not None else None,
                 "algorithmic_bytes": algo[dominant], "launch_ms": round(dom_ms, 5)}
 
-    # spreading's own roof: its 64-bit LDS atomics (one per component and tap for c64,
-    # two for c128), against the ds_add_u64 rate the library's calibration kernel
-    # measures in this run for the access shape of one spreading instruction (eight
-    # rows of eight consecutive words at random starts)
+    # spreading's own roof: its LDS atomics per second against the rate the library's
+    # calibration kernel measures in this run for the access shape of one spreading
+    # instruction (eight rows of eight consecutive words at random starts): 64-bit integer
+    # additions (fixed point: one per component and tap in complex64, two in complex128 with
+    # padded tiles), or FP64 additions (complex128 column sweeps: one per component and tap)
     from paper_2208_00049_amd import calibrate_lds
     taps = 2 * args.m + (2 if args.wide else 0)
-    atomics = w["M"] * taps ** w["D"] * (2 if args.dtype == "c64" else 4)
-    lds_peak = calibrate_lds("ds_add_u64", 2)
+    sweep_f64 = info["spread"] == "sweep" and args.dtype == "c128"
+    per_tap = 4 if (args.dtype == "c128" and not sweep_f64) else 2
+    atomics = w["M"] * taps ** w["D"] * per_tap
+    lds_op = "ds_add_f64" if sweep_f64 else "ds_add_u64"
+    lds_peak = calibrate_lds(lds_op, 2)
     spread_ms = b2b.get("spread", avg_ms.get("spread"))
     lds_roof = None
     if spread_ms:
         rate = atomics / (spread_ms * 1e-3)
         lds_roof = {"kernel": "spread", "bound": "lds_atomic", "atomic_lane_ops": atomics,
-                    "peak_source": "ds_add_u64, rows of 8 consecutive words, measured in this run "
-                                   "(python bench.py --lds-calibrate)",
+                    "op": lds_op,
+                    "peak_source": "%s, rows of 8 consecutive words, measured in this run "
+                                   "(python bench.py --lds-calibrate)" % lds_op,
                     "achieved": round(rate / 1e12, 4), "peak": round(lds_peak / 1e12, 4),
                     "unit": "T lane-ops/s", "frac": round(rate / lds_peak, 4)}
     fwd_fft_ms = sum(v for k, v in avg_ms.items() if k.startswith("fwd_"))
@@ -623,6 +717,7 @@ def main():
                    "sigma": args.sigma, "nodes": w["nodes"],
                    "complex": "complex64" if args.dtype == "c64" else "complex128",
                    "Ntilde": list(info["Ntilde"]), "tile": list(info["tile"]),
+                   "spread": info["spread"],
                    "window": args.window, "stencil": "2m+2" if args.wide else "2m"},
         "plan_ms": round(plan_ms, 2),
         "plan_first_ms": round(plan_first_ms, 2),
@@ -635,23 +730,20 @@ def main():
     }
 
     if not args.profile_only:
-        # FP32 result against FP64 on the same GPU (same FP32-rounded nodes and inputs)
-        if args.dtype == "c64":
-            p64 = Plan(xt.double(), w["N"], m=args.m, sigma=args.sigma, window=args.window,
-                       wide=args.wide)
-            f64 = p64.forward(ft.to(torch.complex128))
-            y64 = p64.adjoint(fht.to(torch.complex128))
-            fwd_err = (torch.linalg.norm(fout.to(torch.complex128) - f64) / torch.linalg.norm(f64)).item()
-            adj_err = (torch.linalg.norm(yout.to(torch.complex128) - y64) / torch.linalg.norm(y64)).item()
-            result["accuracy"] = {"fwd_rel_l2_fp32_vs_fp64": fwd_err, "adj_rel_l2_fp32_vs_fp64": adj_err}
-            p64.close()
+        xs = xt.double().cpu().numpy()
+        fc = ft.cpu().numpy().astype(np.complex128)
+        fhc = fht.cpu().numpy().astype(np.complex128)
+        sample = None
         if not args.no_cpu:
-            xs = xt.double().cpu().numpy()
-            fc = ft.cpu().numpy().astype(np.complex128)
-            fhc = fht.cpu().numpy().astype(np.complex128)
-            result["cpu_baseline"] = cpu_baseline(xs, fc, fhc, w["N"], args.cpu_seconds)
+            result["cpu_baseline"], sample = cpu_baseline(xs, fc, fhc, w["N"], args.cpu_seconds)
+            result["error_vs_ndft"] = errors_vs_ndft(fout, yout, sample)
+        result["other_precision"] = other_precision(args, w, plan, xt, ft, fht, fout, yout,
+                                                    sample)
+        if not args.no_cpu:
+            # the CPU NFFT's error is measured against the NDFT sample at the same nodes
+            same = args.dtype == "c128"
             result["cpu_nfft"] = cpu_nfft(xs, fc, fhc, w["N"], args.m, args.sigma,
-                                          args.cpu_seconds)
+                                          sample if same else None)
     plan.close()
     print(json.dumps(result), flush=True)
 

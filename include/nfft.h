@@ -340,7 +340,7 @@ int nfft_plan_bench_stage(nfft_plan_t p, int stage, int reps, const void *in, vo
  * resampling, subsection "Block-Partitioned Adjoint Resampling", accumulates
  * into a block-local grid, which here lives in LDS).  Launches 8 workgroups
  * of 256 threads per compute unit, each thread performing 2048 operations of
- * kind `op` on a 64 KiB LDS buffer, `reps` times between two HIP events on
+ * kind `op` on a 16 KiB LDS buffer, `reps` times between two HIP events on
  * `stream` (after one untimed launch), and stores the lane operations per
  * second in *lane_ops_per_s.
  *   op:      NFFT_LDS_ADD_U32 / _ADD_U64 / _ADD_F32 / _ADD_F64 (atomic add,

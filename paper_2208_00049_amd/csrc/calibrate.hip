@@ -3,7 +3,8 @@
 // LDS atomics are reported.
 //
 // Each thread of a 256-thread workgroup performs `iters` operations on a
-// 64 KiB LDS buffer at addresses given by the pattern; the rate is the lane
+// 16 KiB LDS buffer at addresses given by the pattern (small enough that eight
+// workgroups, 32 wavefronts, are resident per compute unit); the rate is the lane
 // operations of all workgroups over the launch time.  Address arithmetic is a
 // few VALU instructions per operation, far below the VALU issue rate, so the
 // LDS unit bounds the loop.
@@ -15,7 +16,7 @@ namespace nfft {
 namespace {
 
 constexpr int kCalThreads = 256;
-constexpr int kCalBytes = 65536;
+constexpr int kCalBytes = 16384;
 
 __device__ inline unsigned hash32(unsigned v) {
     v ^= v >> 16;
