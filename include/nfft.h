@@ -304,10 +304,12 @@ int nfft_plan_spread(nfft_plan_t p, int *scheme);
  *   1 forward: FFT along axis 1 (3-D; 4-D: axes 2 and 1, the last one
  *              recorded is kept)            2 forward: FFT along axis 0
  *   3 forward: interpolation
- *   4 adjoint: spreading into the work items' padded tiles (1-D, 3-D: and
- *              the halo merge into the grid; 4-D: straight into the grid)
- *   5 adjoint: FFT along axis 0 (2-D: reads the padded tiles and performs
- *              the halo merge on the way)
+ *   4 adjoint: spreading into the work items' padded tiles (1-D, 3-D padded
+ *              tiles: and the halo merge into the grid; 3-D column sweeps: the
+ *              fhat gather and the sweeps into their scratch; 4-D: straight into
+ *              the grid)
+ *   5 adjoint: FFT along axis 0 (2-D and 3-D column sweeps: reads the spreading
+ *              scratch and performs the merge on the way)
  *   6 adjoint: FFT along axis 1 (3-D; 4-D: axes 1 and 2, the last kept)
  *   7 adjoint: FFT along the last axis + crop + resampling correction
  * Stages a plan does not run report 0.  ms must hold NFFT_NUM_STAGES values.
@@ -325,9 +327,10 @@ int nfft_plan_timing(nfft_plan_t p, double *ms);
  *   stage 3 (interpolation): reads the plan's grid, writes fhat (`out`, M
  *            complex values, device).
  *   stage 4 (spreading): reads fhat (`in`, M complex values, device) and
- *            writes the plan's padded tiles; in 1-D and 3-D also the halo
- *            merge into the plan's grid, as in nfft_adjoint (4-D: writes the
- *            plan's grid).
+ *            writes the plan's spreading scratch; in 1-D and with 3-D padded
+ *            tiles also the halo merge into the plan's grid, as in nfft_adjoint
+ *            (4-D: writes the plan's grid; 2-D and 3-D column sweeps leave the
+ *            merge to the first adjoint FFT pass, as nfft_adjoint does).
  * Errors: NFFT_ERR_ARG for another stage, reps < 1 or a missing pointer
  * (when M > 0); NFFT_ERR_HIP for a failed launch or event.
  */

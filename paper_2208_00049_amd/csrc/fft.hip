@@ -406,6 +406,131 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
     }
 }
 
+// Axis-0 pass of the 3-D adjoint whose input is the scratch of the column
+// sweeps: grid point (p, i1, i2) is the sum of the scratch planes p of the up to
+// four columns that cover (i1, i2) and, for the first 2m - 1 planes of a segment,
+// of the preceding segments' halo planes -- the sweep's merge, in the same order
+// of summation (the four column planes, then the four halo planes).  The B columns of a workgroup lie in one row of one 16 x 16
+// column (B divides 16), so every source read is a run of B consecutive values.
+template <typename T, bool POW2>
+__global__ void __launch_bounds__(1024) k_fft_axis0_from_sweep(cplx<T> *grid, FftLine fl, AxisPass a,
+                                                               SweepSource ss) {
+    constexpr int DIR = +1;  // the adjoint's first pass
+    using C = cplx<T>;
+    grid += blockIdx.y * a.cstride;  // channel
+    const C *scr = (const C *)ss.scr + blockIdx.y * ss.cstride;
+    const C *halo = scr + ss.sg.main_cells;
+    extern __shared__ unsigned char smem_raw[];
+    C *lds = reinterpret_cast<C *>(smem_raw);
+    const int L = fl.L, LP = L + kLinePad;
+    const int B = a.lines_per_block;  // a power of two dividing 16
+    const int lgB = __ffs(B) - 1;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const long long inner = a.inner;
+    const int i0 = blk * B;
+    const Geom &g = ss.g;
+    const int taps = g.taps, P = kSweepQ + taps - 1, PP = P * P;
+    const int ncols = ss.sg.ncols, nsc = ss.sg.nsc, Ls = ss.sg.L * g.Q[0];  // planes per segment
+    C *twl = lds + B * LP;
+    if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, nthr);
+
+    // this thread's column and its up to four sources (column, offset in its padded plane)
+    const int bb = tid & (B - 1);  // fixed per thread: nthr is a multiple of B
+    const int i1 = i0 / g.Nt[2], i2 = i0 - i1 * g.Nt[2] + bb;
+    const int t1 = i1 / kSweepQ, a1 = i1 - t1 * kSweepQ;
+    const int t2 = i2 / kSweepQ, a2 = i2 - t2 * kSweepQ;
+    int src_col[4], src_off[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int e1 = e >> 1, e2 = e & 1;  // the source column precedes along axis 1 / 2
+        int c1 = t1 - e1, c2 = t2 - e2;
+        if (c1 < 0) c1 += g.T[1];
+        if (c2 < 0) c2 += g.T[2];
+        const bool ok = !((e1 && a1 >= taps - 1) || (e2 && a2 >= taps - 1));
+        src_col[e] = ok ? c1 * g.T[2] + c2 : -1;
+        src_off[e] = (a1 + (e1 ? kSweepQ : 0)) * P + a2 + (e2 ? kSweepQ : 0);
+    }
+    // the columns' planes (all four sources' loads of U elements in flight) ...
+    constexpr int U = 4;
+    for (int base = 0; base < L * B; base += U * nthr) {
+        C v[U][4];
+        int r_of[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr + tid;
+            const int r = (idx < L * B ? idx : bb) >> lgB;  // plane
+            r_of[u] = idx < L * B ? r : -1;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = src_col[e] >= 0;
+                v[u][e] = ok ? scr[((size_t)r * ncols + src_col[e]) * PP + src_off[e]]
+                             : cmake<C>((T)0, (T)0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r_of[u] < 0) continue;
+            T sr = (T)0, si = (T)0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sr += v[u][e].x;
+                si += v[u][e].y;
+            }
+            lds[bb * LP + r_of[u]] = cmake<C>(sr, si);
+        }
+    }
+    __syncthreads();
+    // ... then the preceding segments' halo planes on the first taps - 1 planes of
+    // every segment (each element has one writer in both loops)
+    const int nh = nsc * (taps - 1);
+    for (int idx = tid; idx < nh * B; idx += nthr) {
+        const int hb = idx & (B - 1), h = idx >> lgB;
+        const int kseg = h / (taps - 1), j = h - kseg * (taps - 1);
+        const int kpred = kseg == 0 ? nsc - 1 : kseg - 1;
+        const int r = kseg * Ls + j;
+        // the source columns of column hb (recomputed: hb differs from this thread's bb)
+        const int hi2 = i0 - i1 * g.Nt[2] + hb;
+        const int ht2 = hi2 / kSweepQ, ha2 = hi2 - ht2 * kSweepQ;
+        C hv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int e1 = e >> 1, e2 = e & 1;
+            int c1 = t1 - e1, c2 = ht2 - e2;
+            if (c1 < 0) c1 += g.T[1];
+            if (c2 < 0) c2 += g.T[2];
+            const bool ok = !((e1 && a1 >= taps - 1) || (e2 && ha2 >= taps - 1));
+            const int off = (a1 + (e1 ? kSweepQ : 0)) * P + ha2 + (e2 ? kSweepQ : 0);
+            const int cc = c1 * g.T[2] + c2;
+            hv[e] = ok ? halo[((size_t)(cc * nsc + kpred) * (taps - 1) + j) * PP + off]
+                       : cmake<C>((T)0, (T)0);
+        }
+        T hr = (T)0, hi = (T)0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            hr += hv[e].x;
+            hi += hv[e].y;
+        }
+        C acc = lds[hb * LP + r];
+        acc.x += hr;
+        acc.y += hi;
+        lds[hb * LP + r] = acc;
+    }
+    __syncthreads();
+
+    const int b = tid / fl.tpl, t = tid % fl.tpl;
+    const bool active = b < B;
+    if (fl.tw_lds) line_fft<C, DIR, POW2>(lds + (active ? b : 0) * LP, active, t, fl, twl);
+    else line_fft<C, DIR, POW2>(lds + (active ? b : 0) * LP, active, t, fl, (const C *)fl.tw);
+
+    const int nout = a.out_band_N ? a.out_band_N : L;
+    for (int idx = tid; idx < nout * B; idx += nthr) {
+        const int cb = idx & (B - 1), r = idx >> lgB;
+        const int row = a.out_band_N ? band_pos(r, a.out_band_N, L) : r;
+        if (i0 + cb < inner) grid[(long long)row * inner + i0 + cb] = lds[cb * LP + row];
+    }
+}
+
 // Last-axis pass on contiguous lines.  mode 0: grid -> grid over all lines.
 // mode 1: f -> grid; the line of outer position (i_0, .., i_{D-2}) in I_N gets
 // f[i_0]..[r] * beta_0[i_0] .. beta_last[r] at (r - floor(N/2)) mod Nt, zeros
@@ -600,6 +725,30 @@ hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const Axi
         if (p.D == 2) NFFT_PAD_LAUNCH(double, 2) else NFFT_PAD_LAUNCH(double, 3)
     }
 #undef NFFT_PAD_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_axis0_from_sweep(const nfft_plan_s &p, void *grid, const AxisPass &a,
+                                       const void *scr, hipStream_t s) {
+    const int B = a.lines_per_block;
+    const size_t cs = p.dtype == NFFT_C64 ? sizeof(cplx<float>) : sizeof(cplx<double>);
+    size_t shm = 0;
+    const FftLine fl = with_lds_table(p, p.line[0], B, cs, shm);
+    SweepSource ss{scr, p.sweep, p.geom, (long long)sweep_scratch_cells(p)};
+    const dim3 g((unsigned)(a.inner / B), (unsigned)a.K);
+    const bool pow2 = (fl.L & (fl.L - 1)) == 0;
+#define NFFT_SWEEP_LAUNCH(T)                                                                       \
+    {                                                                                              \
+        auto kern = pow2 ? k_fft_axis0_from_sweep<T, true> : k_fft_axis0_from_sweep<T, false>;     \
+        if (shm > 65536) {                                                                         \
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),              \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm); \
+            if (e != hipSuccess) return e;                                                         \
+        }                                                                                          \
+        hipLaunchKernelGGL(kern, g, dim3(B * fl.tpl), shm, s, (cplx<T> *)grid, fl, a, ss);         \
+    }
+    if (p.dtype == NFFT_C64) NFFT_SWEEP_LAUNCH(float) else NFFT_SWEEP_LAUNCH(double)
+#undef NFFT_SWEEP_LAUNCH
     return hipGetLastError();
 }
 

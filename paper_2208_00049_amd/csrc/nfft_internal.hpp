@@ -113,9 +113,11 @@ template <typename T, int D> struct NodeRec {
 // of L tiles along axis 0; a segment's workgroup keeps a ring of R = Q_0 + taps - 1
 // padded planes in LDS.  Scratch per channel: main_cells values (every grid plane
 // of every column, padded to (kSweepQ + taps - 1)^2 points), then per segment its
-// taps - 1 trailing halo planes.
+// taps - 1 trailing halo planes, then fhat in sorted node order (M values) and the
+// gather's kSweepParts block maxima (doubles, one per complex slot).
 constexpr int kSweepQ = 16;
 constexpr int kSweepMaxSegTiles = 64;
+constexpr int kSweepParts = 256;  // blocks of the fhat gather
 struct SweepGeom {
     int on;              // 1: the plan spreads by column sweeps
     int ncols;           // columns (T_1 T_2)
@@ -123,6 +125,8 @@ struct SweepGeom {
     int L;               // tiles per segment (divides T_0)
     int R;               // ring planes
     long long main_cells;
+    long long sorted_off;  // offset of the sorted fhat (main + halo values)
+    long long part_off;    // offset of the block maxima (sorted_off + M)
 };
 
 // Factorisation of one FFT line length and its twiddle table exp(-2 pi i t / L).
@@ -164,6 +168,15 @@ struct PadSource {
     Geom g;
     int M2;               // 2m
     long long cstride;    // elements between the channels' sets of padded tiles
+};
+
+// Source of the first adjoint axis pass when it also merges the column sweeps
+// of 3-D spreading (see the sweep's merge kernel).
+struct SweepSource {
+    const void *scr;      // channel 0's sweep scratch, complex
+    SweepGeom sg;
+    Geom g;
+    long long cstride;    // values between the channels' scratch
 };
 
 struct ContigPass {
@@ -283,6 +296,9 @@ hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, 
 // axis-0 adjoint pass reading the merged padded tiles instead of the grid (D >= 2)
 hipError_t launch_fft_axis0_from_pad(const nfft_plan_s &p, void *grid, const AxisPass &a,
                                      const void *pad, hipStream_t s);
+// axis-0 adjoint pass reading and merging the column sweeps' scratch (3-D sweep plans)
+hipError_t launch_fft_axis0_from_sweep(const nfft_plan_s &p, void *grid, const AxisPass &a,
+                                       const void *scr, hipStream_t s);
 hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, const ContigPass &c,
                              hipStream_t s);
 
@@ -300,9 +316,10 @@ hipError_t launch_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfh
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                          bool merge = true, int K = 1, void *pad = nullptr);
 
-// spread_sweep.hip: column-sweep spreading and its merge into grid (K channels)
+// spread_sweep.hip: column-sweep spreading (the fhat gather and the sweep) and, with
+// merge, the merge into grid (K channels); without, the first adjoint FFT pass merges
 hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
-                               int K, void *pad);
+                               int K, void *pad, bool merge);
 // static LDS of the sweep kernel (staged chunk, segment tables)
 size_t sweep_static_lds(int dtype);
 // points of one padded column plane
@@ -312,8 +329,7 @@ inline size_t sweep_ring_bytes(int R, int taps) { return (size_t)R * 2 * sweep_p
 inline size_t sweep_ring_bytes(const nfft_plan_s &p) { return sweep_ring_bytes(p.sweep.R, p.geom.taps); }
 // scratch values per channel: the column planes and the segments' halo planes
 inline size_t sweep_scratch_cells(const nfft_plan_s &p) {
-    return (size_t)p.sweep.main_cells + (size_t)p.sweep.ncols * p.sweep.nsc * (p.geom.taps - 1) *
-                                            sweep_plane_cells(p.geom.taps);
+    return (size_t)p.sweep.part_off + kSweepParts;
 }
 
 }  // namespace nfft

@@ -342,6 +342,9 @@ bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q)
     p.sweep.nsc = T0 / L;
     p.sweep.R = q0 + taps - 1;
     p.sweep.main_cells = (long long)p.Nt[0] * ncols * sweep_plane_cells(taps);
+    p.sweep.sorted_off = p.sweep.main_cells +
+                         (long long)ncols * p.sweep.nsc * (taps - 1) * sweep_plane_cells(taps);
+    p.sweep.part_off = p.sweep.sorted_off + p.M;
     Q[0] = q0;
     Q[1] = Q[2] = kSweepQ;
     return true;
@@ -801,8 +804,9 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pa
         hipError_t e;
         {
             StageTimer t(p, a == 0 ? 5 : 6, s);
-            e = merge_here ? launch_fft_axis0_from_pad(p, grid, ap, pad, s)
-                           : launch_fft_axis(p, grid, ap, s);
+            e = !merge_here  ? launch_fft_axis(p, grid, ap, s)
+                : p.sweep.on ? launch_fft_axis0_from_sweep(p, grid, ap, pad, s)
+                             : launch_fft_axis0_from_pad(p, grid, ap, pad, s);
         }
         if (e != hipSuccess) return e;
     }
@@ -892,10 +896,11 @@ hipError_t run_forward(const nfft_plan_s &p, const void *f, void *fhat, int K, v
 
 hipError_t run_adjoint(const nfft_plan_s &p, const void *fhat, void *y, int K, void *grid,
                        void *pad, hipStream_t s) {
-    // 2-D: the halo merge of spreading is done by the first adjoint FFT pass (in
-    // 3-D the separate merge kernel is faster: a pass's columns would span one
-    // short tile edge, and each grid value gathers from up to eight tiles)
-    const bool fuse = p.D == 2;
+    // 2-D and 3-D column sweeps: the merge of spreading is done by the first adjoint
+    // FFT pass (for 3-D padded tiles the separate merge kernel is faster: a pass's
+    // columns would span one short tile edge, and each grid value gathers from up
+    // to eight tiles)
+    const bool fuse = p.D == 2 || p.sweep.on;
     hipError_t e;
     {
         StageTimer t(p, 4, s);
@@ -985,7 +990,7 @@ int nfft_plan_bench_stage(nfft_plan_t p, int stage, int reps, const void *in, vo
     if (e == hipSuccess) e = hipEventRecord(a, s);
     for (int i = 0; i < reps && e == hipSuccess && p->M > 0; ++i)
         e = stage == 3 ? launch_interp(*p, p->grid, out, s)
-                       : launch_spread(*p, in, p->grid, s, p->D != 2);
+                       : launch_spread(*p, in, p->grid, s, p->D != 2 && !p->sweep.on);
     if (e == hipSuccess) e = hipEventRecord(b, s);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;

@@ -71,7 +71,7 @@ hipError_t launch_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfh
 hipError_t launch_spread(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                          bool merge, int K, void *pad) {
     if (!pad) pad = p.pad;
-    if (p.sweep.on) return launch_spread_sweep(p, fhat, grid, s, K, pad);
+    if (p.sweep.on) return launch_spread_sweep(p, fhat, grid, s, K, pad, merge);
     return p.dtype == NFFT_C64 ? spread_t<float>(p, fhat, grid, s, merge, K, pad)
                                : spread_t<double>(p, fhat, grid, s, merge, K, pad);
 }

@@ -17,11 +17,21 @@
 // that cover it (its own column and, within 2m - 1 of its leading edges along
 // axes 1 and 2, the columns before it) and, within 2m - 1 planes of a segment
 // start, the halo slots of the segments before.  Every grid value has one
-// writer, in a fixed order of summation; no global atomics are used.
+// writer, in a fixed order of summation; no global atomics are used.  In the
+// adjoint transform the merge is done by the first (axis-0) FFT pass as it
+// loads its lines (fft.hip); the merge kernel here serves the single
+// resampling step.
+//
+// Before the sweep, a gather kernel puts fhat into the sorted node order (the one
+// random access to fhat) and records per block the largest |Re|, |Im|, from which
+// every sweep workgroup takes the transform's fixed-point scale; the sweep then
+// reads node records and values as consecutive runs and loads the next chunk of
+// nodes while it accumulates the current one.
 //
 // Accumulation in LDS:
 //   complex64:  64-bit fixed point per component with a power-of-two scale of
-//               the segment (as in the tiled kernel): exact, order independent.
+//               the transform (from its largest |Re|, |Im|): exact, independent
+//               of the order of the additions.
 //   complex128: FP64 LDS atomic additions (ds_add_f64), two per tap instead of
 //               the four 64-bit integer ones an exact 96-bit sum takes, and 16
 //               bytes per point instead of 32, so that the 16 x 16 columns fit.
@@ -68,13 +78,54 @@ template <typename T, int CH> struct SweepStage {
 template <typename T> constexpr int sweep_chunk() { return sizeof(T) == 4 ? 1024 : 512; }
 template <typename T> constexpr int sweep_threads() { return 1024; }
 
+// fsorted[s] = fhat[perm[s]] for the sorted positions s of block b's range, and
+// part[b] = the largest max(|Re|, |Im|) among them (+infinity if one is not finite).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sweep_gather(const cplx<T> *__restrict__ fhat, const int *__restrict__ perm, int M,
+                   cplx<T> *__restrict__ scr, long long sorted_off, long long part_off,
+                   long long fstride, long long sstride) {
+    using C = cplx<T>;
+    fhat += blockIdx.y * fstride;  // channel
+    scr += blockIdx.y * sstride;
+    C *fsorted = scr + sorted_off;
+    double *part = reinterpret_cast<double *>(scr + part_off);
+    __shared__ double wmax[4];
+    const int per = (M + gridDim.x - 1) / gridDim.x;
+    const int b0 = blockIdx.x * per, b1 = min(M, b0 + per);
+    T mx = (T)0;
+    for (int s0 = b0; s0 < b1; s0 += 4 * 256) {
+        int pm[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * 256 + threadIdx.x;
+            pm[u] = perm[s < b1 ? s : b0];
+        }
+        C v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = fhat[pm[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * 256 + threadIdx.x;
+            if (s < b1) {
+                fsorted[s] = v[u];
+                mx = fmax(mx, scale_mag(v[u].x, v[u].y));
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = (double)mx;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+}
+
 template <typename T, int M2, bool GW>
 __global__ void __launch_bounds__(sweep_threads<T>())
     k_spread_sweep(cplx<T> *__restrict__ scr, Geom g, SweepGeom sg,
-                   const NodeRec<T, 3> *__restrict__ nodes, const int *__restrict__ perm,
-                   const int *__restrict__ key_start, const T *__restrict__ coef, int window,
-                   WinParams<T> wp, T wmax_prod, const cplx<T> *__restrict__ fhat,
-                   long long sstride, long long fstride) {
+                   const NodeRec<T, 3> *__restrict__ nodes, const int *__restrict__ key_start,
+                   const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
+                   long long sstride) {
     using C = cplx<T>;
     using A = SweepAcc<T>;
     using W = typename A::W;
@@ -84,12 +135,13 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     constexpr int NPW = 64 / M2;
     constexpr double kLimit = 1073741824.0;  // 2^30: bound of a scaled c64 contribution
     scr += blockIdx.y * sstride;              // channel
-    fhat += blockIdx.y * fstride;
+    const C *fsorted = scr + sg.sorted_off;
+    const double *part = reinterpret_cast<const double *>(scr + sg.part_off);
     extern __shared__ unsigned char smem_raw[];
     W *acc = reinterpret_cast<W *>(smem_raw);  // [R][Re, Im][PP]
     __shared__ SweepStage<T, CH> st;
-    __shared__ int seg_off[kSweepMaxSegTiles + 1];  // node offsets of the segment's tiles
-    __shared__ int seg_beg[kSweepMaxSegTiles];      // first sorted node of each tile
+    __shared__ int seg_beg[kSweepMaxSegTiles + 1];  // node range of each tile of the segment
+    __shared__ int seg_end[kSweepMaxSegTiles + 1];
     __shared__ unsigned long long amax_bits;
 
     const int seg = blockIdx.x;
@@ -99,38 +151,23 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     const int R = sg.R, Q0 = g.Q[0];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    // node ranges of the segment's tiles, then a pass over its values for the
-    // fixed-point scale (and the detection of a non-finite value)
     if (tid < nt) {
         const int tile = ((tb + tid) * g.T[1] + t1) * g.T[2] + t2;
         seg_beg[tid] = key_start[tile << 3];
-        seg_off[tid + 1] = key_start[(tile + 1) << 3] - key_start[tile << 3];
+        seg_end[tid] = key_start[(tile + 1) << 3];
     }
-    if (tid == 0) {
-        seg_off[0] = 0;
-        amax_bits = 0ull;
-    }
+    if (tid == 0) amax_bits = 0ull;
+    // the transform's largest |Re|, |Im| from the gather's block maxima
+    double pm = 0.0;
+    for (int i = tid; i < kSweepParts; i += NT) pm = fmax(pm, part[i]);
     for (int i = tid; i < R * 2 * PP; i += NT) acc[i] = (W)0;
-    __syncthreads();
-    if (tid == 0)
-        for (int t = 0; t < nt; ++t) seg_off[t + 1] += seg_off[t];
-    __syncthreads();
-    const int total = seg_off[nt];
-    {
-        T mx = (T)0;
-        for (int j = tid; j < total; j += NT) {
-            int t = 0;
-            while (seg_off[t + 1] <= j) ++t;
-            const C v = fhat[perm[seg_beg[t] + j - seg_off[t]]];
-            mx = fmax(mx, scale_mag(v.x, v.y));
-        }
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-        if (lane == 0) atomicMax(&amax_bits, (unsigned long long)__double_as_longlong((double)mx));
-    }
+    for (int off = 32; off >= 1; off >>= 1) pm = fmax(pm, __shfl_xor(pm, off, 64));
+    __syncthreads();
+    if (lane == 0) atomicMax(&amax_bits, (unsigned long long)__double_as_longlong(pm));
     __syncthreads();
     const double amax_d = __longlong_as_double((long long)amax_bits);
-    const bool poisoned = isinf(amax_d);  // a non-finite value in the segment
+    const bool poisoned = isinf(amax_d);  // a non-finite value in fhat
     T scale = (T)1;
     if (A::kFixed && amax_d > 0.0 && !poisoned) {
         int e;
@@ -144,26 +181,53 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     lw.load(coef, li, wp.m);
     const T nan = (T)__builtin_nan("");
 
+    // the chunk after (t, c0): the rest of tile t, else the first chunk of the next
+    // tile that has nodes (t = nt: none)
+    auto next_chunk = [&](int &t, int &c0) {
+        c0 += CH;
+        if (c0 < seg_end[t]) return;
+        for (++t; t < nt && seg_beg[t] == seg_end[t]; ++t) {
+        }
+        c0 = t < nt ? seg_beg[t] : 0;
+    };
+    // one node per staging thread in registers: all loads issued at once
+    NodeRec<T, 3> rec;
+    C val;
+    auto load_chunk = [&](int t, int c0) {
+        const int n = min(CH, seg_end[t] - c0);
+        const int k = c0 + (tid < n ? tid : n - 1);
+        rec = nodes[k];
+        val = fsorted[k];
+    };
+    int ct = -1, cc0 = 0;  // the chunk held in registers
+    {
+        int t = -1, c0 = 0;
+        for (++t; t < nt && seg_beg[t] == seg_end[t]; ++t) {
+        }
+        if (t < nt && !poisoned) {
+            ct = t;
+            cc0 = seg_beg[t];
+            load_chunk(ct, cc0);
+        }
+        (void)c0;
+    }
+
     for (int t = 0; t < nt; ++t) {
-        const int t0 = tb + t;
-        const int nb = seg_beg[t], ne = nb + seg_off[t + 1] - seg_off[t];
-        for (int c0 = nb; c0 < (poisoned ? nb : ne); c0 += CH) {
-            const int n = min(CH, ne - c0);
-            {
-                // every load of the thread's node first, then the LDS writes
-                const int k = tid < n ? tid : n - 1;
-                const NodeRec<T, 3> rec = nodes[c0 + k];
-                const C v = fhat[perm[c0 + k]];
-                if (tid < n) {
-                    int r0 = rec.o[0] % R;
-                    st.pk[tid] = r0 | ((rec.o[1] - t1 * kSweepQ) << 8) | ((rec.o[2] - t2 * kSweepQ) << 16);
+        while (ct == t) {
+            const int c0 = cc0, n = min(CH, seg_end[t] - c0);
+            if (tid < n) {
+                st.pk[tid] = (rec.o[0] % R) | ((rec.o[1] - t1 * kSweepQ) << 8) |
+                             ((rec.o[2] - t2 * kSweepQ) << 16);
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) st.fr[d][tid] = rec.fr[d];
-                    st.vr[tid] = v.x;
-                    st.vi[tid] = v.y;
-                }
+                for (int d = 0; d < 3; ++d) st.fr[d][tid] = rec.fr[d];
+                st.vr[tid] = val.x;
+                st.vi[tid] = val.y;
             }
             __syncthreads();
+            // the next chunk's loads overlap the accumulation of this one
+            next_chunk(ct, cc0);
+            if (ct < nt) load_chunk(ct, cc0);
+            else ct = -1;
             for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
                 const int k = base + grp;
                 const bool valid = grp < NPW && k < n;
@@ -193,7 +257,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             __syncthreads();
         }
         // the tile's Q_0 planes are complete: write them out, clear their slots
-        const int p0 = t0 * Q0;
+        const int p0 = (tb + t) * Q0;
         const int rb = p0 % R;
         for (int idx = tid; idx < Q0 * PP; idx += NT) {
             const int kk = idx / PP, cell = idx - kk * PP;
@@ -240,24 +304,37 @@ __global__ void __launch_bounds__(256)
     const int j = p - kseg * sg.L * g.Q[0];  // plane within its segment
     const int kpred = kseg == 0 ? sg.nsc - 1 : kseg - 1;
     const C *halo = scr + sg.main_cells;
-    T sr = (T)0, si = (T)0;
+    // the four column planes, then the four halo planes (the order of the fused pass)
+    int cc[4], off[4];
+    bool ok[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int e1 = e >> 1, e2 = e & 1;  // the source column precedes along axis 1 / 2
-        if ((e1 && a1 >= M2 - 1) || (e2 && a2 >= M2 - 1)) continue;
+        ok[e] = !((e1 && a1 >= M2 - 1) || (e2 && a2 >= M2 - 1));
         int c1 = t1 - e1, c2 = t2 - e2;
         if (c1 < 0) c1 += g.T[1];
         if (c2 < 0) c2 += g.T[2];
-        const int cc = c1 * g.T[2] + c2;
-        const int off = (a1 + (e1 ? kSweepQ : 0)) * P + a2 + (e2 ? kSweepQ : 0);
-        const C v = scr[((size_t)p * sg.ncols + cc) * PP + off];
+        cc[e] = c1 * g.T[2] + c2;
+        off[e] = (a1 + (e1 ? kSweepQ : 0)) * P + a2 + (e2 ? kSweepQ : 0);
+    }
+    T sr = (T)0, si = (T)0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const C v = ok[e] ? scr[((size_t)p * sg.ncols + cc[e]) * PP + off[e]] : cmake<C>((T)0, (T)0);
         sr += v.x;
         si += v.y;
-        if (j < M2 - 1) {
-            const C h = halo[((size_t)(cc * sg.nsc + kpred) * (M2 - 1) + j) * PP + off];
-            sr += h.x;
-            si += h.y;
+    }
+    if (j < M2 - 1) {
+        T hr = (T)0, hi = (T)0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const C h = ok[e] ? halo[((size_t)(cc[e] * sg.nsc + kpred) * (M2 - 1) + j) * PP + off[e]]
+                              : cmake<C>((T)0, (T)0);
+            hr += h.x;
+            hi += h.y;
         }
+        sr += hr;
+        si += hi;
     }
     const long long gi = ((long long)p * g.Nt[1] + t1 * kSweepQ + a1) * g.Nt[2] + t2 * kSweepQ + a2;
     grid[gi] = cmake<C>(sr, si);
@@ -265,24 +342,25 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int M2>
 hipError_t run_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
-                            int K, void *pad) {
+                            int K, void *pad, bool merge) {
     const long long sstride = (long long)sweep_scratch_cells(p);
     const SweepGeom &sg = p.sweep;
-    if (p.M > 0) {
-        const size_t shm = sweep_ring_bytes(p);
-        const bool gw = p.window != NFFT_WINDOW_POLY;
-        auto kern = gw ? k_spread_sweep<T, M2, true> : k_spread_sweep<T, M2, false>;
-        hipError_t e = allow_lds(kern, shm, sizeof(SweepStage<T, sweep_chunk<T>()>) + 1024);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(sg.ncols * sg.nsc, K), dim3(sweep_threads<T>()), shm, s,
-                           (cplx<T> *)pad, p.geom, sg, (const NodeRec<T, 3> *)p.nodes, p.perm,
-                           p.key_start, (const T *)p.coef, p.window, win_params<T>(p),
-                           (T)window_bound(3), (const cplx<T> *)fhat, sstride, (long long)p.M);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    } else {
-        return launch_fill_zero_complex(grid, (int64_t)K * p.G, sizeof(T) == 8, s);
-    }
+    if (p.M == 0) return launch_fill_zero_complex(grid, (int64_t)K * p.G, sizeof(T) == 8, s);
+    hipLaunchKernelGGL(k_sweep_gather<T>, dim3(kSweepParts, K), dim3(256), 0, s,
+                       (const cplx<T> *)fhat, p.perm, (int)p.M, (cplx<T> *)pad, sg.sorted_off,
+                       sg.part_off, (long long)p.M, sstride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t shm = sweep_ring_bytes(p);
+    const bool gw = p.window != NFFT_WINDOW_POLY;
+    auto kern = gw ? k_spread_sweep<T, M2, true> : k_spread_sweep<T, M2, false>;
+    e = allow_lds(kern, shm, sizeof(SweepStage<T, sweep_chunk<T>()>) + 1024);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(sg.ncols * sg.nsc, K), dim3(sweep_threads<T>()), shm, s,
+                       (cplx<T> *)pad, p.geom, sg, (const NodeRec<T, 3> *)p.nodes, p.key_start,
+                       (const T *)p.coef, p.window, win_params<T>(p), (T)window_bound(3), sstride);
+    e = hipGetLastError();
+    if (e != hipSuccess || !merge) return e;
     hipLaunchKernelGGL((k_sweep_merge<T, M2>), dim3(p.geom.Nt[0] * sg.ncols, K), dim3(256), 0, s,
                        (cplx<T> *)grid, p.geom, sg, (const cplx<T> *)pad, (long long)p.G, sstride);
     return hipGetLastError();
@@ -290,21 +368,21 @@ hipError_t run_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, 
 
 template <typename T>
 static hipError_t sweep_t(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s, int K,
-                          void *pad) {
+                          void *pad, bool merge) {
     switch (p.geom.taps) {
-        case 2: return run_spread_sweep<T, 2>(p, fhat, grid, s, K, pad);
-        case 4: return run_spread_sweep<T, 4>(p, fhat, grid, s, K, pad);
-        case 6: return run_spread_sweep<T, 6>(p, fhat, grid, s, K, pad);
-        case 8: return run_spread_sweep<T, 8>(p, fhat, grid, s, K, pad);
-        case 10: return run_spread_sweep<T, 10>(p, fhat, grid, s, K, pad);
+        case 2: return run_spread_sweep<T, 2>(p, fhat, grid, s, K, pad, merge);
+        case 4: return run_spread_sweep<T, 4>(p, fhat, grid, s, K, pad, merge);
+        case 6: return run_spread_sweep<T, 6>(p, fhat, grid, s, K, pad, merge);
+        case 8: return run_spread_sweep<T, 8>(p, fhat, grid, s, K, pad, merge);
+        case 10: return run_spread_sweep<T, 10>(p, fhat, grid, s, K, pad, merge);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
-                               int K, void *pad) {
-    return p.dtype == NFFT_C64 ? sweep_t<float>(p, fhat, grid, s, K, pad)
-                               : sweep_t<double>(p, fhat, grid, s, K, pad);
+                               int K, void *pad, bool merge) {
+    return p.dtype == NFFT_C64 ? sweep_t<float>(p, fhat, grid, s, K, pad, merge)
+                               : sweep_t<double>(p, fhat, grid, s, K, pad, merge);
 }
 
 size_t sweep_static_lds(int dtype) {
