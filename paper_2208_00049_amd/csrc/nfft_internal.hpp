@@ -324,9 +324,27 @@ hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *gri
 size_t sweep_static_lds(int dtype);
 // points of one padded column plane
 inline int sweep_plane_cells(int taps) { return (kSweepQ + taps - 1) * (kSweepQ + taps - 1); }
-// dynamic LDS of the sweep kernel: R planes, two 8-byte words per point
-inline size_t sweep_ring_bytes(int R, int taps) { return (size_t)R * 2 * sweep_plane_cells(taps) * 8; }
-inline size_t sweep_ring_bytes(const nfft_plan_s &p) { return sweep_ring_bytes(p.sweep.R, p.geom.taps); }
+// The complex128 sweep with 2m = 8 and the polynomial window maps one node to a
+// wavefront, lanes over (axis-0 tap, axis-2 tap): an atomic instruction then adds
+// to eight runs of eight consecutive words, one per ring plane, and a plane stride
+// of 8 words modulo 32 puts every four runs on disjoint LDS banks.
+__host__ __device__ constexpr bool sweep_wave_node(bool dbl, int taps, bool poly) {
+    return dbl && taps == 8 && poly;
+}
+// 8-byte words per ring plane: Re and Im of every point, padded as above
+__host__ __device__ constexpr int sweep_plane_stride(int taps, bool wave_node) {
+    return 2 * (kSweepQ + taps - 1) * (kSweepQ + taps - 1) +
+           (wave_node ? (8 - (2 * (kSweepQ + taps - 1) * (kSweepQ + taps - 1)) % 32 + 32) % 32 : 0);
+}
+// dynamic LDS of the sweep kernel: R planes of 8-byte words
+inline size_t sweep_ring_bytes(int R, int taps, bool wave_node) {
+    return (size_t)R * sweep_plane_stride(taps, wave_node) * 8;
+}
+inline size_t sweep_ring_bytes(const nfft_plan_s &p) {
+    return sweep_ring_bytes(p.sweep.R, p.geom.taps,
+                            sweep_wave_node(p.dtype == NFFT_C128, p.geom.taps,
+                                            p.window == NFFT_WINDOW_POLY));
+}
 // scratch values per channel: the column planes and the segments' halo planes
 inline size_t sweep_scratch_cells(const nfft_plan_s &p) {
     return (size_t)p.sweep.part_off + kSweepParts;

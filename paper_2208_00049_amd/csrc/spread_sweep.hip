@@ -75,6 +75,17 @@ template <typename T, int CH> struct SweepStage {
     T vi[CH];
 };
 
+// Value of lane `l` (uniform across the wavefront).
+__device__ inline double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 template <typename T> constexpr int sweep_chunk() { return sizeof(T) == 4 ? 1024 : 512; }
 template <typename T> constexpr int sweep_threads() { return 1024; }
 
@@ -133,6 +144,8 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     constexpr int CH = sweep_chunk<T>();
     constexpr int P = kSweepQ + M2 - 1, PP = P * P;
     constexpr int NPW = 64 / M2;
+    constexpr bool WN = sweep_wave_node(sizeof(T) == 8, M2, !GW);  // one node per wavefront
+    constexpr int SP = sweep_plane_stride(M2, WN);                   // words per ring plane
     constexpr double kLimit = 1073741824.0;  // 2^30: bound of a scaled c64 contribution
     scr += blockIdx.y * sstride;              // channel
     const C *fsorted = scr + sg.sorted_off;
@@ -160,7 +173,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     // the transform's largest |Re|, |Im| from the gather's block maxima
     double pm = 0.0;
     for (int i = tid; i < kSweepParts; i += NT) pm = fmax(pm, part[i]);
-    for (int i = tid; i < R * 2 * PP; i += NT) acc[i] = (W)0;
+    for (int i = tid; i < R * SP; i += NT) acc[i] = (W)0;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) pm = fmax(pm, __shfl_xor(pm, off, 64));
     __syncthreads();
@@ -178,7 +191,17 @@ __global__ void __launch_bounds__(sweep_threads<T>())
 
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
     LaneWindow<T, 3, M2> lw;
-    lw.load(coef, li, wp.m);
+    if constexpr (WN) {
+        // axis 0: tap grp (the lane's plane); axes 1 and 2: tap li
+        const int Z = 2 * wp.m + 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int z = 0; z <= M2; ++z)
+                lw.cf[d][z] = z < Z ? coef[((size_t)d * M2 + (d == 0 ? grp : li)) * Z + z] : (T)0;
+    } else {
+        lw.load(coef, li, wp.m);
+    }
     const T nan = (T)__builtin_nan("");
 
     // the chunk after (t, c0): the rest of tile t, else the first chunk of the next
@@ -228,6 +251,32 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             next_chunk(ct, cc0);
             if (ct < nt) load_chunk(ct, cc0);
             else ct = -1;
+            if constexpr (WN) {
+                // one node per wavefront: lane (grp, li) adds the taps (grp, b, li), b = 0..7
+                for (int k = wave; k < n; k += NT / 64) {
+                    const int pk = st.pk[k];
+                    const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
+                    const T z0 = st.fr[0][k] - (T)0.5, z1 = st.fr[1][k] - (T)0.5,
+                            z2 = st.fr[2][k] - (T)0.5;
+                    T h0 = lw.cf[0][M2], h1 = lw.cf[1][M2], h2 = lw.cf[2][M2];
+#pragma unroll
+                    for (int z = M2 - 1; z >= 0; --z) {
+                        h0 = fma(h0, z0, lw.cf[0][z]);
+                        h1 = fma(h1, z1, lw.cf[1][z]);
+                        h2 = fma(h2, z2, lw.cf[2][z]);
+                    }
+                    const T ws = h0 * h2 * scale;
+                    const T pr = st.vr[k] * ws, pi = st.vi[k] * ws;
+                    int r = r0 + grp;
+                    if (r >= R) r -= R;
+                    W *pl = acc + r * SP + (l1 * P + l2 + li);
+#pragma unroll
+                    for (int b = 0; b < M2; ++b) {
+                        const T wb = lane_value(h1, b);  // lane b holds axis-1 tap b
+                        A::add(pl + b * P, PP, wb * pr, wb * pi);
+                    }
+                }
+            } else {
             for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
                 const int k = base + grp;
                 const bool valid = grp < NPW && k < n;
@@ -248,11 +297,12 @@ __global__ void __launch_bounds__(sweep_threads<T>())
                 for (int a = 0; a < M2; ++a) {
                     int r = r0 + a;
                     if (r >= R) r -= R;
-                    W *pl = cell + r * (2 * PP);
+                    W *pl = cell + r * SP;
                     const T ar = w0[a] * pr, ai = w0[a] * pi;
 #pragma unroll
                     for (int b = 0; b < M2; ++b) A::add(pl + b * P, PP, w1[b] * ar, w1[b] * ai);
                 }
+            }
             }
             __syncthreads();
         }
@@ -263,7 +313,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             const int kk = idx / PP, cell = idx - kk * PP;
             int r = rb + kk;
             if (r >= R) r -= R;
-            W *a = acc + r * (2 * PP) + cell;
+            W *a = acc + r * SP + cell;
             const C v = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv), A::get(a + PP, inv));
             a[0] = (W)0;
             a[PP] = (W)0;
@@ -279,7 +329,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
         const int kk = idx / PP, cell = idx - kk * PP;
         int r = rh + kk;
         if (r >= R) r -= R;
-        const W *a = acc + r * (2 * PP) + cell;
+        const W *a = acc + r * SP + cell;
         halo[idx] = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv), A::get(a + PP, inv));
     }
 }
