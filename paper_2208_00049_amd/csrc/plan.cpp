@@ -310,7 +310,7 @@ bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q)
     auto fits = [&](int q0) {
         if (q0 < 1 || p.Nt[0] % q0 || p.Nt[0] / q0 < 2) return false;
         const int q[3] = {q0, kSweepQ, kSweepQ};
-        const bool wn = sweep_wave_node(p.dtype == NFFT_C128, taps, p.window == NFFT_WINDOW_POLY);
+        const bool wn = sweep_wave_node(taps, p.window == NFFT_WINDOW_POLY);
         return sweep_ring_bytes(q0 + taps - 1, taps, wn) + sweep_static_lds(p.dtype) <= budget &&
                interp_lds(q, 3, taps, cs) <= budget;
     };

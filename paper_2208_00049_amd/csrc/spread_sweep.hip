@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     constexpr int CH = sweep_chunk<T>();
     constexpr int P = kSweepQ + M2 - 1, PP = P * P;
     constexpr int NPW = 64 / M2;
-    constexpr bool WN = sweep_wave_node(sizeof(T) == 8, M2, !GW);  // one node per wavefront
+    constexpr bool WN = sweep_wave_node(M2, !GW);  // one node per wavefront
     constexpr int SP = sweep_plane_stride(M2, WN);                   // words per ring plane
     constexpr double kLimit = 1073741824.0;  // 2^30: bound of a scaled c64 contribution
     scr += blockIdx.y * sstride;              // channel
