@@ -25,6 +25,14 @@ constexpr size_t stage_bytes(int D, int rs) {
 }
 // LDS of the resampling kernels besides the tile: staged chunk and the scale.
 constexpr size_t resample_static_lds(int D, int rs) { return stage_bytes(D, rs) + 16; }
+// Interpolation stages more nodes per chunk in 3-D complex128, whose (8, 16, 16)
+// tile leaves room for one node per thread: a tile's nodes (about 256 at sigma = 2)
+// then come in one chunk, instead of four chunks each behind a barrier and the
+// dependent loads of its node records.
+constexpr int interp_chunk(int D, int rs) { return D == 3 && rs == 8 ? 512 : stage_chunk(D, rs); }
+constexpr size_t interp_static_lds(int D, int rs) {
+    return (size_t)interp_chunk(D, rs) * (4 * D + rs * (D + 2) + 4) + 16;
+}
 
 struct Geom {
     int D;

@@ -111,7 +111,7 @@ bool factor_line(int L, FftLine &fl) {
 size_t interp_lds(const int *Q, int D, int taps, size_t cs) {
     size_t t = cs;
     for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + taps - 1);
-    return t + nfft::resample_static_lds(D, (int)cs / 2);
+    return t + nfft::interp_static_lds(D, (int)cs / 2);
 }
 
 // LDS of the spreading kernel: fixed-point accumulators of the padded tile (one

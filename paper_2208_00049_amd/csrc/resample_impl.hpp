@@ -197,8 +197,8 @@ struct BoxRows {
 
 // ---- staged node data -------------------------------------------------------
 
-template <typename T, int D> struct Stage {
-    static constexpr int kChunk = stage_chunk(D, (int)sizeof(T));
+template <typename T, int D, int CH_ = stage_chunk(D, (int)sizeof(T))> struct Stage {
+    static constexpr int kChunk = CH_;
     int l[D][kChunk];  // stencil origin relative to the workgroup's tile, in [0, Q)
     T fr[D][kChunk];
     T vr[kChunk];      // spreading: fhat value
@@ -280,9 +280,10 @@ __global__ void __launch_bounds__(NT)
     grid += blockIdx.y * gstride;  // channel
     fhat += blockIdx.y * fstride;
     constexpr int NPW = 64 / M2;
-    constexpr int CH = Stage<T, D>::kChunk;
+    using StageT = Stage<T, D, interp_chunk(D, (int)sizeof(T))>;
+    constexpr int CH = StageT::kChunk;
     extern __shared__ unsigned char smem_raw[];
-    __shared__ Stage<T, D> st;
+    __shared__ StageT st;
     C *tile = reinterpret_cast<C *>(smem_raw);
 
     const int4 sp = subs[blockIdx.x];
@@ -847,6 +848,14 @@ __global__ void __launch_bounds__(kResampleThreads)
     }
 }
 
+// Static LDS of the interpolation kernel (its staged node chunk).
+template <typename T, int D> constexpr size_t interp_static_lds_t() {
+    static_assert(sizeof(Stage<T, D, interp_chunk(D, (int)sizeof(T))>) <=
+                      interp_static_lds(D, (int)sizeof(T)),
+                  "staged chunk larger than the LDS the plan reserves for it");
+    return interp_static_lds(D, (int)sizeof(T));
+}
+
 // Static LDS of the resampling kernels (staged node chunk and the scale).
 template <typename T, int D> constexpr size_t static_lds() {
     static_assert(sizeof(Stage<T, D>) <= stage_bytes(D, (int)sizeof(T)),
@@ -891,7 +900,7 @@ hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStr
     const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
     const bool gw = p.window != NFFT_WINDOW_POLY;
     auto kern = gw ? k_interp<T, D, M2, true, false, NT> : k_interp<T, D, M2, false, false, NT>;
-    hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
+    hipError_t e = allow_lds(kern, shm, interp_static_lds_t<T, D>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(NT), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
@@ -907,7 +916,7 @@ hipError_t run_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat,
     constexpr int NT = resample_threads<T, D>();
     const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
     auto kern = k_interp<T, D, M2, false, true, NT>;
-    hipError_t e = allow_lds(kern, shm, static_lds<T, D>());
+    hipError_t e = allow_lds(kern, shm, interp_static_lds_t<T, D>());
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(p.nsub, 1), dim3(NT), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,

@@ -265,15 +265,17 @@ __global__ void __launch_bounds__(sweep_threads<T>())
                         h1 = fma(h1, z1, lw.cf[1][z]);
                         h2 = fma(h2, z2, lw.cf[2][z]);
                     }
-                    const T ws = h0 * h2 * scale;
+                    // the products in the order of the other mapping (bit-identical terms)
+                    const T ws = h2 * scale;
                     const T pr = st.vr[k] * ws, pi = st.vi[k] * ws;
+                    const T ar = h0 * pr, ai = h0 * pi;
                     int r = r0 + grp;
                     if (r >= R) r -= R;
                     W *pl = acc + r * SP + (l1 * P + l2 + li);
 #pragma unroll
                     for (int b = 0; b < M2; ++b) {
                         const T wb = lane_value(h1, b);  // lane b holds axis-1 tap b
-                        A::add(pl + b * P, PP, wb * pr, wb * pi);
+                        A::add(pl + b * P, PP, wb * ar, wb * ai);
                     }
                 }
             } else {
