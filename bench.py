@@ -96,7 +96,7 @@ STAGE_KERNEL = {
                  "interp": ["nfft::k_interp<float, 3, 8, false, false, 512>"]},
     (3, "c128"): {"spread": ["nfft::k_sweep_gather<double>",
                              "nfft::k_spread_sweep<double, 8, false>"],
-                  "interp": ["nfft::k_interp<double, 3, 8, false, false, 512>"]},
+                  "interp": ["nfft::k_interp_sweep<double, 8, false>"]},
     (4, "c64"): {"spread": ["nfft::k_spread_owner<float, 4, 8>"],
                  "interp": ["nfft::k_interp_node<float, 4, 8>"]},
 }

@@ -194,7 +194,7 @@ template <typename T, int DIR, bool POW2>
 __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl, AxisPass a) {
     using C = cplx<T>;
     grid += blockIdx.y * a.cstride;  // channel
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
     const int B = a.lines_per_block;  // a power of two
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
     using C = cplx<T>;
     grid += blockIdx.y * a.cstride;  // channel
     constexpr int ER = 1 << (D - 1);  // shifts along the axes after axis 0
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
     const int B = a.lines_per_block;  // a power of two dividing Q_{D-1}
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_sweep(cplx<T> *grid, Ff
     grid += blockIdx.y * a.cstride;  // channel
     const C *scr = (const C *)ss.scr + blockIdx.y * ss.cstride;
     const C *halo = scr + ss.sg.main_cells;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
     const int B = a.lines_per_block;  // a power of two dividing 16
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     using C = cplx<T>;
     src += blockIdx.y * c.src_cstride;  // channel
     dst += blockIdx.y * c.dst_cstride;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
     const int tid = threadIdx.x;

@@ -330,6 +330,11 @@ hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *gri
                                int K, void *pad, bool merge);
 // static LDS of the sweep kernel (staged chunk, segment tables)
 size_t sweep_static_lds(int dtype);
+// interpolation by column sweeps (the same segments; complex128 plans): K channels
+hipError_t launch_interp_sweep(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                               int K);
+// LDS of the interpolation sweep: a ring of R planes of values and the staged chunk
+size_t interp_sweep_lds(int dtype, int R, int taps);
 // points of one padded column plane
 inline int sweep_plane_cells(int taps) { return (kSweepQ + taps - 1) * (kSweepQ + taps - 1); }
 // The sweep with 2m = 8 and the polynomial window maps one node to a wavefront,

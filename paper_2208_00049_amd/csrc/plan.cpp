@@ -312,6 +312,7 @@ bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q)
         const int q[3] = {q0, kSweepQ, kSweepQ};
         const bool wn = sweep_wave_node(taps, p.window == NFFT_WINDOW_POLY);
         return sweep_ring_bytes(q0 + taps - 1, taps, wn) + sweep_static_lds(p.dtype) <= budget &&
+               interp_sweep_lds(p.dtype, q0 + taps - 1, taps) <= budget &&
                interp_lds(q, 3, taps, cs) <= budget;
     };
     int q0 = 0;

@@ -57,6 +57,7 @@ static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, h
 
 hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
+    if (p.sweep.on && p.dtype == NFFT_C128) return launch_interp_sweep(p, grid, fhat, s, K);
     return p.dtype == NFFT_C64 ? interp_t<float>(p, grid, fhat, s, K)
                                : interp_t<double>(p, grid, fhat, s, K);
 }

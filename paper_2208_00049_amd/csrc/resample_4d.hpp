@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(kOwnerThreads)
     using C = cplx<T>;
     using FP = FixedPoint<T>;
     constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ OwnerStage<T, D, M2> st;
     __shared__ int nb_begin[kOwnerMaxTiles], nb_pre[kOwnerMaxTiles + 1];
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double

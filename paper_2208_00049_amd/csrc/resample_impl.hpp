@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(NT)
     constexpr int NPW = 64 / M2;
     using StageT = Stage<T, D, interp_chunk(D, (int)sizeof(T))>;
     constexpr int CH = StageT::kChunk;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ StageT st;
     C *tile = reinterpret_cast<C *>(smem_raw);
 
@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(NT)
     constexpr int NPW = 64 / M2;
     constexpr int CH = Stage<T, D>::kChunk;
     constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Stage<T, D> st;
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double
 

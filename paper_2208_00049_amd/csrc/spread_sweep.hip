@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     scr += blockIdx.y * sstride;              // channel
     const C *fsorted = scr + sg.sorted_off;
     const double *part = reinterpret_cast<const double *>(scr + sg.part_off);
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     W *acc = reinterpret_cast<W *>(smem_raw);  // [R][Re, Im][PP]
     __shared__ SweepStage<T, CH> st;
     __shared__ int seg_beg[kSweepMaxSegTiles + 1];  // node range of each tile of the segment
@@ -392,6 +392,232 @@ __global__ void __launch_bounds__(256)
     grid[gi] = cmake<C>(sr, si);
 }
 
+// ---- interpolation by column sweeps (step 3 of Algorithm 1) --------------------
+//
+// Used for complex128 plans that spread by column sweeps (3-D 128^3: 0.66 ms
+// against 0.71 ms for the tiled kernel, which reloads every tile's halo; for
+// complex64 the tiled kernel, two workgroups per compute unit, is faster: 0.26
+// against 0.33 ms).  The same columns, segments and tiles as spreading.  The workgroup of a segment
+// keeps the grid planes its tile's nodes read -- planes t_0 Q_0 .. t_0 Q_0 + Q_0 +
+// 2m - 2 of the column's padded cross-section, (16 + 2m - 1)^2 values each, wrapped
+// at the grid's edges -- in a ring in LDS.  While it interpolates tile t_0, the Q_0
+// planes tile t_0 + 1 adds are loaded into registers; afterwards they replace the
+// tile's first Q_0 planes.  Every grid plane of a segment is read from memory once,
+// with its axis-1/2 halo, and the loads overlap the interpolation.
+
+// 512 threads: the complex128 tap loop needs more than the 128 registers a
+// 1024-thread workgroup leaves a thread (complex64, whose tiled kernel is faster
+// and which therefore does not use the sweep, measured 0.33 ms at 512 and 0.36 ms
+// at 1024 threads on the 3-D 128^3 workload).
+template <typename T> constexpr int interp_sweep_threads() { return 512; }
+template <typename T> constexpr int interp_sweep_chunk() { return interp_sweep_threads<T>(); }
+
+template <typename T, int CH> struct InterpStage {
+    int pk[CH];
+    T fr[3][CH];
+    int idx[CH];  // caller's node index
+};
+
+template <typename T, int M2, bool GW>
+__global__ void __launch_bounds__(interp_sweep_threads<T>())
+    k_interp_sweep(const cplx<T> *__restrict__ grid, Geom g, SweepGeom sg,
+                   const NodeRec<T, 3> *__restrict__ nodes, const int *__restrict__ perm,
+                   const int *__restrict__ key_start, const T *__restrict__ coef, int window,
+                   WinParams<T> wp, cplx<T> *__restrict__ fhat, long long gstride, long long fstride) {
+    using C = cplx<T>;
+    constexpr int NT = interp_sweep_threads<T>();
+    constexpr int CH = interp_sweep_chunk<T>();
+    constexpr int P = kSweepQ + M2 - 1, PP = P * P;
+    constexpr int NPW = 64 / M2;
+    constexpr int PF = (8 * PP + NT - 1) / NT;  // prefetched values per thread (Q_0 <= 8)
+    grid += blockIdx.y * gstride;              // channel
+    fhat += blockIdx.y * fstride;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C *ring = reinterpret_cast<C *>(smem_raw);  // [R][PP]
+    __shared__ InterpStage<T, CH> st;
+    __shared__ int seg_beg[kSweepMaxSegTiles + 1];
+    __shared__ int seg_end[kSweepMaxSegTiles + 1];
+
+    const int seg = blockIdx.x;
+    const int col = seg / sg.nsc, kseg = seg - col * sg.nsc;
+    const int t1 = col / g.T[2], t2 = col - t1 * g.T[2];
+    const int tb = kseg * sg.L, nt = sg.L;
+    const int R = sg.R, Q0 = g.Q[0];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int N0 = g.Nt[0], N1 = g.Nt[1], N2 = g.Nt[2];
+
+    // grid offset of point q of the padded cross-section in plane p (unwrapped)
+    auto src = [&](int p, int q) -> long long {
+        const int i = q / P, j = q - i * P;
+        int pp = p >= N0 ? p - N0 : p;
+        int r1 = t1 * kSweepQ + i, r2 = t2 * kSweepQ + j;
+        if (r1 >= N1) r1 -= N1;
+        if (r2 >= N2) r2 -= N2;
+        return ((long long)pp * N1 + r1) * N2 + r2;
+    };
+
+    if (tid < nt) {
+        const int tile = ((tb + tid) * g.T[1] + t1) * g.T[2] + t2;
+        seg_beg[tid] = key_start[tile << 3];
+        seg_end[tid] = key_start[(tile + 1) << 3];
+    }
+    // the first R planes, eight loads per thread in flight
+    {
+        const int p0 = tb * Q0;
+        const int total = R * PP;
+        for (int base = 0; base < total; base += 8 * NT) {
+            C v[8];
+            int dst[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * NT + tid;
+                const int ic = idx < total ? idx : 0;
+                const int kk = ic / PP, q = ic - kk * PP;
+                v[u] = grid[src(p0 + kk, q)];
+                dst[u] = idx < total ? ((p0 + kk) % R) * PP + q : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (dst[u] >= 0) ring[dst[u]] = v[u];
+        }
+    }
+    __syncthreads();
+
+    const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
+    LaneWindow<T, 3, M2> lw;
+    lw.load(coef, li, wp.m);
+
+    auto next_chunk = [&](int &t, int &c0) {
+        c0 += CH;
+        if (c0 < seg_end[t]) return;
+        for (++t; t < nt && seg_beg[t] == seg_end[t]; ++t) {
+        }
+        c0 = t < nt ? seg_beg[t] : 0;
+    };
+    NodeRec<T, 3> rec;
+    int pm = 0;
+    auto load_chunk = [&](int t, int c0) {
+        const int n = min(CH, seg_end[t] - c0);
+        const int k = c0 + (tid < n ? tid : n - 1);
+        rec = nodes[k];
+        pm = perm[k];
+    };
+    int ct = -1, cc0 = 0;
+    {
+        int t = 0;
+        for (; t < nt && seg_beg[t] == seg_end[t]; ++t) {
+        }
+        if (t < nt) {
+            ct = t;
+            cc0 = seg_beg[t];
+            load_chunk(ct, cc0);
+        }
+    }
+
+    for (int t = 0; t < nt; ++t) {
+        // the planes the next tile adds, into registers
+        const int pn = (tb + t) * Q0 + R;
+        const bool more = t + 1 < nt;
+        C pre[PF];
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int idx = u * NT + tid;
+                const int ic = idx < Q0 * PP ? idx : 0;
+                const int kk = ic / PP, q = ic - kk * PP;
+                pre[u] = grid[src(pn + kk, q)];
+            }
+        }
+        while (ct == t) {
+            const int c0 = cc0, n = min(CH, seg_end[t] - c0);
+            if (tid < n) {
+                st.pk[tid] = (rec.o[0] % R) | ((rec.o[1] - t1 * kSweepQ) << 8) |
+                             ((rec.o[2] - t2 * kSweepQ) << 16);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) st.fr[d][tid] = rec.fr[d];
+                st.idx[tid] = pm;
+            }
+            __syncthreads();
+            next_chunk(ct, cc0);
+            if (ct < nt) load_chunk(ct, cc0);
+            else ct = -1;
+            for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
+                const int k = base + grp;
+                const bool valid = grp < NPW && k < n;
+                const int ks = valid ? k : 0;
+                const int pk = st.pk[ks];
+                const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
+                T fr[3], w[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fr[d] = st.fr[d][ks];
+                node_weights<GW, T, 3, M2>(w, lw, fr, (long long)(c0 + ks), li, window, wp);
+                T w0[M2], w1[M2];
+                BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                BcastAll<M2, 0, T>::run(w1, w[1], gbase);
+                // the offsets of the node's M2 ring planes first, so that the tap loop's
+                // reads need no address arithmetic between them
+                const int cell = l1 * P + l2 + li;
+                int po[M2];
+#pragma unroll
+                for (int a = 0; a < M2; ++a) {
+                    const int r = r0 + a;
+                    po[a] = (r >= R ? r - R : r) * PP + cell;
+                }
+                T ar = (T)0, ai = (T)0;
+#pragma unroll
+                for (int a = 0; a < M2; ++a) {
+                    C v[M2];
+#pragma unroll
+                    for (int b = 0; b < M2; ++b) v[b] = ring[po[a] + b * P];
+                    T sr = (T)0, si = (T)0;
+#pragma unroll
+                    for (int b = 0; b < M2; ++b) {
+                        sr = fma(w1[b], v[b].x, sr);
+                        si = fma(w1[b], v[b].y, si);
+                    }
+                    ar = fma(w0[a], sr, ar);
+                    ai = fma(w0[a], si, ai);
+                }
+                ar *= w[2];
+                ai *= w[2];
+                ar = group_sum<M2>(ar, li);
+                ai = group_sum<M2>(ai, li);
+                if (valid && li == 0) fhat[st.idx[ks]] = cmake<C>(ar, ai);
+            }
+            __syncthreads();
+        }
+        if (more) {
+            // the tile's first Q_0 planes are no longer needed: the next tile's take their slots
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int idx = u * NT + tid;
+                if (idx < Q0 * PP) {
+                    const int kk = idx / PP, q = idx - kk * PP;
+                    ring[((pn + kk) % R) * PP + q] = pre[u];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T, int M2>
+hipError_t run_interp_sweep(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                            int K) {
+    const SweepGeom &sg = p.sweep;
+    const size_t shm = (size_t)sg.R * sweep_plane_cells(p.geom.taps) * sizeof(cplx<T>);
+    const bool gw = p.window != NFFT_WINDOW_POLY;
+    auto kern = gw ? k_interp_sweep<T, M2, true> : k_interp_sweep<T, M2, false>;
+    hipError_t e = allow_lds(kern, shm, sizeof(InterpStage<T, interp_sweep_chunk<T>()>) + 1024);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(sg.ncols * sg.nsc, K), dim3(interp_sweep_threads<T>()), shm, s,
+                       (const cplx<T> *)grid,
+                       p.geom, sg, (const NodeRec<T, 3> *)p.nodes, p.perm, p.key_start,
+                       (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
+                       (long long)p.G, (long long)p.M);
+    return hipGetLastError();
+}
+
 template <typename T, int M2>
 hipError_t run_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
                             int K, void *pad, bool merge) {
@@ -437,9 +663,36 @@ hipError_t launch_spread_sweep(const nfft_plan_s &p, const void *fhat, void *gri
                                : sweep_t<double>(p, fhat, grid, s, K, pad, merge);
 }
 
+template <typename T>
+static hipError_t interp_sweep_t(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                                 int K) {
+    switch (p.geom.taps) {
+        case 2: return run_interp_sweep<T, 2>(p, grid, fhat, s, K);
+        case 4: return run_interp_sweep<T, 4>(p, grid, fhat, s, K);
+        case 6: return run_interp_sweep<T, 6>(p, grid, fhat, s, K);
+        case 8: return run_interp_sweep<T, 8>(p, grid, fhat, s, K);
+        case 10: return run_interp_sweep<T, 10>(p, grid, fhat, s, K);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_interp_sweep(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                               int K) {
+    if (p.M == 0) return hipSuccess;
+    return p.dtype == NFFT_C64 ? interp_sweep_t<float>(p, grid, fhat, s, K)
+                               : interp_sweep_t<double>(p, grid, fhat, s, K);
+}
+
 size_t sweep_static_lds(int dtype) {
     return dtype == NFFT_C64 ? sizeof(SweepStage<float, sweep_chunk<float>()>) + 1024
                              : sizeof(SweepStage<double, sweep_chunk<double>()>) + 1024;
+}
+
+size_t interp_sweep_lds(int dtype, int R, int taps) {
+    const size_t ring = (size_t)R * sweep_plane_cells(taps) * (dtype == NFFT_C64 ? 8 : 16);
+    return ring + (dtype == NFFT_C64 ? sizeof(InterpStage<float, interp_sweep_chunk<float>()>)
+                                     : sizeof(InterpStage<double, interp_sweep_chunk<double>()>)) +
+           1024;
 }
 
 }  // namespace nfft
