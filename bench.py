@@ -403,6 +403,27 @@ def bench_multichannel(args, w):
     algo = algorithmic_bytes(dict(w, nodes="radial"), info["Ntilde"], args.dtype)
     dominant = max(st, key=st.get)
     ach = K * algo[dominant] / (st[dominant] * 1e-3) / 1e9
+    # the same K channels in the other precision, on the FP32-rounded nodes and inputs
+    ocdt = torch.complex128 if args.dtype == "c64" else torch.complex64
+    x32 = x.float()
+    p32 = Plan(x32, N, m=args.m, sigma=args.sigma)
+    p64 = Plan(x32.double(), N, m=args.m, sigma=args.sigma)
+    f32, fh32 = f.to(torch.complex64), fh.to(torch.complex64)
+    f64, fh64 = f32.to(torch.complex128), fh32.to(torch.complex128)
+    a32, b32 = p32.forward_many(f32), p32.adjoint_many(fh32)
+    a64, b64 = p64.forward_many(f64), p64.adjoint_many(fh64)
+    po = p64 if args.dtype == "c64" else p32
+    fi, fhi = (f64, fh64) if args.dtype == "c64" else (f32, fh32)
+    fo2 = torch.empty((K, M), dtype=ocdt, device=dev)
+    yo2 = torch.empty((K,) + tuple(N), dtype=ocdt, device=dev)
+    ms_other = timed(lambda: (po.forward_many(fi, out=fo2), po.adjoint_many(fhi, out=yo2)),
+                     max(5, args.steps // 2), 3)
+    rel = lambda a, b: (torch.linalg.norm(a.to(torch.complex128) - b) / torch.linalg.norm(b)).item()
+    other = {"dtype": "f64" if args.dtype == "c64" else "f32", "ms_per_step": round(ms_other, 5),
+             "pts_s": round(K * M / (ms_other * 1e-3), 1),
+             "fwd_rel_l2_fp32_vs_fp64": rel(a32, a64), "adj_rel_l2_fp32_vs_fp64": rel(b32, b64)}
+    p32.close()
+    p64.close()
     return {
         "metric": METRIC, "value": round(K * M / (ms * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -418,6 +439,7 @@ def bench_multichannel(args, w):
         "stages_ms": {k: round(v, 5) for k, v in st.items()},
         "single_channel_calls_ms_per_step": round(ms_single, 5),
         "speedup_vs_single_channel_calls": round(ms_single / ms, 2),
+        "other_precision": other,
         "cpu_baseline": None,
     }
 
@@ -457,6 +479,36 @@ def bench_grad(args, w):
         loss = (nfft_ad(xr, fr, plan=plan) - y).abs().pow(2).sum()
         loss.backward()
     ms = timed(step, args.steps, args.warmup)
+
+    # the same step in both precisions on the FP32-rounded nodes and data: gradients of the
+    # FP32 step against those of the FP64 one, and the other precision's step time
+    def grads(dt):
+        rdt, c = (torch.float32, torch.complex64) if dt == "c64" else (torch.float64, torch.complex128)
+        xs = xt.float().to(rdt)
+        p = Plan(xs, N, m=args.m, sigma=args.sigma)
+        xg = xs.clone().requires_grad_(True)
+        fg = f.to(torch.complex64).to(c).clone().requires_grad_(True)
+        yy = y.to(torch.complex64).to(c)
+
+        def one():
+            xg.grad = None
+            fg.grad = None
+            loss = (nfft_ad(xg, fg, plan=p) - yy).abs().pow(2).sum()
+            loss.backward()
+            return loss
+        loss = one()
+        t = timed(one, max(5, args.steps // 2), 3) if dt != args.dtype else ms
+        out = (loss.item(), fg.grad.clone(), xg.grad.clone(), t)
+        p.close()
+        return out
+    l32, gf32, gx32, t32 = grads("c64")
+    l64, gf64, gx64, t64 = grads("c128")
+    rel = lambda a, b: (torch.linalg.norm(a.to(b.dtype) - b) / torch.linalg.norm(b)).item()
+    other = {"dtype": "f64" if args.dtype == "c64" else "f32",
+             "ms_per_step": round(t64 if args.dtype == "c64" else t32, 5),
+             "loss_rel_fp32_vs_fp64": abs(l32 - l64) / abs(l64),
+             "grad_f_rel_l2_fp32_vs_fp64": rel(gf32, gf64),
+             "grad_x_rel_l2_fp32_vs_fp64": rel(gx32, gx64)}
     return {
         "metric": METRIC, "value": round(M / (ms * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -466,6 +518,7 @@ def bench_grad(args, w):
                    "sigma": args.sigma, "nodes": "radial 256 x 256, radial jitter U(+-0.5/Ntilde)",
                    "step": "forward, loss, backward (grad f, grad x)"},
         "plan_ms": round(plan_ms, 2),
+        "other_precision": other,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -483,7 +536,10 @@ def bench_batch(args, w):
     specs = wl.batched_specs(w["count"], config=w["config"])
     plans, fs, fhs, fos, yos = [], [], [], [], []
     for b, (N, M) in enumerate(specs):
-        x = torch.tensor(wl.uniform_nodes(M, 2, config=3, stream=100 + b), dtype=xdt, device=dev)
+        # FP32-rounded nodes in both precisions, so that the two batches differ only by
+        # their arithmetic
+        x = torch.tensor(wl.uniform_nodes(M, 2, config=3, stream=100 + b), dtype=torch.float32,
+                         device=dev).to(xdt)
         plans.append(Plan(x, N, m=args.m, sigma=args.sigma))
         fs.append(torch.tensor(wl.cn01(N, config=3, stream=300 + b), dtype=cdt, device=dev))
         fhs.append(torch.tensor(wl.cn01((M,), config=3, stream=500 + b), dtype=cdt, device=dev))
@@ -498,6 +554,36 @@ def bench_batch(args, w):
             p.adjoint(fh, out=yo)
     ms_eager = timed(eager, max(2, args.steps // 5), 2)
     total = sum(M for _, M in specs)
+    # the batch in the other precision (FP32-rounded nodes and data for both): step time, and
+    # the FP32 results against the FP64 ones over all transforms (rel-l2 of the concatenation)
+    ocdt = torch.complex128 if args.dtype == "c64" else torch.complex64
+    oxdt = torch.float64 if args.dtype == "c64" else torch.float32
+    oplans, ofs, ofhs, ofos, oyos = [], [], [], [], []
+    for p, f, fh, fo, yo in zip(plans, fs, fhs, fos, yos):
+        xb = torch.tensor(wl.uniform_nodes(p.M, 2, config=3, stream=100 + len(oplans)),
+                          dtype=torch.float32, device=dev).to(oxdt)
+        oplans.append(Plan(xb, p.N, m=args.m, sigma=args.sigma))
+        ofs.append(f.to(torch.complex64).to(ocdt))
+        ofhs.append(fh.to(torch.complex64).to(ocdt))
+        ofos.append(torch.empty(p.M, dtype=ocdt, device=dev))
+        oyos.append(torch.empty(p.N, dtype=ocdt, device=dev))
+    obatch = Batch(oplans, nstreams=8)
+    ms_other = timed(lambda: (obatch.forward(ofs, ofos), obatch.adjoint(ofhs, oyos)),
+                     max(5, args.steps // 2), 3)
+    batch.forward(fs, fos)
+    batch.adjoint(fhs, yos)
+    torch.cuda.synchronize()
+    (f32s, y32s, f64s, y64s) = ((fos, yos, ofos, oyos) if args.dtype == "c64" else
+                                (ofos, oyos, fos, yos))
+    cat = lambda ts: torch.cat([t.reshape(-1).to(torch.complex128) for t in ts])
+    rel = lambda a, b: (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+    other = {"dtype": "f64" if args.dtype == "c64" else "f32", "ms_per_step": round(ms_other, 5),
+             "pts_s": round(total / (ms_other * 1e-3), 1),
+             "fwd_rel_l2_fp32_vs_fp64": rel(cat(f32s), cat(f64s)),
+             "adj_rel_l2_fp32_vs_fp64": rel(cat(y32s), cat(y64s))}
+    obatch.close()
+    for p in oplans:
+        p.close()
     return {
         "metric": METRIC, "value": round(total / (ms * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
@@ -509,6 +595,7 @@ def bench_batch(args, w):
         "roofline": None,
         "eager_calls_ms_per_step": round(ms_eager, 5),
         "speedup_vs_eager_calls": round(ms_eager / ms, 2),
+        "other_precision": other,
         "cpu_baseline": None,
     }
 
@@ -690,15 +777,20 @@ def main():
     per_tap = 4 if (args.dtype == "c128" and not sweep_f64) else 2
     atomics = w["M"] * taps ** w["D"] * per_tap
     lds_op = "ds_add_f64" if sweep_f64 else "ds_add_u64"
-    lds_peak = calibrate_lds(lds_op, 2)
+    # the roof is the unit's best rate (consecutive words, no bank conflicts); the rate for
+    # rows of eight words at random starts (one instruction of the padded-tile kernels) is
+    # reported beside it
+    lds_peak = calibrate_lds(lds_op, 0)
+    lds_rows = calibrate_lds(lds_op, 2)
     spread_ms = b2b.get("spread", avg_ms.get("spread"))
     lds_roof = None
     if spread_ms:
         rate = atomics / (spread_ms * 1e-3)
         lds_roof = {"kernel": "spread", "bound": "lds_atomic", "atomic_lane_ops": atomics,
                     "op": lds_op,
-                    "peak_source": "%s, rows of 8 consecutive words, measured in this run "
+                    "peak_source": "%s on consecutive words, measured in this run "
                                    "(python bench.py --lds-calibrate)" % lds_op,
+                    "rows_of_8_rate": round(lds_rows / 1e12, 4),
                     "achieved": round(rate / 1e12, 4), "peak": round(lds_peak / 1e12, 4),
                     "unit": "T lane-ops/s", "frac": round(rate / lds_peak, 4)}
     fwd_fft_ms = sum(v for k, v in avg_ms.items() if k.startswith("fwd_"))
