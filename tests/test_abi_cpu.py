@@ -122,3 +122,13 @@ def test_batch_and_tuner_argument_errors(lib):
                                       None, 0, None, ctypes.byref(ms)) == -1
     assert lib.nfft_strerror(-5).decode() == "node coordinate is NaN or infinite"
     assert lib.nfft_strerror(12345).decode() == "unknown error"
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="checks the behaviour without a GPU")
+def test_valid_plan_without_device_is_a_hip_error(lib):
+    """Valid arguments pass validation; the first HIP call then fails (no device) and the
+    call returns NFFT_ERR_HIP with the handle untouched."""
+    h = ctypes.c_void_p()
+    N = (ctypes.c_int64 * 3)(32, 32, 32)
+    rc = lib.nfft_plan_create(ctypes.byref(h), 3, N, 10, FAKE, 4, 2.0, 1, None)
+    assert rc == -4 and h.value is None
