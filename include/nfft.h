@@ -220,21 +220,42 @@ int nfft_forward_deriv(nfft_plan_t p, const void *f, void *dfhat, void *stream);
 int nfft_node_grad(nfft_plan_t p, const void *a, const void *dfhat, void *grad_x, void *stream);
 
 /*
- * Batches of independent transforms (different plans, sizes and node sets),
- * run as one HIP graph.  nfft_batch_create takes n distinct plans (a plan may
- * appear once: its grid serves one transform at a time) and the number of
- * streams (1..16) over which the transforms' kernel chains are spread inside
- * the graph.  nfft_batch_forward / nfft_batch_adjoint take host arrays of n
- * device pointers (in[i], out[i] as for nfft_forward / nfft_adjoint of plan i)
- * and launch the graph on `stream`; the graph is captured on the first call
- * and again whenever a pointer differs from the previous call's.  The plans
- * must outlive the batch; their per-stage timing is not recorded in batch
- * calls.  nfft_batch_destroy synchronises the device.
+ * Batches of independent transforms (different plans, sizes and node sets:
+ * the paper's plan/apply interface, section "Implementation", applied to many
+ * plans at once; each transform is Algorithm 1 / Algorithm 2 of its plan).
+ * nfft_batch_create takes n distinct plans (a plan may appear once: its grid
+ * serves one transform at a time) and a stream count (1..16).
+ *
+ * Fused mode: when the plans share the complex type, D <= 3, the stencil
+ * width, the polynomial window and the padded-tile spreading (not the 3-D
+ * column sweeps), every stage of the transform chain -- each FFT pass, the
+ * interpolation, the spreading and its halo merge -- is ONE kernel launch over
+ * the work of all n transforms (2-D: three launches per direction; 1-D: two /
+ * three; 3-D: four / five).  The launches of a direction are captured into a
+ * HIP graph on the first call of that direction and replayed; results equal
+ * those of the plans' own nfft_forward / nfft_adjoint calls bit for bit.
+ * Otherwise each transform's kernel chain is captured into one graph over up
+ * to `nstreams` streams (recaptured whenever a pointer differs from the
+ * previous call's).
+ *
+ * nfft_batch_forward / nfft_batch_adjoint take host arrays of n device
+ * pointers (in[i], out[i] as for nfft_forward / nfft_adjoint of plan i) and
+ * launch on `stream`.  When a pointer differs from the direction's previous
+ * call the fused mode drains `stream` and rewrites its device pointer table
+ * (a synchronous copy); with unchanged pointers a call only launches.  Calls of
+ * one batch must not overlap (the plans' grids are shared).  The plans must
+ * outlive the batch; their per-stage timing is not recorded in batch calls.
+ * nfft_batch_info reports the mode (fused: 1) and, in fused mode, the kernel
+ * launches per forward and per adjoint call (NULL outputs are skipped).
+ * nfft_batch_destroy synchronises the device.  Errors: NFFT_ERR_ARG (NULL or
+ * repeated plans, NULL pointers where the plan needs data), NFFT_ERR_NOMEM,
+ * NFFT_ERR_HIP.
  */
 typedef struct nfft_batch_s *nfft_batch_t;
 int nfft_batch_create(nfft_batch_t *out, int n, const nfft_plan_t *plans, int nstreams);
 int nfft_batch_forward(nfft_batch_t b, const void *const *f, void *const *fhat, void *stream);
 int nfft_batch_adjoint(nfft_batch_t b, const void *const *fhat, void *const *y, void *stream);
+int nfft_batch_info(nfft_batch_t b, int *fused, int *launches_forward, int *launches_adjoint);
 int nfft_batch_destroy(nfft_batch_t b);
 
 /*

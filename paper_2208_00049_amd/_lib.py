@@ -35,7 +35,7 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
            "nfft_batch_create", "nfft_batch_forward", "nfft_batch_adjoint", "nfft_batch_destroy",
            "nfft_plan_create_tuned", "nfft_forward_deriv", "nfft_node_grad", "nfft_strerror",
            "nfft_plan_window_peak", "nfft_calibrate_lds", "nfft_forward_many_noalloc",
-           "nfft_plan_spread"]
+           "nfft_plan_spread", "nfft_batch_info"]
 SPREAD = {"auto": 0, "tiled": 1, "sweep": 2}
 NFFT_NUM_STAGES = 8
 LDS_OPS = {"ds_add_u32": 0, "ds_add_u64": 1, "ds_add_f32": 2, "ds_add_f64": 3,
@@ -100,6 +100,8 @@ def load():
     lib.nfft_batch_adjoint.argtypes = [vp, ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_void_p), vp]
     lib.nfft_batch_destroy.argtypes = [vp]
+    lib.nfft_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]
     lib.nfft_plan_create_tuned.argtypes = [plan_p, ctypes.c_int, i64p, ctypes.c_int64, vp,
                                            ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                            ctypes.POINTER(Options), ctypes.c_int, vp,

@@ -16,8 +16,9 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "runtime.cpp", "precompute.hip", "binsort.hip", "fft.hip", "resample.hip",
-           "calibrate.hip", "spread_sweep.hip"]
+# the longest compilations first (they run in parallel)
+SOURCES = ["resample.hip", "batch.hip", "spread_sweep.hip", "fft.hip", "plan.cpp", "runtime.cpp",
+           "precompute.hip", "binsort.hip", "calibrate.hip"]
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -18,7 +18,6 @@
 
 namespace nfft {
 
-constexpr int kLinePad = 1;  // complex values of padding after each LDS line
 
 // Copy the twiddle table (L values) into LDS: every thread issues its loads,
 // up to eight at a time, before it writes any of them.
@@ -190,10 +189,11 @@ __device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, 
 
 // Strided axis pass: the workgroup owns B consecutive inner columns of one outer
 // position; rows are read and written B complex values at a time.
+// bx: the workgroup's block among the nbx blocks of this grid's pass.
 template <typename T, int DIR, bool POW2>
-__global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl, AxisPass a) {
+__device__ inline void fft_strided_body(cplx<T> *grid, const FftLine &fl, const AxisPass &a, int bx,
+                                        int nbx) {
     using C = cplx<T>;
-    grid += blockIdx.y * a.cstride;  // channel
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
     const int lgB = __ffs(B) - 1;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nchunk = (int)((a.inner + B - 1) / B);
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int blk = xcd_block(bx, nbx);
     const int o = blk / nchunk;
     long long obase = 0;
     {
@@ -267,6 +267,11 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
     }
 }
 
+template <typename T, int DIR, bool POW2>
+__global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl, AxisPass a) {
+    fft_strided_body<T, DIR, POW2>(grid + blockIdx.y * a.cstride, fl, a, blockIdx.x, gridDim.x);
+}
+
 // Axis-0 pass of the adjoint (D >= 2, all Nt_0 rows in, the band of I_N out)
 // whose input is not the grid but the padded tiles of spreading: grid point
 // (c_0, c') is the sum, over the source tiles that cover it, of their work
@@ -274,11 +279,11 @@ __global__ void __launch_bounds__(1024) k_fft_strided(cplx<T> *grid, FftLine fl,
 // the merge kernel).  The B columns of a workgroup lie in one tile column, so
 // the item ranges of the tiles along axis 0 are read into LDS once.
 template <typename T, int D, bool POW2>
-__global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftLine fl, AxisPass a,
-                                                             PadSource ps) {
+__device__ inline void fft_axis0_from_pad_body(cplx<T> *grid, const FftLine &fl, const AxisPass &a,
+                                               const PadSource &ps, const cplx<T> *pad, int bx,
+                                               int nbx) {
     constexpr int DIR = +1;  // the adjoint's first pass
     using C = cplx<T>;
-    grid += blockIdx.y * a.cstride;  // channel
     constexpr int ER = 1 << (D - 1);  // shifts along the axes after axis 0
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
@@ -286,7 +291,7 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
     const int B = a.lines_per_block;  // a power of two dividing Q_{D-1}
     const int lgB = __ffs(B) - 1;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int blk = xcd_block(bx, nbx);
     const long long inner = a.inner;
     const int i0 = blk * B;
     const Geom &g = ps.g;
@@ -328,7 +333,6 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
     if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, nthr);
     __syncthreads();
 
-    const C *pad = (const C *)ps.pad + blockIdx.y * ps.cstride;
     const float rq0 = 1.0f / (float)g.Q[0];
     const int bb = tid & (B - 1);  // fixed per thread: nthr is a multiple of B
     int al[D];                     // offsets of this thread's column, axes 1..D-1
@@ -404,6 +408,14 @@ __global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftL
         const int row = a.out_band_N ? band_pos(r, a.out_band_N, L) : r;
         if (i0 + cb < inner) grid[(long long)row * inner + i0 + cb] = lds[cb * LP + row];
     }
+}
+
+template <typename T, int D, bool POW2>
+__global__ void __launch_bounds__(1024) k_fft_axis0_from_pad(cplx<T> *grid, FftLine fl, AxisPass a,
+                                                             PadSource ps) {
+    fft_axis0_from_pad_body<T, D, POW2>(grid + blockIdx.y * a.cstride, fl, a, ps,
+                                        (const cplx<T> *)ps.pad + blockIdx.y * ps.cstride,
+                                        blockIdx.x, gridDim.x);
 }
 
 // Axis-0 pass of the 3-D adjoint whose input is the scratch of the column
@@ -539,18 +551,17 @@ template <typename T> struct DecPtrs {
     const T *d[kMaxD];  // resampling-correction factors per axis
 };
 
+// bx: the workgroup's block; ch: its channel (the derivative channels use it).
 template <typename T, int DIR, bool POW2>
-__global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T> *dst, FftLine fl,
-                                                     ContigPass c, DecPtrs<T> dec) {
+__device__ inline void fft_contig_body(const cplx<T> *src, cplx<T> *dst, const FftLine &fl,
+                                       const ContigPass &c, const DecPtrs<T> &dec, int bx, int ch) {
     using C = cplx<T>;
-    src += blockIdx.y * c.src_cstride;  // channel
-    dst += blockIdx.y * c.dst_cstride;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C *lds = reinterpret_cast<C *>(smem_raw);
     const int L = fl.L, LP = L + kLinePad;
     const int tid = threadIdx.x;
     const int b = tid / fl.tpl, t = tid % fl.tpl;
-    const int line_id = blockIdx.x * c.lines_per_block + b;
+    const int line_id = bx * c.lines_per_block + b;
     const bool active = b < c.lines_per_block && line_id < c.nlines;
     C *line = lds + (b < c.lines_per_block ? b : 0) * LP;
     C *twl = lds + c.lines_per_block * LP;  // twiddle table after the lines (when it fits)
@@ -579,8 +590,8 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     frow *= c.N[D - 1];
     // derivative channels (mode 1): channel d multiplies f by -2 pi i n_d
     const T twopi = (T)6.283185307179586476925;
-    if (c.deriv && (int)blockIdx.y < D - 1) {
-        const int d = blockIdx.y;
+    if (c.deriv && ch < D - 1) {
+        const int d = ch;
         fac *= (T)(iv[d] - c.N[d] / 2) * twopi;
     }
     const int Nl = c.N[D - 1];
@@ -601,7 +612,7 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
                 const int rr = r >= 0 ? r : 0;
                 const C x = src[frow + rr];
                 T s = fac * declast[rr];
-                if (c.deriv && blockIdx.y == D - 1) s *= (T)(rr - Nl / 2) * twopi;
+                if (c.deriv && ch == D - 1) s *= (T)(rr - Nl / 2) * twopi;
                 C y = cscale(x, s);
                 if (c.deriv) y = cmake<C>(y.y, -y.x);  // times -i
                 v[j] = r >= 0 ? y : cmake<C>((T)0, (T)0);
@@ -643,13 +654,11 @@ __global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T>
     }
 }
 
-// The twiddle table goes to LDS when the pass's lines leave room for it.
-inline FftLine with_lds_table(const nfft_plan_s &p, const FftLine &fl, int B, size_t cs, size_t &shm) {
-    FftLine out = fl;
-    const size_t lines = (size_t)B * (fl.L + kLinePad) * cs;
-    out.tw_lds = lines + (size_t)fl.L * cs <= (size_t)p.lds_limit;
-    shm = lines + (out.tw_lds ? (size_t)fl.L * cs : 0);
-    return out;
+template <typename T, int DIR, bool POW2>
+__global__ void __launch_bounds__(1024) k_fft_contig(const cplx<T> *src, cplx<T> *dst, FftLine fl,
+                                                     ContigPass c, DecPtrs<T> dec) {
+    fft_contig_body<T, DIR, POW2>(src + blockIdx.y * c.src_cstride, dst + blockIdx.y * c.dst_cstride,
+                                  fl, c, dec, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -690,6 +699,94 @@ static hipError_t fft_contig_t(const nfft_plan_s &p, const void *src, void *dst,
     hipLaunchKernelGGL(kern, g, dim3(B * fl.tpl), shm, s, (const cplx<T> *)src,
                        (cplx<T> *)dst, fl, c, dec);
     return hipGetLastError();
+}
+
+// ---- fused batches: one launch per pass for the transforms of a batch ----------
+
+template <typename T, int DIR, bool POW2>
+__global__ void __launch_bounds__(1024)
+    k_fft_contig_batch(const BxFft *__restrict__ tab, const int *__restrict__ b2e,
+                       const void *const *__restrict__ in, void *const *__restrict__ out) {
+    const int e = b2e[blockIdx.x];
+    if (e < 0) return;
+    const BxFft &x = tab[e];
+    DecPtrs<T> dec;
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d) dec.d[d] = (const T *)x.dec[d];
+    const cplx<T> *src = (const cplx<T> *)(x.src_user ? in[x.t] : x.src);
+    cplx<T> *dst = (cplx<T> *)(x.dst_user ? out[x.t] : x.grid);
+    fft_contig_body<T, DIR, POW2>(src, dst, x.fl, x.c, dec, blockIdx.x - x.start, 0);
+}
+
+template <typename T, int DIR, bool POW2>
+__global__ void __launch_bounds__(1024)
+    k_fft_strided_batch(const BxFft *__restrict__ tab, const int *__restrict__ b2e) {
+    const int e = b2e[blockIdx.x];
+    if (e < 0) return;
+    const BxFft &x = tab[e];
+    fft_strided_body<T, DIR, POW2>((cplx<T> *)x.grid, x.fl, x.a, blockIdx.x - x.start, x.nblk);
+}
+
+template <typename T, int D, bool POW2>
+__global__ void __launch_bounds__(1024)
+    k_fft_axis0_from_pad_batch(const BxFft *__restrict__ tab, const int *__restrict__ b2e) {
+    const int e = b2e[blockIdx.x];
+    if (e < 0) return;
+    const BxFft &x = tab[e];
+    fft_axis0_from_pad_body<T, D, POW2>((cplx<T> *)x.grid, x.fl, x.a, x.ps,
+                                        (const cplx<T> *)x.ps.pad, blockIdx.x - x.start, x.nblk);
+}
+
+template <typename K> static hipError_t allow_shm(K kern, size_t shm) {
+    if (shm <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T, int DIR, bool POW2>
+static hipError_t fft_batch_t(int kind, int D, const BxFft *tab, const int *b2e,
+                              const void *const *in, void *const *out, int nblocks, int nthreads,
+                              size_t shm, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (kind == kBxContig) {
+        auto kern = k_fft_contig_batch<T, DIR, POW2>;
+        e = allow_shm(kern, shm);
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), shm, s, tab, b2e, in, out);
+    } else if (kind == kBxStrided) {
+        auto kern = k_fft_strided_batch<T, DIR, POW2>;
+        e = allow_shm(kern, shm);
+        if (e == hipSuccess) hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), shm, s, tab, b2e);
+    } else if (DIR > 0 && (D == 2 || D == 3)) {
+        auto kern = D == 2 ? k_fft_axis0_from_pad_batch<T, 2, POW2> : k_fft_axis0_from_pad_batch<T, 3, POW2>;
+        e = allow_shm(kern, shm);
+        if (e == hipSuccess) hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), shm, s, tab, b2e);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t fft_batch_dir(int kind, int D, int dir, bool pow2, const BxFft *tab,
+                                const int *b2e, const void *const *in, void *const *out,
+                                int nblocks, int nthreads, size_t shm, hipStream_t s) {
+    if (dir < 0)
+        return pow2 ? fft_batch_t<T, -1, true>(kind, D, tab, b2e, in, out, nblocks, nthreads, shm, s)
+                    : fft_batch_t<T, -1, false>(kind, D, tab, b2e, in, out, nblocks, nthreads, shm, s);
+    return pow2 ? fft_batch_t<T, 1, true>(kind, D, tab, b2e, in, out, nblocks, nthreads, shm, s)
+                : fft_batch_t<T, 1, false>(kind, D, tab, b2e, in, out, nblocks, nthreads, shm, s);
+}
+
+hipError_t launch_fft_batch(int kind, int dtype, int D, int dir, bool pow2, const BxFft *tab,
+                            const int *b2e, const void *const *in, void *const *out, int nblocks,
+                            int nthreads, size_t shm, hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+    if (nthreads < 1 || nthreads > 1024) return hipErrorInvalidValue;
+    return dtype == NFFT_C64
+               ? fft_batch_dir<float>(kind, D, dir, pow2, tab, b2e, in, out, nblocks, nthreads, shm, s)
+               : fft_batch_dir<double>(kind, D, dir, pow2, tab, b2e, in, out, nblocks, nthreads, shm, s);
 }
 
 hipError_t launch_fft_axis(const nfft_plan_s &p, void *grid, const AxisPass &a, hipStream_t s) {

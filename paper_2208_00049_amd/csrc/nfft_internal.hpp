@@ -310,6 +310,74 @@ hipError_t launch_fft_axis0_from_sweep(const nfft_plan_s &p, void *grid, const A
 hipError_t launch_fft_contig(const nfft_plan_s &p, const void *src, void *dst, const ContigPass &c,
                              hipStream_t s);
 
+// ---- fused batches (runtime.cpp): one launch per stage for all transforms ----
+//
+// Block b of a stage launch serves entry b2e[b] of the stage's table (-1: an idle
+// block; every entry's range starts at a multiple of the XCD count, so that the
+// kernels' XCD-aware renumbering of their blocks holds inside the range) as block
+// b - start of that entry's own pass.  `t` indexes the caller's pointer arrays.
+struct BxFft {
+    int t;
+    int start, nblk;
+    int src_user, dst_user;  // last-axis pass: read the caller's input / write its output
+    const void *src;         // last-axis pass: the source when it is not the caller's
+    void *grid;              // the plan's grid (a strided pass's data, a last-axis destination)
+    FftLine fl;
+    ContigPass c;
+    AxisPass a;
+    PadSource ps;            // first adjoint pass with the halo merge (2-D)
+    const void *dec[kMaxD];  // resampling-correction factors
+};
+struct BxResample {
+    int t;
+    int start, nblk;
+    void *buf;               // interpolation: the plan's grid; spreading, merge: its padded tiles
+    void *grid;              // merge: the plan's grid
+    Geom g;
+    const void *nodes;
+    const int *perm;
+    const int4 *subs;
+    const int *tile_sub;
+    const void *coef;
+    int window;
+    int m;
+    double beta[kMaxD];
+    double inv_peak[kMaxD];
+    const void *tab;
+    long long S;
+    double wmax_prod;
+};
+enum BatchFftKind { kBxContig = 0, kBxStrided = 1, kBxFromPad = 2 };
+enum BatchResampleKind { kBxInterp = 0, kBxSpread = 1, kBxMerge = 2 };
+// fft.hip / resample.hip: one stage launch over nblocks blocks of nthreads threads
+hipError_t launch_fft_batch(int kind, int dtype, int D, int dir, bool pow2, const BxFft *tab,
+                            const int *b2e, const void *const *in, void *const *out, int nblocks,
+                            int nthreads, size_t shm, hipStream_t s);
+hipError_t launch_resample_batch(int kind, int dtype, int D, int taps, bool gw, const BxResample *tab,
+                                 const int *b2e, const void *const *in, void *const *out,
+                                 int nblocks, size_t shm, hipStream_t s);
+// threads of the resampling kernels' workgroups (256, 512 in 3-D)
+int resample_block_threads(int D);
+
+constexpr int kLinePad = 1;  // complex values of padding after each LDS line of an FFT pass
+// The twiddle table goes to LDS when the pass's B lines leave room for it; shm: the
+// pass's dynamic LDS (lines and table).
+inline FftLine with_lds_table(const nfft_plan_s &p, const FftLine &fl, int B, size_t cs, size_t &shm) {
+    FftLine out = fl;
+    const size_t lines = (size_t)B * (fl.L + kLinePad) * cs;
+    out.tw_lds = lines + (size_t)fl.L * cs <= (size_t)p.lds_limit;
+    shm = lines + (out.tw_lds ? (size_t)fl.L * cs : 0);
+    return out;
+}
+
+// plan.cpp: the FFT passes of a plan.  contig_pass: the last-axis pass (mode 1: f ->
+// grid with the resampling correction and zero padding; mode 2: grid -> y with crop
+// and correction; mode 0: plain grid -> grid).  axis_pass: the strided pass along
+// axis a < D - 1, direction dir; pruned: the forward loads, the adjoint stores,
+// only the band rows of I_N, and the axes before a hold only their band.
+ContigPass contig_pass(const nfft_plan_s &p, int mode, int dir, int K);
+AxisPass axis_pass(const nfft_plan_s &p, int a, int dir, int K, bool pruned);
+
 // resample.hip
 // out[j*D + d] = Re(conj(a_j) v[d*M + j]) for the plan's M nodes
 hipError_t launch_node_grad(const nfft_plan_s &p, const void *a, const void *v, void *out,

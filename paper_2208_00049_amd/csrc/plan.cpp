@@ -442,6 +442,54 @@ int lines_per_block_strided(const FftLine &fl, size_t cs, int64_t inner) {
 }  // namespace
 
 namespace nfft {
+
+ContigPass contig_pass(const nfft_plan_s &p, int mode, int dir, int K) {
+    const int D = p.D;
+    ContigPass c{};
+    c.K = K;
+    c.mode = mode;
+    c.D = D;
+    c.dir = dir;
+    c.src_cstride = mode == 1 ? p.NN : p.G;
+    c.dst_cstride = mode == 2 ? p.NN : p.G;
+    c.nlines = 1;
+    for (int d = 0; d < kMaxD; ++d) {
+        c.N[d] = (int)p.N[d];
+        c.Nt[d] = (int)p.Nt[d];
+    }
+    for (int d = 0; d < D - 1; ++d) {
+        c.outer_len[d] = mode == 0 ? (int)p.Nt[d] : (int)p.N[d];
+        c.outer_band[d] = mode == 0 ? 0 : 1;
+        c.nlines *= c.outer_len[d];
+    }
+    c.lines_per_block = lines_per_block_contig(p.line[D - 1], csize(p.dtype));
+    return c;
+}
+
+AxisPass axis_pass(const nfft_plan_s &p, int a, int dir, int K, bool pruned) {
+    AxisPass ap{};
+    ap.axis = a;
+    ap.inner = 1;
+    for (int d = a + 1; d < p.D; ++d) ap.inner *= (int)p.Nt[d];
+    ap.outer_len = 1;
+    for (int d = 0; d < a; ++d) {
+        ap.outer_n[d] = pruned ? (int)p.N[d] : (int)p.Nt[d];
+        ap.outer_band[d] = pruned ? 1 : 0;
+        ap.outer_Nt[d] = (int)p.Nt[d];
+        long long st = 1;
+        for (int e = d + 1; e < p.D; ++e) st *= p.Nt[e];
+        ap.outer_stride[d] = st;
+        ap.outer_len *= ap.outer_n[d];
+    }
+    ap.in_band_N = pruned && dir < 0 ? (int)p.N[a] : 0;
+    ap.out_band_N = pruned && dir > 0 ? (int)p.N[a] : 0;
+    ap.dir = dir;
+    ap.K = K;
+    ap.cstride = p.G;
+    ap.lines_per_block = lines_per_block_strided(p.line[a], csize(p.dtype), ap.inner);
+    return ap;
+}
+
 int validate_plan_args(int D, const int64_t *N, int64_t M, const void *x, int m, double sigma,
                        int dtype, const nfft_options *opts) {
     return validate(D, N, M, x, m, sigma, dtype, opts);
@@ -713,47 +761,15 @@ struct StageTimer {
     }
 };
 
-// forward FFT with the resampling correction fused into the first (last-axis)
-// pass; K channels: f at stride prod(N), grids at stride G
-// Outer structure of the strided pass along axis a: the axes before it, each
-// either its band of I_N (band = true) or its whole oversampled length.
-void set_outer(AxisPass &ap, const nfft_plan_s &p, int a, bool band) {
-    ap.outer_len = 1;
-    for (int d = 0; d < a; ++d) {
-        ap.outer_n[d] = band ? (int)p.N[d] : (int)p.Nt[d];
-        ap.outer_band[d] = band ? 1 : 0;
-        ap.outer_Nt[d] = (int)p.Nt[d];
-        long long st = 1;
-        for (int e = d + 1; e < p.D; ++e) st *= p.Nt[e];
-        ap.outer_stride[d] = st;
-        ap.outer_len *= ap.outer_n[d];
-    }
-}
-
+// Forward FFT with the resampling correction fused into the first (last-axis)
+// pass; K channels: f at stride prod(N), grids at stride G.
 // deriv: K = D channels from one f, channel d with coefficients -2 pi i n_d f_n
 hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, hipStream_t s,
                        bool deriv = false) {
     const int D = p.D;
-    const size_t cs = csize(p.dtype);
-    ContigPass c{};
-    c.K = K;
+    ContigPass c = contig_pass(p, 1, -1, K);
     c.deriv = deriv ? 1 : 0;
-    c.src_cstride = deriv ? 0 : p.NN;
-    c.dst_cstride = p.G;
-    c.mode = 1;
-    c.D = D;
-    c.dir = -1;
-    c.nlines = 1;
-    for (int d = 0; d < kMaxD; ++d) {
-        c.N[d] = (int)p.N[d];
-        c.Nt[d] = (int)p.Nt[d];
-    }
-    for (int d = 0; d < D - 1; ++d) {
-        c.outer_len[d] = (int)p.N[d];
-        c.outer_band[d] = 1;
-        c.nlines *= (int)p.N[d];
-    }
-    c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    if (deriv) c.src_cstride = 0;
     hipError_t e;
     {
         StageTimer t(p, 0, s);
@@ -761,17 +777,7 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, h
     }
     if (e != hipSuccess) return e;
     for (int a = D - 2; a >= 0; --a) {
-        AxisPass ap{};
-        ap.axis = a;
-        ap.inner = 1;
-        for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
-        set_outer(ap, p, a, true);  // the axes before a hold only their band rows
-        ap.in_band_N = (int)p.N[a];
-        ap.out_band_N = 0;
-        ap.dir = -1;
-        ap.K = K;
-        ap.cstride = p.G;
-        ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
+        const AxisPass ap = axis_pass(p, a, -1, K, true);
         {
             StageTimer t(p, a == 0 ? 2 : 1, s);
             e = launch_fft_axis(p, grid, ap, s);
@@ -787,19 +793,8 @@ hipError_t forward_fft(const nfft_plan_s &p, const void *f, void *grid, int K, h
 hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pad, int K,
                        hipStream_t s, bool from_pad) {
     const int D = p.D;
-    const size_t cs = csize(p.dtype);
     for (int a = 0; a <= D - 2; ++a) {
-        AxisPass ap{};
-        ap.axis = a;
-        ap.inner = 1;
-        for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
-        set_outer(ap, p, a, true);  // the axes before a were cropped to their band
-        ap.in_band_N = 0;
-        ap.out_band_N = (int)p.N[a];
-        ap.dir = +1;
-        ap.K = K;
-        ap.cstride = p.G;
-        ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
+        AxisPass ap = axis_pass(p, a, +1, K, true);
         const bool merge_here = from_pad && a == 0;
         if (merge_here)  // the workgroup's columns must lie in one tile column
             while (p.geom.Q[D - 1] % ap.lines_per_block) ap.lines_per_block /= 2;
@@ -812,24 +807,7 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pa
         }
         if (e != hipSuccess) return e;
     }
-    ContigPass c{};
-    c.K = K;
-    c.src_cstride = p.G;
-    c.dst_cstride = p.NN;
-    c.mode = 2;
-    c.D = D;
-    c.dir = +1;
-    c.nlines = 1;
-    for (int d = 0; d < kMaxD; ++d) {
-        c.N[d] = (int)p.N[d];
-        c.Nt[d] = (int)p.Nt[d];
-    }
-    for (int d = 0; d < D - 1; ++d) {
-        c.outer_len[d] = (int)p.N[d];
-        c.outer_band[d] = 1;
-        c.nlines *= (int)p.N[d];
-    }
-    c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    const ContigPass c = contig_pass(p, 2, +1, K);
     StageTimer t(p, 7, s);
     return launch_fft_contig(p, grid, y, c, s);
 }
@@ -837,35 +815,11 @@ hipError_t adjoint_fft(const nfft_plan_s &p, void *y, void *grid, const void *pa
 // plain unpruned FFT of a whole grid, all axes
 hipError_t plain_fft(const nfft_plan_s &p, void *grid, int dir, hipStream_t s) {
     const int D = p.D;
-    const size_t cs = csize(p.dtype);
-    ContigPass c{};
-    c.K = 1;
-    c.mode = 0;
-    c.D = D;
-    c.dir = dir;
-    c.nlines = 1;
-    for (int d = 0; d < kMaxD; ++d) {
-        c.N[d] = (int)p.N[d];
-        c.Nt[d] = (int)p.Nt[d];
-    }
-    for (int d = 0; d < D - 1; ++d) {
-        c.outer_len[d] = (int)p.Nt[d];
-        c.outer_band[d] = 0;
-        c.nlines *= (int)p.Nt[d];
-    }
-    c.lines_per_block = lines_per_block_contig(p.line[D - 1], cs);
+    const ContigPass c = contig_pass(p, 0, dir, 1);
     hipError_t e = launch_fft_contig(p, grid, grid, c, s);
     if (e != hipSuccess) return e;
     for (int a = D - 2; a >= 0; --a) {
-        AxisPass ap{};
-        ap.axis = a;
-        ap.inner = 1;
-        for (int d = a + 1; d < D; ++d) ap.inner *= (int)p.Nt[d];
-        set_outer(ap, p, a, false);
-        ap.dir = dir;
-        ap.K = 1;
-        ap.lines_per_block = lines_per_block_strided(p.line[a], cs, ap.inner);
-        e = launch_fft_axis(p, grid, ap, s);
+        e = launch_fft_axis(p, grid, axis_pass(p, a, dir, 1, false), s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

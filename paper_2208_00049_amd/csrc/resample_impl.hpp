@@ -270,15 +270,14 @@ __device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, in
 // derivative-of-window interpolation d fhat_j / d x_jd = sum over the stencil of
 // Nt_d P'_{t_d}(frac_d - 1/2) prod_{e != d} P_{t_e} times the grid value -- written
 // to fhat[d * fstride + j].
-template <typename T, int D, int M2, bool GW, bool DV = false, int NT = kResampleThreads>
-__global__ void __launch_bounds__(NT)
-    k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
-             const int *__restrict__ perm, const int4 *__restrict__ subs,
-             const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat,
-             long long gstride, long long fstride) {
+// item: the work item (index into subs) of the workgroup.
+template <typename T, int D, int M2, bool GW, bool DV, int NT>
+__device__ inline void interp_body(const cplx<T> *__restrict__ grid, const Geom &g,
+                                   const NodeRec<T, D> *__restrict__ nodes,
+                                   const int *__restrict__ perm, const int4 *__restrict__ subs,
+                                   const T *__restrict__ coef, int window, const WinParams<T> &wp,
+                                   cplx<T> *__restrict__ fhat, long long fstride, int item) {
     using C = cplx<T>;
-    grid += blockIdx.y * gstride;  // channel
-    fhat += blockIdx.y * fstride;
     constexpr int NPW = 64 / M2;
     using StageT = Stage<T, D, interp_chunk(D, (int)sizeof(T))>;
     constexpr int CH = StageT::kChunk;
@@ -286,7 +285,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ StageT st;
     C *tile = reinterpret_cast<C *>(smem_raw);
 
-    const int4 sp = subs[blockIdx.x];
+    const int4 sp = subs[item];
     int t0[D], P[D];
     {
         int rem = sp.x;
@@ -512,6 +511,16 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
+template <typename T, int D, int M2, bool GW, bool DV = false, int NT = kResampleThreads>
+__global__ void __launch_bounds__(NT)
+    k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
+             const int *__restrict__ perm, const int4 *__restrict__ subs,
+             const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat,
+             long long gstride, long long fstride) {
+    interp_body<T, D, M2, GW, DV, NT>(grid + blockIdx.y * gstride, g, nodes, perm, subs, coef,
+                                      window, wp, fhat + blockIdx.y * fstride, fstride, blockIdx.x);
+}
+
 // ---- spreading accumulators --------------------------------------------------
 //
 // LDS float atomics are slow on this hardware (measured about 30 times slower
@@ -579,15 +588,14 @@ template <> struct FixedPoint<double> {
 // the tile extended by the (2m-1)-wide trailing halo, in LDS, and writes that
 // padded tile to its own slot of the scratch buffer.  Every node's stencil lies
 // inside the padded tile, so the tap loops carry no bounds tests.
-template <typename T, int D, int M2, bool GW, int NT = kResampleThreads>
-__global__ void __launch_bounds__(NT)
-    k_spread(cplx<T> *__restrict__ pad, Geom g, const NodeRec<T, D> *__restrict__ nodes,
-             const int *__restrict__ perm, const int4 *__restrict__ subs,
-             const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
-             const cplx<T> *__restrict__ fhat, long long pstride, long long fstride) {
+// item: the work item (index into subs, and the padded tile's slot in pad).
+template <typename T, int D, int M2, bool GW, int NT>
+__device__ inline void spread_body(cplx<T> *__restrict__ pad, const Geom &g,
+                                   const NodeRec<T, D> *__restrict__ nodes,
+                                   const int *__restrict__ perm, const int4 *__restrict__ subs,
+                                   const T *__restrict__ coef, int window, const WinParams<T> &wp,
+                                   T wmax_prod, const cplx<T> *__restrict__ fhat, int item) {
     using C = cplx<T>;
-    pad += blockIdx.y * pstride;  // channel
-    fhat += blockIdx.y * fstride;
     using FP = FixedPoint<T>;
     constexpr int NPW = 64 / M2;
     constexpr int CH = Stage<T, D>::kChunk;
@@ -596,7 +604,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ Stage<T, D> st;
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double
 
-    const int4 sp = subs[blockIdx.x];
+    const int4 sp = subs[item];
     int t0[D], P[D];
     {
         int rem = sp.x;
@@ -732,7 +740,7 @@ __global__ void __launch_bounds__(NT)
     // the padded tile goes to the item's scratch slot, unscaled (NaN for a non-finite item)
     const T inv = (T)(1.0 / (double)scale);
     const T nan = (T)__builtin_nan("");
-    C *out = pad + (size_t)blockIdx.x * ptot;
+    C *out = pad + (size_t)item * ptot;
     for (int idx = threadIdx.x; idx < ptot; idx += NT) {
         const unsigned long long *ap = acc + idx;
         out[idx] = poisoned ? cmake<C>(nan, nan)
@@ -740,20 +748,29 @@ __global__ void __launch_bounds__(NT)
     }
 }
 
+template <typename T, int D, int M2, bool GW, int NT = kResampleThreads>
+__global__ void __launch_bounds__(NT)
+    k_spread(cplx<T> *__restrict__ pad, Geom g, const NodeRec<T, D> *__restrict__ nodes,
+             const int *__restrict__ perm, const int4 *__restrict__ subs,
+             const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
+             const cplx<T> *__restrict__ fhat, long long pstride, long long fstride) {
+    spread_body<T, D, M2, GW, NT>(pad + blockIdx.y * pstride, g, nodes, perm, subs, coef, window, wp,
+                                  wmax_prod, fhat + blockIdx.y * fstride, blockIdx.x);
+}
+
 // Halo merge: grid point l of tile p is the sum of the padded tiles that cover
 // it -- those of the work items of p and, within 2m-1 of p's leading edge along
 // a set e of axes, those of the tile preceding p along e (cyclically).  Each
 // grid value is written once, by one thread, in a fixed order of summation.
+// bx: the workgroup's block among the nbx (one per tile) of this grid's merge.
 template <typename T, int D>
-__global__ void __launch_bounds__(kResampleThreads)
-    k_spread_merge(cplx<T> *__restrict__ grid, Geom g, const cplx<T> *__restrict__ pad,
-                   const int *__restrict__ tile_sub, int M2, long long gstride, long long pstride) {
+__device__ inline void spread_merge_body(cplx<T> *__restrict__ grid, const Geom &g,
+                                         const cplx<T> *__restrict__ pad,
+                                         const int *__restrict__ tile_sub, int M2, int bx, int nbx) {
     using C = cplx<T>;
-    grid += blockIdx.y * gstride;  // channel
-    pad += blockIdx.y * pstride;
     // consecutive tiles on one XCD: a tile's own rows and the halo rows its
     // neighbour reads share cache lines (3-D 128^3: merge 15-65 us faster)
-    const int p = xcd_block(blockIdx.x, gridDim.x);
+    const int p = xcd_block(bx, nbx);
     int tc[D], P[D];
     int ptot = 1;
     {
@@ -846,6 +863,14 @@ __global__ void __launch_bounds__(kResampleThreads)
             grid[gi] = cmake<C>(sr, si);
         }
     }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kResampleThreads)
+    k_spread_merge(cplx<T> *__restrict__ grid, Geom g, const cplx<T> *__restrict__ pad,
+                   const int *__restrict__ tile_sub, int M2, long long gstride, long long pstride) {
+    spread_merge_body<T, D>(grid + blockIdx.y * gstride, g, pad + blockIdx.y * pstride, tile_sub, M2,
+                            blockIdx.x, gridDim.x);
 }
 
 // Static LDS of the interpolation kernel (its staged node chunk).

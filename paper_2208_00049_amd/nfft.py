@@ -287,11 +287,13 @@ class Plan:
 
 
 class Batch:
-    """Independent transforms of several plans run as one HIP graph (see nfft_batch_create).
+    """Independent transforms of several plans (see nfft_batch_create): one kernel launch per
+    stage for all of them when the plans share type, D <= 3, stencil and window (``info()``
+    reports the mode and the launches per call), else their kernel chains in one HIP graph.
 
     ``forward(fs, outs)`` / ``adjoint(fhats, outs)`` take lists of tensors, one per plan, in
-    the plans' order; the graph is captured on the first call and again whenever a tensor
-    differs from the previous call's (keep the same tensors to replay it).
+    the plans' order; keep the same tensors from call to call (new pointers cost a stream
+    synchronisation, or a graph capture).
     """
 
     def __init__(self, plans, nstreams=4):
@@ -315,6 +317,14 @@ class Batch:
         out = (ctypes.c_void_p * n)(*[t.data_ptr() for t in outs])
         _lib.check(fn(self._h, inp, out, _stream_handle(self.device)), name)
         return outs
+
+    def info(self):
+        """{"fused": bool, "launches_forward": int, "launches_adjoint": int}"""
+        f, lf, la = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(self._lib.nfft_batch_info(self._h, ctypes.byref(f), ctypes.byref(lf),
+                                             ctypes.byref(la)), "nfft_batch_info")
+        return {"fused": bool(f.value), "launches_forward": lf.value,
+                "launches_adjoint": la.value}
 
     def forward(self, fs, outs):
         return self._run(self._lib.nfft_batch_forward, fs, outs, lambda p: p.N, lambda p: (p.M,),

@@ -8,6 +8,10 @@ run as one HIP graph, and the tile autotuner.
   graph is replayed several times with eager work of the same plans and
   synchronisations in between, every replay is checked, and a changed output
   tensor makes the batch capture a new graph.
+* Fused batch (plans of one type, D, stencil and window): one launch per stage
+  (the count is asserted), results bit for bit those of the plans' own calls
+  over repeated calls, with a plan without nodes, odd and mixed sizes, and new
+  tensors between calls; one transform is checked against the FP64 oracle.
 * Tuner: the chosen tiles are among the candidates and the tuned plan agrees
   with a default plan within the rounding tolerance of the type.
 """
@@ -99,6 +103,68 @@ def test_batch_graph_replays(device):
     for r, o in zip(ref_f, outs_f):
         assert torch.equal(r, o)
     b.close()
+
+
+FUSED_CASES = [
+    # (specs [(N, M)], m, dtype, tiled 3-D, launches forward, launches adjoint)
+    ([((512, 512), 262144), ((64, 64), 10000), ((128, 128), 0), ((256, 256), 50000),
+      ((128, 128), 130000), ((64, 64), 500)], 4, "c64", False, 3, 3),
+    ([((48, 64), 4000), ((33, 20), 900), ((64, 64), 7000)], 6, "c128", False, 3, 3),
+    ([((256,), 512), ((1000,), 3000), ((96,), 0), ((64,), 200)], 4, "c128", False, 2, 3),
+    ([((16, 16, 16), 6000), ((32, 32, 32), 30000), ((16, 24, 16), 2000)], 4, "c64", True, 4, 5),
+]
+
+
+@pytest.mark.parametrize("specs,m,dt,tiled,lf,la", FUSED_CASES)
+def test_batch_fused_equals_plans(device, specs, m, dt, tiled, lf, la):
+    from paper_2208_00049_amd import Batch
+    kw = {"spread": "tiled"} if tiled else {}
+    plans, xs = [], []
+    for i, (N, M) in enumerate(specs):
+        p, x = plan_for(device, N, M, m, 2.0, dt, config=96 + i, **kw)
+        plans.append(p)
+        xs.append(x)
+    fs = [to_dev(wl.cn01(N, config=96, stream=i), dt, device) for i, (N, M) in enumerate(specs)]
+    fhs = [to_dev(wl.cn01((M,), config=97, stream=i), dt, device) for i, (N, M) in enumerate(specs)]
+    ref_f = [p.forward(f).clone() for p, f in zip(plans, fs)]
+    ref_a = [p.adjoint(fh).clone() for p, fh in zip(plans, fhs)]
+    b = Batch(plans)
+    info = b.info()
+    print("fused batch", [s for s in specs], dt, info, flush=True)
+    assert info == {"fused": True, "launches_forward": lf, "launches_adjoint": la}
+    outs_f = [torch.empty_like(r) for r in ref_f]
+    outs_a = [torch.empty_like(r) for r in ref_a]
+    for rep in range(3):
+        for o in outs_f + outs_a:
+            o.fill_(float("nan"))
+        b.forward(fs, outs_f)
+        b.adjoint(fhs, outs_a)
+        torch.cuda.synchronize()
+        for r, o in zip(ref_f + ref_a, outs_f + outs_a):
+            assert torch.equal(r, o)
+        plans[rep % len(plans)].adjoint(fhs[rep % len(plans)])  # eager work in between
+        torch.cuda.synchronize()
+    # new tensors: the pointer table is rewritten
+    outs_a = [torch.full_like(r, float("nan")) for r in ref_a]
+    fs2 = [f.clone() for f in fs]
+    b.adjoint(fhs, outs_a)
+    b.forward(fs2, outs_f)
+    torch.cuda.synchronize()
+    for r, o in zip(ref_f + ref_a, outs_f + outs_a):
+        assert torch.equal(r, o)
+    k = max(range(len(specs)), key=lambda i: specs[i][1])
+    N, M = specs[k]
+    tol = e2e_tol(N, 2.0, m, dt)
+    assert rel2(outs_f[k].cpu().numpy(), na.forward(xs[k], fs[k].cpu().numpy(), m, 2.0)) < tol
+    assert rel2(outs_a[k].cpu().numpy(), na.adjoint(xs[k], fhs[k].cpu().numpy(), N, m, 2.0)) < tol
+    b.close()
+
+
+def test_batch_mixed_plans_use_a_graph(device):
+    from paper_2208_00049_amd import Batch
+    p1, _ = plan_for(device, (64, 64), 1000, 4, 2.0, "c64", config=98)
+    p2, _ = plan_for(device, (64, 64), 1000, 4, 2.0, "c128", config=98)
+    assert Batch([p1, p2]).info()["fused"] is False
 
 
 def test_batch_rejects_duplicate_plans(device):
