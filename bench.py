@@ -766,17 +766,13 @@ def main():
                 "traffic": round(traffic) if traffic is not None else None,
                 "algorithmic_bytes": algo[dominant], "launch_ms": round(dom_ms, 5)}
 
-    # spreading's own roof: its LDS atomics per second against the rate the library's
-    # calibration kernel measures in this run for the access shape of one spreading
-    # instruction (eight rows of eight consecutive words at random starts): 64-bit integer
-    # additions (fixed point: one per component and tap in complex64, two in complex128 with
-    # padded tiles), or FP64 additions (complex128 column sweeps: one per component and tap)
+    # spreading's own roof: its LDS atomics per second (64-bit integer additions of the
+    # fixed-point accumulators, one per component and tap) against the rate the library's
+    # calibration kernel measures in this run
     from paper_2208_00049_amd import calibrate_lds
     taps = 2 * args.m + (2 if args.wide else 0)
-    sweep_f64 = info["spread"] == "sweep" and args.dtype == "c128"
-    per_tap = 4 if (args.dtype == "c128" and not sweep_f64) else 2
-    atomics = w["M"] * taps ** w["D"] * per_tap
-    lds_op = "ds_add_f64" if sweep_f64 else "ds_add_u64"
+    atomics = w["M"] * taps ** w["D"] * 2
+    lds_op = "ds_add_u64"
     # the roof is the unit's best rate (consecutive words, no bank conflicts); the rate for
     # rows of eight words at random starts (one instruction of the padded-tile kernels) is
     # reported beside it

@@ -386,11 +386,8 @@ __device__ inline void fft_axis0_from_pad_body(cplx<T> *grid, const FftLine &fl,
                 sr += v[u][e].x;
                 si += v[u][e].y;
                 if (src[u][e] >= 0)
-                    for (int s = rng[2 * src[u][e]] + 1; s < rng[2 * src[u][e] + 1]; ++s) {
-                        const C w = pad[(size_t)s * ptot + off[u][e]];
-                        sr += w.x;
-                        si += w.y;
-                    }
+                    add_split_items(sr, si, pad, ptot, off[u][e], rng[2 * src[u][e]] + 1,
+                                    rng[2 * src[u][e] + 1]);
             }
             lds[bb * LP + r_of[u]] = cmake<C>(sr, si);
         }

@@ -115,9 +115,9 @@ size_t interp_lds(const int *Q, int D, int taps, size_t cs) {
 }
 
 // LDS of the spreading kernel: fixed-point accumulators of the padded tile (one
-// int64 per component for c64, two for c128) plus the staged node chunk.
+// int64 per component) plus the staged node chunk.
 size_t spread_lds(const int *Q, int D, int taps, size_t cs) {
-    size_t t = (cs == 8 ? 16 : 32);
+    size_t t = 16;
     for (int d = 0; d < D; ++d) t *= (size_t)(Q[d] + taps - 1);
     return t + nfft::resample_static_lds(D, (int)cs / 2);
 }

@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kOwnerThreads)
                    const cplx<T> *__restrict__ fhat, long long gstride, long long fstride,
                    OwnerLayout lay) {
     using C = cplx<T>;
-    using FP = FixedPoint<T>;
+    using FP = typename OwnerAcc<T>::type;
     constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ OwnerStage<T, D, M2> st;
@@ -416,12 +416,7 @@ __global__ void __launch_bounds__(kOwnerThreads)
     const double amax_d = __longlong_as_double((long long)amax_bits);
     const bool poisoned = isinf(amax_d);  // a non-finite candidate value (same in every thread)
     const double bound = amax_d * (double)wmax_prod;
-    T scale = (T)1;
-    if (bound > 0.0 && !poisoned) {
-        int e;
-        (void)frexp(FP::kLimit / bound, &e);
-        scale = (T)ldexp(1.0, e - 1);
-    }
+    const T scale = bound > 0.0 && !poisoned ? FP::scale(bound, total) : (T)1;
 
     const TapCoef<T, M2> tc = owner_coef<T, D, M2>(coef, window, wp.m);
     constexpr int CH = OwnerStage<T, D, M2>::CH;
@@ -477,7 +472,7 @@ hipError_t run_spread_owner(const nfft_plan_s &p, const void *fhat, void *grid, 
                             int K) {
     // padded accumulator layout where it fits beside the staged candidates
     const size_t stat = owner_static_lds(D, M2, (int)sizeof(T));
-    const size_t cell_bytes = 2 * FixedPoint<T>::kSlots * sizeof(unsigned long long);
+    const size_t cell_bytes = 2 * OwnerAcc<T>::type::kSlots * sizeof(unsigned long long);
     OwnerLayout lay = owner_layout(p.geom, D, true);
     if ((size_t)lay.cells * cell_bytes + stat > (size_t)p.lds_limit) lay = owner_layout(p.geom, D, false);
     const size_t shm = (size_t)lay.cells * cell_bytes;

@@ -38,6 +38,16 @@
 
 namespace nfft {
 
+// Channels per interpolation workgroup of a multi-channel call: two where both
+// channels' tiles fit 64 KiB beside the staged nodes (polynomial window, D <= 2), so
+// that each node's weights serve both.  Measured on the 32-channel radial workload
+// (2-D 256^2, M = 65536): interpolation 59 us with one channel per workgroup, 58 us
+// with two, 73 us with four (one workgroup per CU fewer than the latency needs).
+template <typename T, int D> inline int interp_channel_block(int K, bool gw, size_t tile) {
+    if (D > 2 || gw || K < 2) return 1;
+    return 2 * tile + interp_static_lds(D, (int)sizeof(T)) <= 65536 ? 2 : 1;
+}
+
 template <typename T> struct WinParams {
     T beta[kMaxD];
     T inv_peak[kMaxD];  // direct evaluation: pi / sinh(beta), the stored window's normalisation
@@ -270,13 +280,17 @@ __device__ inline void row_weights_2d(T *w0, T w_axis0, long long gk, int li, in
 // derivative-of-window interpolation d fhat_j / d x_jd = sum over the stencil of
 // Nt_d P'_{t_d}(frac_d - 1/2) prod_{e != d} P_{t_e} times the grid value -- written
 // to fhat[d * fstride + j].
-// item: the work item (index into subs) of the workgroup.
-template <typename T, int D, int M2, bool GW, bool DV, int NT>
+// item: the work item (index into subs) of the workgroup; kb: the channels it serves
+// (grids at stride gstride, fhat at stride fstride; the derivative mode takes one).
+// Every channel's tile is in LDS at once, so each node's weights are evaluated once
+// and serve all kb channels.
+template <typename T, int D, int M2, bool GW, bool DV, int NT, int KB = 1>
 __device__ inline void interp_body(const cplx<T> *__restrict__ grid, const Geom &g,
                                    const NodeRec<T, D> *__restrict__ nodes,
                                    const int *__restrict__ perm, const int4 *__restrict__ subs,
                                    const T *__restrict__ coef, int window, const WinParams<T> &wp,
-                                   cplx<T> *__restrict__ fhat, long long fstride, int item) {
+                                   cplx<T> *__restrict__ fhat, long long fstride, int item,
+                                   int kb = 1, long long gstride = 0) {
     using C = cplx<T>;
     constexpr int NPW = 64 / M2;
     using StageT = Stage<T, D, interp_chunk(D, (int)sizeof(T))>;
@@ -328,10 +342,13 @@ __device__ inline void interp_body(const cplx<T> *__restrict__ grid, const Geom 
 
     // copy the tile and its trailing halo into LDS, wrapping at the grid edge;
     // eight loads per thread are in flight before the first LDS write
-    {
-        int total = 1;
+    int ptot = 1;
 #pragma unroll
-        for (int d = 0; d < D; ++d) total *= P[d];
+    for (int d = 0; d < D; ++d) ptot *= P[d];
+    for (int ch = 0; ch < kb; ++ch) {
+        const int total = ptot;
+        const cplx<T> *gsrc = grid + ch * gstride;
+        C *tdst = tile + ch * ptot;
         const float rl = 1.0f / (float)P[D - 1];
         const float r1 = D == 3 ? 1.0f / (float)P[1] : 1.0f;
         constexpr int U = 8;
@@ -360,11 +377,11 @@ __device__ inline void interp_body(const cplx<T> *__restrict__ grid, const Geom 
                 }
                 int c = t0[D - 1] + col;
                 if (c >= g.Nt[D - 1]) c -= g.Nt[D - 1];
-                v[u] = grid[gb + c];
+                v[u] = gsrc[gb + c];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (dst[u] >= 0) tile[dst[u]] = v[u];
+                if (dst[u] >= 0) tdst[dst[u]] = v[u];
         }
     }
 
@@ -465,60 +482,71 @@ __device__ inline void interp_body(const cplx<T> *__restrict__ grid, const Geom 
                 continue;
             }
             node_weights<GW, T, D, M2>(w, lw, fr, gk, li, window, wp);
-            T ar = (T)0, ai = (T)0;
-            if constexpr (D == 1) {
-                const C v = tile[l[0] + li];
-                ar = w[0] * v.x;
-                ai = w[0] * v.y;
-            } else if constexpr (D == 2) {
-                T w0[M2];
-                row_weights_2d<GW, T, M2>(w0, w[0], gk, li, gbase, window, wp);
-                const C *row = tile + l[0] * P[1] + l[1] + li;
-#pragma unroll
-                for (int a = 0; a < M2; ++a) {
-                    const C v = row[a * P[1]];
-                    ar = fma(w0[a], v.x, ar);
-                    ai = fma(w0[a], v.y, ai);
-                }
-                ar *= w[1];
-                ai *= w[1];
-            } else {
-                T w0[M2], w1[M2];
+            // the broadcast row weights of the node, for every channel
+            T w0[D >= 2 ? M2 : 1], w1[D == 3 ? M2 : 1];
+            if constexpr (D == 2) row_weights_2d<GW, T, M2>(w0, w[0], gk, li, gbase, window, wp);
+            if constexpr (D == 3) {
                 BcastAll<M2, 0, T>::run(w0, w[0], gbase);
                 BcastAll<M2, 0, T>::run(w1, w[1], gbase);
-                const C *base3 = tile + (l[0] * P[1] + l[1]) * P[2] + l[2] + li;
-#pragma unroll
-                for (int a = 0; a < M2; ++a) {
-                    T sr = (T)0, si = (T)0;
-                    const C *rowp = base3 + a * P[1] * P[2];
-#pragma unroll
-                    for (int b = 0; b < M2; ++b) {
-                        const C v = rowp[b * P[2]];
-                        sr = fma(w1[b], v.x, sr);
-                        si = fma(w1[b], v.y, si);
-                    }
-                    ar = fma(w0[a], sr, ar);
-                    ai = fma(w0[a], si, ai);
-                }
-                ar *= w[2];
-                ai *= w[2];
             }
-            ar = group_sum<M2>(ar, li);
-            ai = group_sum<M2>(ai, li);
-            if (valid && li == 0) fhat[st.idx[ks]] = cmake<C>(ar, ai);
+            const int dst = st.idx[ks];
+#pragma unroll
+            for (int ch = 0; ch < KB; ++ch) {
+                if (ch >= kb) break;
+                const C *tc = tile + ch * ptot;
+                T ar = (T)0, ai = (T)0;
+                if constexpr (D == 1) {
+                    const C v = tc[l[0] + li];
+                    ar = w[0] * v.x;
+                    ai = w[0] * v.y;
+                } else if constexpr (D == 2) {
+                    const C *row = tc + l[0] * P[1] + l[1] + li;
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) {
+                        const C v = row[a * P[1]];
+                        ar = fma(w0[a], v.x, ar);
+                        ai = fma(w0[a], v.y, ai);
+                    }
+                    ar *= w[1];
+                    ai *= w[1];
+                } else {
+                    const C *base3 = tc + (l[0] * P[1] + l[1]) * P[2] + l[2] + li;
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) {
+                        T sr = (T)0, si = (T)0;
+                        const C *rowp = base3 + a * P[1] * P[2];
+#pragma unroll
+                        for (int b = 0; b < M2; ++b) {
+                            const C v = rowp[b * P[2]];
+                            sr = fma(w1[b], v.x, sr);
+                            si = fma(w1[b], v.y, si);
+                        }
+                        ar = fma(w0[a], sr, ar);
+                        ai = fma(w0[a], si, ai);
+                    }
+                    ar *= w[2];
+                    ai *= w[2];
+                }
+                ar = group_sum<M2>(ar, li);
+                ai = group_sum<M2>(ai, li);
+                if (valid && li == 0) fhat[ch * fstride + dst] = cmake<C>(ar, ai);
+            }
         }
         __syncthreads();
     }
 }
 
-template <typename T, int D, int M2, bool GW, bool DV = false, int NT = kResampleThreads>
+template <typename T, int D, int M2, bool GW, bool DV = false, int NT = kResampleThreads, int KB = 1>
 __global__ void __launch_bounds__(NT)
     k_interp(const cplx<T> *__restrict__ grid, Geom g, const NodeRec<T, D> *__restrict__ nodes,
              const int *__restrict__ perm, const int4 *__restrict__ subs,
              const T *__restrict__ coef, int window, WinParams<T> wp, cplx<T> *__restrict__ fhat,
-             long long gstride, long long fstride) {
-    interp_body<T, D, M2, GW, DV, NT>(grid + blockIdx.y * gstride, g, nodes, perm, subs, coef,
-                                      window, wp, fhat + blockIdx.y * fstride, fstride, blockIdx.x);
+             long long gstride, long long fstride, int K) {
+    // channel block blockIdx.y: channels KB * blockIdx.y .. (at most KB of the K)
+    const int c0 = blockIdx.y * KB;
+    interp_body<T, D, M2, GW, DV, NT, KB>(grid + c0 * gstride, g, nodes, perm, subs, coef, window,
+                                          wp, fhat + c0 * fstride, fstride, blockIdx.x,
+                                          min(KB, K - c0), gstride);
 }
 
 // ---- spreading accumulators --------------------------------------------------
@@ -526,19 +554,25 @@ __global__ void __launch_bounds__(NT)
 // LDS float atomics are slow on this hardware (measured about 30 times slower
 // than integer ones), so the tile is accumulated in fixed point with 64-bit
 // integer LDS atomics, which also makes the sum exact and independent of the
-// order of the additions.  Each workgroup picks a power-of-two scale s from the
-// largest |Re|, |Im| of its nodes' fhat and the window maximum, so that every
-// scaled contribution c*s is below 2^30 (c64) or 2^62 (c128) in magnitude.
-//   c64:  c*s is truncated to an int32 and added to one int64 per component
-//         (resolution 2^-30 of the largest possible contribution; no
-//         overflow below 2^33 contributions per grid point).
-//   c128: c*s is split into hi = floor(c*s / 2^32) and lo = c*s - hi*2^32 in
-//         [0, 2^32), added to an int64 and a uint64 per component (96 bits).
+// order of the additions.  Each workgroup scales its contributions c by s, from
+// the largest |Re|, |Im| of its nodes' fhat times the bound of the window product
+// (window_bound), so that every |c*s| is below a limit; one int64 per component and
+// grid point:
+//   c64:  s is a power of two, |c*s| < 2^30, truncated to an int32 (resolution
+//         2^-30 of the largest possible contribution; no overflow below 2^33
+//         contributions per point; s and 1/s exact).
+//   c128: s = limit(n) / bound, limit(n) = min(2^51 (1 - 2^-10), 2^62 / n') for a
+//         workgroup of n nodes (n' = n rounded up to a power of two): a node adds to
+//         a grid point at most once, so n contributions stay below 2^62, and below
+//         2^51 the rounding to the nearest integer is exact by adding 1.5 * 2^52 and
+//         reading the integer off the mantissa.  Resolution 2^-51 of the largest
+//         possible contribution for n <= 2048 (FP64 rounds each value to 2^-53 of
+//         itself); s is not a power of two, so the read-out's 1/s adds one FP64
+//         rounding.
 // The accumulators are planes of the padded tile (structure of arrays): plane
 // s holds slot s of every cell, so one atomic instruction of a wavefront (eight
 // nodes' rows of 2m consecutive cells) touches consecutive 8-byte words of one
-// plane and spreads over all LDS banks.  Planes: c64 [Re][Im]; c128 [Re hi][Re
-// lo][Im hi][Im lo].
+// plane and spreads over all LDS banks.  Planes: [Re][Im].
 template <typename T> struct FixedPoint;
 
 // Magnitude a value contributes to the fixed-point scale: max(|Re|, |Im|), or +infinity
@@ -550,9 +584,22 @@ template <typename T> __device__ inline T scale_mag(T re, T im) {
     return (isfinite(re) && isfinite(im)) ? fmax(fabs(re), fabs(im)) : (T)INFINITY;
 }
 
+// The nearest integer to v, |v| < 2^51: v + 1.5 * 2^52 lies in (2^52, 2^53), where
+// the spacing of doubles is 1, and the integer is its mantissa less the shift's
+// (the addition is kept separate from the product that forms v, so that every
+// instantiation rounds the same way).
+__device__ inline long long round_to_ll(double v) {
+    return __double_as_longlong(__dadd_rn(v, 6755399441055744.0)) - 0x4338000000000000LL;
+}
+
 template <> struct FixedPoint<float> {
     static constexpr int kSlots = 1;  // int64 slots per component
-    static constexpr double kLimit = 1073741824.0;  // 2^30
+    // scale for contributions bounded by `bound` (> 0) in a workgroup of n nodes
+    __device__ static inline float scale(double bound, int) {
+        int e;
+        (void)frexp(1073741824.0 / bound, &e);  // 2^30 / bound = f 2^e, f in [0.5, 1)
+        return (float)ldexp(1.0, e - 1);
+    }
     // a: the cell's word in plane 0; ps: plane size (cells); cr, ci: scaled, |c| < 2^30
     __device__ static inline void add(unsigned long long *a, int ps, float cr, float ci) {
         atomicAdd(a, (unsigned long long)(long long)(int)cr);
@@ -564,8 +611,35 @@ template <> struct FixedPoint<float> {
 };
 
 template <> struct FixedPoint<double> {
+    static constexpr int kSlots = 1;
+    // n: the most contributions one grid point can receive (the workgroup's nodes)
+    __device__ static inline double scale(double bound, int n) {
+        double l = 4611686018427387904.0;  // 2^62
+        for (int c = 1; c < n; c *= 2) l *= 0.5;
+        const double lmax = 2251799813685248.0 * (1.0 - 1.0 / 1024.0);  // 2^51 (1 - 2^-10)
+        return (l < lmax ? l : lmax) / bound;
+    }
+    __device__ static inline void add(unsigned long long *a, int ps, double cr, double ci) {
+        atomicAdd(a, (unsigned long long)round_to_ll(cr));
+        atomicAdd(a + ps, (unsigned long long)round_to_ll(ci));
+    }
+    __device__ static inline double read(const unsigned long long *a, int ps, int comp) {
+        return (double)(long long)a[(size_t)comp * ps];
+    }
+};
+
+// The exact 96-bit complex128 accumulator of the tile-owner spreading (D = 4), whose
+// workgroups take contributions from every node of up to 81 tiles, too many for a
+// 64-bit sum at full resolution: c*s below 2^62 is split into hi = floor(c*s / 2^32)
+// and lo = c*s - hi*2^32 in [0, 2^32), added to an int64 and a uint64 (two slots per
+// component: planes [Re hi][Re lo][Im hi][Im lo]).
+struct FixedPoint96 {
     static constexpr int kSlots = 2;
-    static constexpr double kLimit = 4611686018427387904.0;  // 2^62
+    __device__ static inline double scale(double bound, int) {
+        int e;
+        (void)frexp(4611686018427387904.0 / bound, &e);  // 2^62 / bound = f 2^e
+        return ldexp(1.0, e - 1);
+    }
     __device__ static inline void add1(unsigned long long *a, int ps, double v) {
         const int hi = __double2int_rd(v * 2.3283064365386963e-10);  // floor(v / 2^32)
         const double rest = v - (double)hi * 4294967296.0;               // in [0, 2^32)
@@ -582,6 +656,9 @@ template <> struct FixedPoint<double> {
         return (double)(long long)c[0] * 4294967296.0 + (double)c[ps];
     }
 };
+// Accumulator of the tile-owner spreading per type.
+template <typename T> struct OwnerAcc { using type = FixedPoint<T>; };
+template <> struct OwnerAcc<double> { using type = FixedPoint96; };
 
 // Spreading of one work item (a tile's node range, at most a few hundred to a
 // thousand nodes).  The workgroup accumulates the item's contributions into
@@ -681,12 +758,7 @@ __device__ inline void spread_body(cplx<T> *__restrict__ pad, const Geom &g,
     const double amax_d = __longlong_as_double((long long)amax_bits);
     const bool poisoned = isinf(amax_d);  // a non-finite value in the item (same in every thread)
     const double bound = amax_d * (double)wmax_prod;
-    T scale = (T)1;
-    if (bound > 0.0 && !poisoned) {
-        int e;
-        (void)frexp(FP::kLimit / bound, &e);
-        scale = (T)ldexp(1.0, e - 1);
-    }
+    const T scale = bound > 0.0 && !poisoned ? FP::scale(bound, nitem) : (T)1;
 
     for (int c0 = sp.y; c0 < (poisoned ? sp.y : sp.z); c0 += CH) {
         const int n = min(CH, sp.z - c0);
@@ -850,12 +922,8 @@ __device__ inline void spread_merge_body(cplx<T> *__restrict__ grid, const Geom 
             for (int e = 0; e < NE; ++e) {
                 sr += v[u][e].x;
                 si += v[u][e].y;
-                if (in[u][e])  // further items of a split tile (rare)
-                    for (int s = rng[2 * e] + 1; s < rng[2 * e + 1]; ++s) {
-                        const C w = pad[(size_t)s * ptot + off[u][e]];
-                        sr += w.x;
-                        si += w.y;
-                    }
+                if (in[u][e])  // further items of a split tile
+                    add_split_items(sr, si, pad, ptot, off[u][e], rng[2 * e] + 1, rng[2 * e + 1]);
             }
             long long gi = 0;
 #pragma unroll
@@ -922,15 +990,19 @@ template <typename T, int D, int M2>
 hipError_t run_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
     constexpr int NT = resample_threads<T, D>();
-    const size_t shm = padded_cells(p.geom, D) * sizeof(cplx<T>);
+    const size_t tile = padded_cells(p.geom, D) * sizeof(cplx<T>);
     const bool gw = p.window != NFFT_WINDOW_POLY;
-    auto kern = gw ? k_interp<T, D, M2, true, false, NT> : k_interp<T, D, M2, false, false, NT>;
+    const int kb = interp_channel_block<T, D>(K, gw, tile);
+    auto kern = gw ? k_interp<T, D, M2, true, false, NT, 1> : k_interp<T, D, M2, false, false, NT, 1>;
+    if constexpr (D <= 2)
+        if (kb == 2) kern = k_interp<T, D, M2, false, false, NT, 2>;
+    const size_t shm = kb * tile;
     hipError_t e = allow_lds(kern, shm, interp_static_lds_t<T, D>());
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(p.nsub, K), dim3(NT), shm, s,
+    hipLaunchKernelGGL(kern, dim3(p.nsub, (K + kb - 1) / kb), dim3(NT), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
-                       (long long)p.G, (long long)p.M);
+                       (long long)p.G, (long long)p.M, K);
     return hipGetLastError();
 }
 
@@ -946,7 +1018,7 @@ hipError_t run_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat,
     hipLaunchKernelGGL(kern, dim3(p.nsub, 1), dim3(NT), shm, s,
                        (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
                        p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)dfhat,
-                       (long long)p.G, (long long)p.M);
+                       (long long)p.G, (long long)p.M, 1);
     return hipGetLastError();
 }
 

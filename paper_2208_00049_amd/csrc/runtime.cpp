@@ -249,12 +249,24 @@ int fused_build(nfft_batch_s &b) {
             finish_fft(sb, pl);
             built[dir].push_back(std::move(sb));
         };
+        // resampling stages: the transforms with the most nodes per work item first, so
+        // that the longest workgroups do not form the launch's tail
         auto res_stage = [&](int kind) {
             StageBuild sb;
             sb.st.fft = false;
             sb.st.kind = kind;
-            for (int i : ids) sb.res.push_back(res_entry(*b.plans[i], i, kind));
-            finish_res(sb, pl);
+            std::vector<int> rid = ids;
+            if (kind != nfft::kBxMerge)
+                std::stable_sort(rid.begin(), rid.end(), [&](int i, int j) {
+                    const nfft_plan_s &a = *b.plans[i], &c = *b.plans[j];
+                    return a.M * std::max(c.nsub, 1) > c.M * std::max(a.nsub, 1);
+                });
+            std::vector<const nfft_plan_s *> rpl;
+            for (int i : rid) {
+                sb.res.push_back(res_entry(*b.plans[i], i, kind));
+                rpl.push_back(b.plans[i]);
+            }
+            finish_res(sb, rpl);
             built[dir].push_back(std::move(sb));
         };
         if (dir == 0) {

@@ -28,42 +28,43 @@
 // reads node records and values as consecutive runs and loads the next chunk of
 // nodes while it accumulates the current one.
 //
-// Accumulation in LDS:
-//   complex64:  64-bit fixed point per component with a power-of-two scale of
-//               the transform (from its largest |Re|, |Im|): exact, independent
-//               of the order of the additions.
-//   complex128: FP64 LDS atomic additions (ds_add_f64), two per tap instead of
-//               the four 64-bit integer ones an exact 96-bit sum takes, and 16
-//               bytes per point instead of 32, so that the 16 x 16 columns fit.
-//               Sums are correct to FP64 rounding; their order, and so the last
-//               bits of the result, can differ between calls.
+// Accumulation in LDS: 64-bit fixed point per component (the tiled kernels'
+// scheme, resample_impl.hpp) with a scale from the transform's largest |Re|, |Im|:
+// exact, independent of the order of the additions, so the adjoint is bitwise
+// reproducible.  complex64 adds truncated int32 contributions below 2^30;
+// complex128 rounds contributions to integers, scaled for the most nodes that reach
+// one grid plane of the segment (no grid point receives more contributions), where
+// that count leaves the full 2^-51 resolution (at most kSweepFixedNodes).  A denser
+// complex128 segment (a cluster) accumulates with FP64 LDS atomics instead in the
+// same 8-byte words: correct to FP64 rounding, whose order -- and so the last bits
+// of such a segment's sums -- can differ between calls.
+#include <type_traits>
+
 #include "resample_impl.hpp"
 
 namespace nfft {
 
-template <typename T> struct SweepAcc;
+constexpr int kSweepFixedNodes = 2048;
 
-template <> struct SweepAcc<float> {
+// a: the point's Re word; the Im word is `im` words further; fixed: the segment's
+// words are fixed-point sums (always in complex64), else FP64 sums
+template <typename T> struct SweepAcc {
     using W = unsigned long long;
-    static constexpr bool kFixed = true;
-    // a: the point's Re word; the Im word is `im` words further; |cr|, |ci| < 2^30
-    __device__ static inline void add(W *a, int im, float cr, float ci) {
-        atomicAdd(a, (W)(long long)(int)cr);
-        atomicAdd(a + im, (W)(long long)(int)ci);
+    __device__ static inline void add(W *a, int im, T cr, T ci, bool fixed) {
+        if constexpr (sizeof(T) == 8) {
+            if (!fixed) {
+                atomicAdd(reinterpret_cast<double *>(a), (double)cr);
+                atomicAdd(reinterpret_cast<double *>(a + im), (double)ci);
+                return;
+            }
+        }
+        FixedPoint<T>::add(a, im, cr, ci);
     }
-    __device__ static inline float get(const W *a, double inv) {
-        return (float)((double)(long long)*a * inv);
+    __device__ static inline T get(const W *a, double inv, bool fixed) {
+        if constexpr (sizeof(T) == 8)
+            if (!fixed) return (T)__longlong_as_double((long long)*a);
+        return (T)((double)(long long)*a * inv);
     }
-};
-
-template <> struct SweepAcc<double> {
-    using W = double;
-    static constexpr bool kFixed = false;
-    __device__ static inline void add(W *a, int im, double cr, double ci) {
-        atomicAdd(a, cr);
-        atomicAdd(a + im, ci);
-    }
-    __device__ static inline double get(const W *a, double) { return *a; }
 };
 
 // Staged nodes of one chunk: ring slot and in-column offsets packed into one
@@ -146,7 +147,6 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     constexpr int NPW = 64 / M2;
     constexpr bool WN = sweep_wave_node(M2, !GW);  // one node per wavefront
     constexpr int SP = sweep_plane_stride(M2, WN);                   // words per ring plane
-    constexpr double kLimit = 1073741824.0;  // 2^30: bound of a scaled c64 contribution
     scr += blockIdx.y * sstride;              // channel
     const C *fsorted = scr + sg.sorted_off;
     const double *part = reinterpret_cast<const double *>(scr + sg.part_off);
@@ -164,12 +164,25 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     const int R = sg.R, Q0 = g.Q[0];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+    // the most contributions a grid plane of the segment receives: a plane takes nodes
+    // of at most W = 1 + ceil((taps - 1) / Q_0) consecutive tiles of the column
+    __shared__ int seg_nodes;
+    if (tid == 0) {
+        amax_bits = 0ull;
+        seg_nodes = 0;
+    }
     if (tid < nt) {
         const int tile = ((tb + tid) * g.T[1] + t1) * g.T[2] + t2;
         seg_beg[tid] = key_start[tile << 3];
         seg_end[tid] = key_start[(tile + 1) << 3];
     }
-    if (tid == 0) amax_bits = 0ull;
+    __syncthreads();
+    if (tid < nt) {
+        const int W = 1 + (M2 - 1 + Q0 - 1) / Q0;
+        int sum = 0;
+        for (int j = max(0, tid - W + 1); j <= tid; ++j) sum += seg_end[j] - seg_beg[j];
+        atomicMax(&seg_nodes, sum);
+    }
     // the transform's largest |Re|, |Im| from the gather's block maxima
     double pm = 0.0;
     for (int i = tid; i < kSweepParts; i += NT) pm = fmax(pm, part[i]);
@@ -181,12 +194,9 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     __syncthreads();
     const double amax_d = __longlong_as_double((long long)amax_bits);
     const bool poisoned = isinf(amax_d);  // a non-finite value in fhat
-    T scale = (T)1;
-    if (A::kFixed && amax_d > 0.0 && !poisoned) {
-        int e;
-        (void)frexp(kLimit / (amax_d * (double)wmax_prod), &e);
-        scale = (T)ldexp(1.0, e - 1);
-    }
+    const bool fixed = sizeof(T) == 4 || seg_nodes <= kSweepFixedNodes;
+    const T scale = amax_d > 0.0 && !poisoned && fixed
+                        ? FixedPoint<T>::scale(amax_d * (double)wmax_prod, seg_nodes) : (T)1;
     const double inv = 1.0 / (double)scale;
 
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
@@ -251,61 +261,67 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             next_chunk(ct, cc0);
             if (ct < nt) load_chunk(ct, cc0);
             else ct = -1;
-            if constexpr (WN) {
-                // one node per wavefront: lane (grp, li) adds the taps (grp, b, li), b = 0..7
-                for (int k = wave; k < n; k += NT / 64) {
-                    const int pk = st.pk[k];
+            // the accumulation, with the segment's kind of sum fixed at compile time
+            auto accumulate = [&](auto fixed_tag) {
+                constexpr bool kFixed = decltype(fixed_tag)::value;
+                if constexpr (WN) {
+                    // one node per wavefront: lane (grp, li) adds the taps (grp, b, li), b = 0..7
+                    for (int k = wave; k < n; k += NT / 64) {
+                        const int pk = st.pk[k];
+                        const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
+                        const T z0 = st.fr[0][k] - (T)0.5, z1 = st.fr[1][k] - (T)0.5,
+                                z2 = st.fr[2][k] - (T)0.5;
+                        T h0 = lw.cf[0][M2], h1 = lw.cf[1][M2], h2 = lw.cf[2][M2];
+    #pragma unroll
+                        for (int z = M2 - 1; z >= 0; --z) {
+                            h0 = fma(h0, z0, lw.cf[0][z]);
+                            h1 = fma(h1, z1, lw.cf[1][z]);
+                            h2 = fma(h2, z2, lw.cf[2][z]);
+                        }
+                        // the products in the order of the other mapping (bit-identical terms)
+                        const T ws = h2 * scale;
+                        const T pr = st.vr[k] * ws, pi = st.vi[k] * ws;
+                        const T ar = h0 * pr, ai = h0 * pi;
+                        int r = r0 + grp;
+                        if (r >= R) r -= R;
+                        W *pl = acc + r * SP + (l1 * P + l2 + li);
+    #pragma unroll
+                        for (int b = 0; b < M2; ++b) {
+                            const T wb = lane_value(h1, b);  // lane b holds axis-1 tap b
+                            A::add(pl + b * P, PP, wb * ar, wb * ai, kFixed);
+                        }
+                    }
+                } else {
+                for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
+                    const int k = base + grp;
+                    const bool valid = grp < NPW && k < n;
+                    const int ks = valid ? k : 0;
+                    const int pk = st.pk[ks];
                     const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
-                    const T z0 = st.fr[0][k] - (T)0.5, z1 = st.fr[1][k] - (T)0.5,
-                            z2 = st.fr[2][k] - (T)0.5;
-                    T h0 = lw.cf[0][M2], h1 = lw.cf[1][M2], h2 = lw.cf[2][M2];
-#pragma unroll
-                    for (int z = M2 - 1; z >= 0; --z) {
-                        h0 = fma(h0, z0, lw.cf[0][z]);
-                        h1 = fma(h1, z1, lw.cf[1][z]);
-                        h2 = fma(h2, z2, lw.cf[2][z]);
-                    }
-                    // the products in the order of the other mapping (bit-identical terms)
-                    const T ws = h2 * scale;
-                    const T pr = st.vr[k] * ws, pi = st.vi[k] * ws;
-                    const T ar = h0 * pr, ai = h0 * pi;
-                    int r = r0 + grp;
-                    if (r >= R) r -= R;
-                    W *pl = acc + r * SP + (l1 * P + l2 + li);
-#pragma unroll
-                    for (int b = 0; b < M2; ++b) {
-                        const T wb = lane_value(h1, b);  // lane b holds axis-1 tap b
-                        A::add(pl + b * P, PP, wb * ar, wb * ai);
+                    T fr[3], w[3];
+    #pragma unroll
+                    for (int d = 0; d < 3; ++d) fr[d] = st.fr[d][ks];
+                    node_weights<GW, T, 3, M2>(w, lw, fr, (long long)(c0 + ks), li, window, wp);
+                    const T ws = valid ? w[2] * scale : (T)0;
+                    const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
+                    T w0[M2], w1[M2];
+                    BcastAll<M2, 0, T>::run(w0, w[0], gbase);
+                    BcastAll<M2, 0, T>::run(w1, w[1], gbase);
+                    W *cell = acc + (l1 * P + l2 + li);
+    #pragma unroll
+                    for (int a = 0; a < M2; ++a) {
+                        int r = r0 + a;
+                        if (r >= R) r -= R;
+                        W *pl = cell + r * SP;
+                        const T ar = w0[a] * pr, ai = w0[a] * pi;
+    #pragma unroll
+                        for (int b = 0; b < M2; ++b) A::add(pl + b * P, PP, w1[b] * ar, w1[b] * ai, kFixed);
                     }
                 }
-            } else {
-            for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
-                const int k = base + grp;
-                const bool valid = grp < NPW && k < n;
-                const int ks = valid ? k : 0;
-                const int pk = st.pk[ks];
-                const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
-                T fr[3], w[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) fr[d] = st.fr[d][ks];
-                node_weights<GW, T, 3, M2>(w, lw, fr, (long long)(c0 + ks), li, window, wp);
-                const T ws = valid ? w[2] * scale : (T)0;
-                const T pr = st.vr[ks] * ws, pi = st.vi[ks] * ws;
-                T w0[M2], w1[M2];
-                BcastAll<M2, 0, T>::run(w0, w[0], gbase);
-                BcastAll<M2, 0, T>::run(w1, w[1], gbase);
-                W *cell = acc + (l1 * P + l2 + li);
-#pragma unroll
-                for (int a = 0; a < M2; ++a) {
-                    int r = r0 + a;
-                    if (r >= R) r -= R;
-                    W *pl = cell + r * SP;
-                    const T ar = w0[a] * pr, ai = w0[a] * pi;
-#pragma unroll
-                    for (int b = 0; b < M2; ++b) A::add(pl + b * P, PP, w1[b] * ar, w1[b] * ai);
                 }
-            }
-            }
+            };
+            if (sizeof(T) == 4 || fixed) accumulate(std::true_type{});
+            else if constexpr (sizeof(T) == 8) accumulate(std::false_type{});
             __syncthreads();
         }
         // the tile's Q_0 planes are complete: write them out, clear their slots
@@ -316,7 +332,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             int r = rb + kk;
             if (r >= R) r -= R;
             W *a = acc + r * SP + cell;
-            const C v = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv), A::get(a + PP, inv));
+            const C v = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv, fixed), A::get(a + PP, inv, fixed));
             a[0] = (W)0;
             a[PP] = (W)0;
             scr[((size_t)(p0 + kk) * sg.ncols + col) * PP + cell] = v;
@@ -332,7 +348,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
         int r = rh + kk;
         if (r >= R) r -= R;
         const W *a = acc + r * SP + cell;
-        halo[idx] = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv), A::get(a + PP, inv));
+        halo[idx] = poisoned ? cmake<C>(nan, nan) : cmake<C>(A::get(a, inv, fixed), A::get(a + PP, inv, fixed));
     }
 }
 

@@ -55,11 +55,11 @@ def test_2d_512(device, nodes, dt, m):
 
 
 # Default tiles of the 3-D 128^3 workload (M = 2^21): the column sweeps' (8, 16, 16) for both
-# sigma (oversampled 256^3 and 160^3) and both types; the padded-tile scheme (spread="tiled",
-# exact fixed-point sums in complex128 too) takes 8^3 tiles for complex128 at sigma = 2.
+# sigma (oversampled 256^3 and 160^3) and both types, and the padded-tile scheme's
+# (spread="tiled") for this sparse node set in complex128 at sigma = 2.
 TILE_3D = {(2.0, "c64", "auto"): (8, 16, 16), (1.25, "c64", "auto"): (8, 16, 16),
            (2.0, "c128", "auto"): (8, 16, 16), (1.25, "c128", "auto"): (8, 16, 16),
-           (2.0, "c128", "tiled"): (8, 8, 8)}
+           (2.0, "c128", "tiled"): (8, 16, 16)}
 SIGMA_DT_3D = [(2.0, "c64", "auto"), (1.25, "c64", "auto"), (2.0, "c128", "auto"),
                (1.25, "c128", "auto"), (2.0, "c128", "tiled")]
 
