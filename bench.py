@@ -310,6 +310,38 @@ def rocfft_reference(Nt, cdt, reps=20):
     return a.elapsed_time(b) / reps
 
 
+def copy_floor(stage_bytes, reps=50):
+    """The fixed cost an FFT pass cannot go below: for each pass, a plain device copy that
+    moves the pass's algorithmic bytes (half read, half written), timed alone and as a chain
+    in the passes' order, with events on the current stream (the plan's).  Returns
+    microseconds per copy (mean) and for the chain."""
+    import torch
+    bufs = []
+    for k, nbytes in stage_bytes.items():
+        n = max(1, nbytes // 8)  # float32 elements of one side
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        bufs.append((k, a, torch.empty_like(a)))
+    for _, a, b in bufs:
+        b.copy_(a)
+    torch.cuda.synchronize()
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for k, a, b in bufs:
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        out[k] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+    e0.record()
+    for _ in range(reps):
+        for _, a, b in bufs:
+            b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"copy_us": out, "chain_us": round(e0.elapsed_time(e1) * 1e3 / reps, 2)}
+
+
 def call_stats(fns, reps, flush_bytes=0):
     """Per-call milliseconds of each callable in `fns` (run in turn, `reps` times), timed
     with events on torch's current stream -- the stream the plan's kernels run on.  With
@@ -797,6 +829,20 @@ def main():
                   "ours_fwd_fft_ms": round(fwd_fft_ms, 5),
                   "note": "ours: resampling correction + pruned FFT passes of one forward "
                           "transform; torch.fft.fftn (rocFFT): plain unpruned FFT of the grid"}
+    # the FFT passes against plain copies of their bytes (the launch and first-load floor
+    # of a chain of kernels of that size)
+    fft_floor = None
+    if not args.profile_only:
+        fft_keys = [k for k in ("fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0",
+                                "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv")
+                    if k in avg_ms and k in algo]
+        fl = copy_floor({k: algo[k] for k in fft_keys})
+        fft_floor = {"passes_us": {k: round(avg_ms[k] * 1e3, 2) for k in fft_keys},
+                     "passes_total_us": round(sum(avg_ms[k] for k in fft_keys) * 1e3, 2),
+                     "copy_us": fl["copy_us"], "copy_chain_us": fl["chain_us"],
+                     "note": "each FFT pass against a plain device copy (torch) moving its "
+                             "algorithmic bytes; chain: the copies back to back in the "
+                             "passes' order"}
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "pts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
@@ -815,6 +861,7 @@ def main():
         "kernels": kernels,
         "back_to_back_ms": {k: round(v, 5) for k, v in b2b.items()},
         "rocfft_reference": rocfft,
+        "fft_floor": fft_floor,
         "lds_roof": lds_roof,
     }
 

@@ -434,7 +434,12 @@ template <typename T, int CH> struct InterpStage {
     int idx[CH];  // caller's node index
 };
 
-template <typename T, int M2, bool GW>
+// ISO: every axis has the same window (the same shape parameter), so a lane keeps one
+// axis's tap coefficients instead of three (complex128: 221 instead of 255 VGPRs, the
+// most two waves per SIMD allow).  The next tile's prefetched planes are held as arrays
+// of reals: as an array of complex values the compiler placed them in scratch memory
+// (0.6 GB of writes per call on the 3-D 128^3 workload).
+template <typename T, int M2, bool GW, bool ISO>
 __global__ void __launch_bounds__(interp_sweep_threads<T>())
     k_interp_sweep(const cplx<T> *__restrict__ grid, Geom g, SweepGeom sg,
                    const NodeRec<T, 3> *__restrict__ nodes, const int *__restrict__ perm,
@@ -500,7 +505,7 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
     __syncthreads();
 
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
-    LaneWindow<T, 3, M2> lw;
+    LaneWindow<T, ISO ? 1 : 3, M2> lw;
     lw.load(coef, li, wp.m);
 
     auto next_chunk = [&](int &t, int &c0) {
@@ -534,14 +539,16 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
         // the planes the next tile adds, into registers
         const int pn = (tb + t) * Q0 + R;
         const bool more = t + 1 < nt;
-        C pre[PF];
+        T pre_x[PF], pre_y[PF];  // (real and imaginary parts: kept in registers)
         if (more) {
 #pragma unroll
             for (int u = 0; u < PF; ++u) {
                 const int idx = u * NT + tid;
                 const int ic = idx < Q0 * PP ? idx : 0;
                 const int kk = ic / PP, q = ic - kk * PP;
-                pre[u] = grid[src(pn + kk, q)];
+                const C v = grid[src(pn + kk, q)];
+                pre_x[u] = v.x;
+                pre_y[u] = v.y;
             }
         }
         while (ct == t) {
@@ -566,7 +573,14 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
                 T fr[3], w[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) fr[d] = st.fr[d][ks];
-                node_weights<GW, T, 3, M2>(w, lw, fr, (long long)(c0 + ks), li, window, wp);
+                if constexpr (ISO) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        w[d] = tap_weight<T, M2>(lw.cf[0], fr[d], li, NFFT_WINDOW_POLY, wp.beta[d],
+                                                 wp.inv_peak[d], nullptr, 0, wp.m);
+                } else {
+                    node_weights<GW, T, 3, M2>(w, lw, fr, (long long)(c0 + ks), li, window, wp);
+                }
                 T w0[M2], w1[M2];
                 BcastAll<M2, 0, T>::run(w0, w[0], gbase);
                 BcastAll<M2, 0, T>::run(w1, w[1], gbase);
@@ -609,7 +623,7 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
                 const int idx = u * NT + tid;
                 if (idx < Q0 * PP) {
                     const int kk = idx / PP, q = idx - kk * PP;
-                    ring[((pn + kk) % R) * PP + q] = pre[u];
+                    ring[((pn + kk) % R) * PP + q] = cmake<C>(pre_x[u], pre_y[u]);
                 }
             }
             __syncthreads();
@@ -623,7 +637,9 @@ hipError_t run_interp_sweep(const nfft_plan_s &p, const void *grid, void *fhat, 
     const SweepGeom &sg = p.sweep;
     const size_t shm = (size_t)sg.R * sweep_plane_cells(p.geom.taps) * sizeof(cplx<T>);
     const bool gw = p.window != NFFT_WINDOW_POLY;
-    auto kern = gw ? k_interp_sweep<T, M2, true> : k_interp_sweep<T, M2, false>;
+    const bool iso = !gw && kb_beta(p, 1) == kb_beta(p, 0) && kb_beta(p, 2) == kb_beta(p, 0);
+    auto kern = gw ? k_interp_sweep<T, M2, true, false>
+                   : iso ? k_interp_sweep<T, M2, false, true> : k_interp_sweep<T, M2, false, false>;
     hipError_t e = allow_lds(kern, shm, sizeof(InterpStage<T, interp_sweep_chunk<T>()>) + 1024);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(sg.ncols * sg.nsc, K), dim3(interp_sweep_threads<T>()), shm, s,
