@@ -60,7 +60,7 @@ typedef enum {
 enum {
     NFFT_OK = 0,
     NFFT_ERR_ARG = -1,         /* invalid argument (null pointer, bad size, sigma <= 1, ...) */
-    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (D > 4, ...) */
+    NFFT_ERR_UNSUPPORTED = -2, /* valid per the paper but outside this library (D > 6, ...) */
     NFFT_ERR_NOMEM = -3,       /* device allocation failed */
     NFFT_ERR_HIP = -4,         /* a HIP runtime call failed (no device, launch failure, ...) */
     NFFT_ERR_NODES = -5,       /* a node coordinate is NaN or infinite */
@@ -90,12 +90,13 @@ typedef struct {
                              tiles per axis.  D = 4: must divide Ntilde_d; the spreading
                              workgroup of a tile reads at most 81 tiles' nodes, the product
                              over the axes of min(Ntilde_d/Q_d, 2 + (taps-2)/Q_d), else
-                             NFFT_ERR_UNSUPPORTED. */
+                             NFFT_ERR_UNSUPPORTED.  D >= 5: must be all 0 (automatic
+                             tiles), else NFFT_ERR_UNSUPPORTED. */
     int window;           /* NFFT_WINDOW_POLY (default), _DIRECT, _TENSOR, _LINEAR or _FULL */
     int max_block_nodes;  /* cap on nodes per resampling work item (a tile's nodes are cut
                              into items of at most this many), 0 = automatic (D <= 3: 1024,
                              512 in 1-D/2-D when the tiles hold <= 512 nodes on average;
-                             16 for D = 4, whose interpolation takes one wavefront per
+                             16 for D >= 4, whose interpolation takes one wavefront per
                              node) */
     int wide;             /* 1: (2m+2)^D-point stencil with the untruncated window, sampled
                              beyond its truncation interval (the alternative of subsection
@@ -119,12 +120,14 @@ enum { NFFT_SPREAD_AUTO = 0, NFFT_SPREAD_TILED = 1, NFFT_SPREAD_SWEEP = 2 };
 /*
  * Create a plan (Algorithm 1/2 inputs D, m, N, Ntilde and the nodes).
  *   out    receives the plan handle (unchanged on error)
- *   D      1, 2, 3 or 4.  D <= 3 resamples through LDS tiles of the grid; D = 4
+ *   D      1 .. 6.  D <= 3 resamples through LDS tiles of the grid; D >= 4
  *          (whose tile plus stencil halo does not fit in LDS) interpolates from
  *          the grid in device memory, one wavefront per node, and spreads
  *          tile by tile: a workgroup owns one tile and adds every node whose
  *          stencil reaches it in exact fixed point (no global atomics, no
- *          scratch, bitwise reproducible).
+ *          scratch, bitwise reproducible).  D >= 4 needs D * taps <= 128
+ *          (taps = 2m, or 2m + 2 with the wide stencil), else
+ *          NFFT_ERR_UNSUPPORTED; D >= 5 takes its tiles automatically.
  *   N      host array of D sizes >= 2 (even or odd)
  *   M      number of nodes, >= 0 (M = 0 is allowed)
  *   x      device pointer to the nodes (may be NULL when M == 0)

@@ -30,7 +30,7 @@
 #define M_PI 3.14159265358979323846
 #endif
 
-#define MAXD 4
+#define MAXD 6
 
 #ifdef _OPENMP
 #include <omp.h>

@@ -17,8 +17,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # the longest compilations first (they run in parallel)
-SOURCES = ["resample.hip", "batch.hip", "spread_sweep.hip", "fft.hip", "plan.cpp", "runtime.cpp",
-           "precompute.hip", "binsort.hip", "calibrate.hip"]
+SOURCES = ["resample.hip", "resample_nd.hip", "batch.hip", "spread_sweep.hip", "fft.hip",
+           "plan.cpp", "runtime.cpp", "precompute.hip", "binsort.hip", "calibrate.hip"]
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

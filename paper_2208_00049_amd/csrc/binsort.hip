@@ -189,6 +189,8 @@ hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int 
         case 2: f ? keys_t<float, 2>(p, x, keys, counts, bad, s) : keys_t<double, 2>(p, x, keys, counts, bad, s); break;
         case 3: f ? keys_t<float, 3>(p, x, keys, counts, bad, s) : keys_t<double, 3>(p, x, keys, counts, bad, s); break;
         case 4: f ? keys_t<float, 4>(p, x, keys, counts, bad, s) : keys_t<double, 4>(p, x, keys, counts, bad, s); break;
+        case 5: f ? keys_t<float, 5>(p, x, keys, counts, bad, s) : keys_t<double, 5>(p, x, keys, counts, bad, s); break;
+        case 6: f ? keys_t<float, 6>(p, x, keys, counts, bad, s) : keys_t<double, 6>(p, x, keys, counts, bad, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -338,6 +340,8 @@ hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int 
         case 2: f ? gather_t<float, 2>(p, x, s) : gather_t<double, 2>(p, x, s); break;
         case 3: f ? gather_t<float, 3>(p, x, s) : gather_t<double, 3>(p, x, s); break;
         case 4: f ? gather_t<float, 4>(p, x, s) : gather_t<double, 4>(p, x, s); break;
+        case 5: f ? gather_t<float, 5>(p, x, s) : gather_t<double, 5>(p, x, s); break;
+        case 6: f ? gather_t<float, 6>(p, x, s) : gather_t<double, 6>(p, x, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -567,7 +567,7 @@ __device__ inline void fft_contig_body(const cplx<T> *src, cplx<T> *dst, const F
     const T *declast = dec.d[D - 1];
 
     // outer indices i_0..i_{D-2} of the line (the last fastest), its grid row and f row
-    int iv[kMaxD] = {0, 0, 0, 0};
+    int iv[kMaxD] = {};
     {
         int rem = line_id;
         for (int d = D - 2; d >= 0; --d) {

@@ -9,7 +9,7 @@
 
 namespace nfft {
 
-constexpr int kMaxD = 4;
+constexpr int kMaxD = 6;
 constexpr int kMaxRadixPasses = 16;
 constexpr int kResampleThreads = 256;  // workgroup size of the resampling kernels
 
@@ -45,16 +45,16 @@ struct Geom {
     int lo;          // stencil points before the node's cell: taps/2 - 1
 };
 
-// Tile-owner spreading (D = 4): a workgroup owns one tile and visits the nodes
+// Tile-owner spreading (D >= 4): a workgroup owns one tile and visits the nodes
 // whose stencil reaches into it.  A node binned in tile p - b along axis d can
 // reach tile p only for b <= 1 + (taps - 2) / Q_d: the candidate tiles per axis
 // are r_d = min(T_d, 2 + (taps - 2) / Q_d), their product at most
-// kOwnerMaxTiles (tile edges >= taps / 2 keep r_d <= 3).
+// owner_max_tiles(D) = 3^D (tile edges >= taps / 2 keep r_d <= 3).
 __host__ __device__ inline int owner_reach(const Geom &g, int d) {
     const int r = 2 + (g.taps - 2) / g.Q[d];
     return r < g.T[d] ? r : g.T[d];
 }
-constexpr int kOwnerMaxTiles = 81;  // candidate tiles of one workgroup (3^4)
+constexpr int owner_max_tiles(int D) { return D <= 0 ? 1 : 3 * owner_max_tiles(D - 1); }
 // Candidate nodes staged per round by the tile-owner kernels (their box weights
 // take at most about 32 KiB in c64, 16 KiB in c128, whose accumulator tile is
 // twice as large), and the kernels' static LDS: staged candidates (sorted
@@ -69,7 +69,7 @@ constexpr int owner_chunk_n(int D, int taps, int rs) {
 }
 constexpr size_t owner_static_lds(int D, int taps, int rs) {
     return (size_t)owner_chunk_n(D, taps, rs) * (4 * (1 + 3 * D) + (size_t)rs * (D + 2 + D * taps)) +
-           4 * (2 * kOwnerMaxTiles + 3) + 256;
+           4 * (2 * owner_max_tiles(D) + 3) + 256;
 }
 // Workgroup of the tile-owner spreading kernel: 1024 threads, 16 wavefronts per
 // CU (the tile's accumulators take most of the LDS, one workgroup fits per CU),
@@ -388,6 +388,11 @@ hipError_t launch_node_grad(const nfft_plan_s &p, const void *a, const void *v, 
 // K channels: grids at stride G, fhat at stride M, padded tiles at stride pad_elems()
 hipError_t launch_interp(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
                          int K = 1);
+// resample_nd.hip: the resampling kernels of D = 4, 5, 6 (K channels)
+hipError_t launch_interp_nd(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s,
+                            int K);
+hipError_t launch_spread_nd(const nfft_plan_s &p, const void *fhat, void *grid, hipStream_t s,
+                            int K);
 // derivative-of-window interpolation, D <= 3 with the polynomial window: dfhat D x M
 hipError_t launch_interp_deriv(const nfft_plan_s &p, const void *grid, void *dfhat, hipStream_t s);
 // merge = false: only the padded tiles are produced (the next pass merges them)

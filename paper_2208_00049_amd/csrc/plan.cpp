@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kMaxM = 10;
 constexpr size_t kLdsBudget = 65536;
+constexpr int kOptionTiles = 4;  // tile edges nfft_options holds
 // Default cap on a work item's nodes, per D.  1-D/2-D: 1024, or 512 when the
 // tiles hold at most 512 nodes on average -- then only locally dense tiles (a
 // radial trajectory's centre) are split, and smaller pieces balance them better,
@@ -28,7 +29,7 @@ constexpr size_t kLdsBudget = 65536;
 // a padded tile to every halo merge).  3-D tiles hold ~512 nodes on average at
 // sigma = 2 and keep 1024.  D = 4 interpolates one node per wavefront, so small
 // items spread a tile's nodes over many workgroups.
-constexpr int kDefaultBlockNodes[5] = {0, 1024, 1024, 1024, 16};
+constexpr int kDefaultBlockNodes[kMaxD + 1] = {0, 1024, 1024, 1024, 16, 16, 16};
 constexpr int kSparseBlockNodes = 512;
 constexpr int kMaxChannels = 65535;  // channels of one multi-channel call (grid y dimension)
 
@@ -66,14 +67,18 @@ size_t node_rec_size(nfft_dtype t, int D) {
             case 1: return sizeof(NodeRec<float, 1>);
             case 2: return sizeof(NodeRec<float, 2>);
             case 3: return sizeof(NodeRec<float, 3>);
-            default: return sizeof(NodeRec<float, 4>);
+            case 4: return sizeof(NodeRec<float, 4>);
+            case 5: return sizeof(NodeRec<float, 5>);
+            default: return sizeof(NodeRec<float, 6>);
         }
     }
     switch (D) {
         case 1: return sizeof(NodeRec<double, 1>);
         case 2: return sizeof(NodeRec<double, 2>);
         case 3: return sizeof(NodeRec<double, 3>);
-        default: return sizeof(NodeRec<double, 4>);
+        case 4: return sizeof(NodeRec<double, 4>);
+        case 5: return sizeof(NodeRec<double, 5>);
+        default: return sizeof(NodeRec<double, 6>);
     }
 }
 
@@ -142,33 +147,33 @@ int pick_edge(int64_t Nt, int want, int taps) {
     return 0;
 }
 
-// D = 4: a spreading workgroup owns one tile (its fixed-point accumulators in
-// LDS) and reads the nodes of at most kOwnerMaxTiles
-// tiles, which tile edges >= taps/2 guarantee.  A tile edge is any divisor of
-// Nt_d.  Default: per axis the smallest divisor >= max(8, taps/2), then the
-// largest edge shrinks (to a smaller divisor >= taps/2) until the tile fits the
-// workgroup LDS `budget`.
-int choose_tiles_4d(const int64_t *Nt, int taps, nfft_dtype dt, const int *req, size_t budget,
-                    int *Q) {
+// D >= 4: a spreading workgroup owns one tile (its fixed-point accumulators in
+// LDS) and reads the nodes of at most owner_max_tiles(D) = 3^D tiles, which tile
+// edges >= taps/2 guarantee.  A tile edge is any divisor of Nt_d.  Default: per axis
+// the smallest divisor >= max(8, taps/2), then the largest edge shrinks (to a
+// smaller divisor >= taps/2) until the tile fits the workgroup LDS `budget`.
+// req: requested edges (D = 4 only; NULL or all zero: automatic).
+int choose_tiles_4d(int D, const int64_t *Nt, int taps, nfft_dtype dt, const int *req,
+                    size_t budget, int *Q) {
     const size_t cs = csize(dt);
-    const size_t stat = owner_static_lds(4, taps, (int)rsize(dt));
+    const size_t stat = owner_static_lds(D, taps, (int)rsize(dt));
     auto fits = [&](const int *q) {
         size_t cells = 1;
-        for (int d = 0; d < 4; ++d) cells *= (size_t)q[d];
+        for (int d = 0; d < D; ++d) cells *= (size_t)q[d];
         return cells * owner_cell_bytes((int)cs) + stat <= budget;
     };
     auto reach_ok = [&](const int *q) {
         Geom g{};
         g.taps = taps;
         int nb = 1;
-        for (int d = 0; d < 4; ++d) {
+        for (int d = 0; d < D; ++d) {
             g.Q[d] = q[d];
             g.T[d] = (int)(Nt[d] / q[d]);
             nb *= owner_reach(g, d);
         }
-        return nb <= kOwnerMaxTiles;
+        return nb <= owner_max_tiles(D);
     };
-    if (req && (req[0] || req[1] || req[2] || req[3])) {
+    if (D == 4 && req && (req[0] || req[1] || req[2] || req[3])) {
         for (int d = 0; d < 4; ++d) {
             if (req[d] < 1 || Nt[d] % req[d]) return NFFT_ERR_ARG;
             Q[d] = req[d];
@@ -176,7 +181,7 @@ int choose_tiles_4d(const int64_t *Nt, int taps, nfft_dtype dt, const int *req, 
         return reach_ok(Q) && fits(Q) ? NFFT_OK : NFFT_ERR_UNSUPPORTED;
     }
     const int lo = std::max(1, taps / 2);
-    for (int d = 0; d < 4; ++d) {
+    for (int d = 0; d < D; ++d) {
         Q[d] = (int)Nt[d];
         for (int q = std::max(8, lo); q < Nt[d]; ++q)
             if (Nt[d] % q == 0) {
@@ -186,7 +191,7 @@ int choose_tiles_4d(const int64_t *Nt, int taps, nfft_dtype dt, const int *req, 
     }
     while (!fits(Q)) {
         int best = -1, bq = 0;
-        for (int d = 0; d < 4; ++d) {
+        for (int d = 0; d < D; ++d) {
             int q = Q[d] - 1;
             while (q >= lo && Nt[d] % q) --q;
             if (q >= lo && (best < 0 || Q[d] > Q[best])) {
@@ -363,6 +368,8 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
     if (m > kMaxM) return NFFT_ERR_UNSUPPORTED;
     if (!(sigma > 1.0) || !isfinite(sigma) || sigma > 16.0) return NFFT_ERR_ARG;
     if (dtype != NFFT_C64 && dtype != NFFT_C128) return NFFT_ERR_ARG;
+    // D >= 4: a wavefront holds a node's D x taps weight table, at most two entries a lane
+    if (D >= 4 && D * (2 * m + (opts && opts->wide ? 2 : 0)) > 128) return NFFT_ERR_UNSUPPORTED;
     int64_t G = 1;
     for (int d = 0; d < D; ++d) {
         if (N[d] < 2) return NFFT_ERR_ARG;
@@ -381,8 +388,12 @@ int validate(int D, const int64_t *N, int64_t M, const void *x, int m, double si
         if (opts->spread < NFFT_SPREAD_AUTO || opts->spread > NFFT_SPREAD_SWEEP) return NFFT_ERR_ARG;
         for (int i = 0; i < 2; ++i)
             if (opts->reserved[i]) return NFFT_ERR_ARG;
-        for (int d = 0; d < kMaxD; ++d)
+        for (int d = 0; d < kOptionTiles; ++d)
             if (opts->tile[d] < 0 || (d >= D && opts->tile[d] != 0)) return NFFT_ERR_ARG;
+        // the options hold four tile edges: D >= 5 plans take their tiles automatically
+        if (D > kOptionTiles)
+            for (int d = 0; d < kOptionTiles; ++d)
+                if (opts->tile[d]) return NFFT_ERR_UNSUPPORTED;
     }
     return NFFT_OK;
 }
@@ -562,8 +573,9 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         int dev_lds = 0;
         TRY(hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
         p->lds_limit = dev_lds;
-        int Q[kMaxD] = {1, 1, 1, 1};
-        const int *req = opts ? opts->tile : nullptr;
+        int Q[kMaxD];
+        for (int d = 0; d < kMaxD; ++d) Q[d] = 1;
+        const int *req = opts && D <= kOptionTiles ? opts->tile : nullptr;
         int trc;
         const int smode = opts ? opts->spread : NFFT_SPREAD_AUTO;
         if (D == 3 && smode != NFFT_SPREAD_TILED &&
@@ -571,8 +583,8 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
             trc = NFFT_OK;
         } else if (D == 3 && smode == NFFT_SPREAD_SWEEP) {
             trc = NFFT_ERR_UNSUPPORTED;
-        } else if (D == 4) {
-            trc = choose_tiles_4d(p->Nt, taps, dtype, req, (size_t)dev_lds, Q);
+        } else if (D >= 4) {
+            trc = choose_tiles_4d(D, p->Nt, taps, dtype, req, (size_t)dev_lds, Q);
         } else {
             // sparse 3-D node sets (under 1/4 node per grid point, e.g. sigma = 2 with
             // M = |I_N|) take the larger 8 x 16 x 16 tiles that need the device's whole

@@ -225,12 +225,16 @@ hipError_t launch_window_tables(const nfft_plan_s &p, hipStream_t s) {
         if (p.D == 1) NFFT_WT(float, 1);
         else if (p.D == 2) NFFT_WT(float, 2);
         else if (p.D == 3) NFFT_WT(float, 3);
-        else NFFT_WT(float, 4);
+        else if (p.D == 4) NFFT_WT(float, 4);
+        else if (p.D == 5) NFFT_WT(float, 5);
+        else NFFT_WT(float, 6);
     } else {
         if (p.D == 1) NFFT_WT(double, 1);
         else if (p.D == 2) NFFT_WT(double, 2);
         else if (p.D == 3) NFFT_WT(double, 3);
-        else NFFT_WT(double, 4);
+        else if (p.D == 4) NFFT_WT(double, 4);
+        else if (p.D == 5) NFFT_WT(double, 5);
+        else NFFT_WT(double, 6);
     }
 #undef NFFT_WT
     return hipGetLastError();

@@ -1,5 +1,5 @@
 // Instantiation and dispatch of the resampling kernels over (type, D, 2m).
-#include "resample_4d.hpp"
+#include "resample_impl.hpp"
 
 namespace nfft {
 
@@ -27,7 +27,9 @@ static hipError_t interp_t(const nfft_plan_s &p, const void *grid, void *fhat, h
         case 1: NFFT_DISPATCH_M(run_interp, T, 1, p, grid, fhat, s, K)
         case 2: NFFT_DISPATCH_M(run_interp, T, 2, p, grid, fhat, s, K)
         case 3: NFFT_DISPATCH_M(run_interp, T, 3, p, grid, fhat, s, K)
-        case 4: NFFT_DISPATCH_M(run_interp_node, T, 4, p, grid, fhat, s, K)
+        case 4:
+        case 5:
+        case 6: return launch_interp_nd(p, grid, fhat, s, K);
         default: return hipErrorInvalidValue;
     }
 }
@@ -50,7 +52,9 @@ static hipError_t spread_t(const nfft_plan_s &p, const void *fhat, void *grid, h
         case 1: NFFT_DISPATCH_M(run_spread, T, 1, p, fhat, grid, s, merge, K, pad)
         case 2: NFFT_DISPATCH_M(run_spread, T, 2, p, fhat, grid, s, merge, K, pad)
         case 3: NFFT_DISPATCH_M(run_spread, T, 3, p, fhat, grid, s, merge, K, pad)
-        case 4: NFFT_DISPATCH_M(run_spread_owner, T, 4, p, fhat, grid, s, K)
+        case 4:
+        case 5:
+        case 6: return launch_spread_nd(p, fhat, grid, s, K);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,6 +1,6 @@
-// Resampling kernels for D = 4 (paper, step 3 of Algorithm 1 and step 1 of
+// Resampling kernels for D >= 4 (paper, step 3 of Algorithm 1 and step 1 of
 // Algorithm 2, with the dimension-agnostic tensor-product window of subsection
-// "Direct NFFT").
+// "Direct NFFT"); instantiated for D = 4, 5 and 6.
 //
 // The tiled kernels of D <= 3 give a work item its tile plus the (taps-1)-wide
 // trailing halo.  In four dimensions that box has (Q + taps - 1)^4 cells, which
@@ -380,10 +380,10 @@ __global__ void __launch_bounds__(kOwnerThreads)
     constexpr int SL = 2 * FP::kSlots;  // accumulator slots per grid point
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ OwnerStage<T, D, M2> st;
-    __shared__ int nb_begin[kOwnerMaxTiles], nb_pre[kOwnerMaxTiles + 1];
+    __shared__ int nb_begin[owner_max_tiles(D)], nb_pre[owner_max_tiles(D) + 1];
     __shared__ unsigned long long amax_bits;  // bits of a non-negative double
     __shared__ int next_k[2];                 // candidate counters of even and odd rounds
-    static_assert(sizeof(OwnerStage<T, D, M2>) + sizeof(int) * (2 * kOwnerMaxTiles + 3) + 8 <=
+    static_assert(sizeof(OwnerStage<T, D, M2>) + sizeof(int) * (2 * owner_max_tiles(D) + 3) + 8 <=
                       owner_static_lds(D, M2, (int)sizeof(T)),
                   "staged candidates larger than the LDS the plan reserves for them");
     grid += blockIdx.y * gstride;
@@ -458,11 +458,16 @@ __global__ void __launch_bounds__(kOwnerThreads)
 template <typename T, int D, int M2>
 hipError_t run_interp_node(const nfft_plan_s &p, const void *grid, void *fhat, hipStream_t s, int K) {
     if (p.nsub == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_interp_node<T, D, M2>), dim3(p.nsub, K), dim3(kResampleThreads), 0, s,
-                       (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
-                       p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
-                       (long long)p.G, (long long)p.M);
-    return hipGetLastError();
+    // the node's weight table is held by the lanes of a wavefront, two entries each
+    if constexpr (D * M2 > 128) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_interp_node<T, D, M2>), dim3(p.nsub, K), dim3(kResampleThreads), 0, s,
+                           (const cplx<T> *)grid, p.geom, (const NodeRec<T, D> *)p.nodes, p.perm,
+                           p.subs, (const T *)p.coef, p.window, win_params<T>(p), (cplx<T> *)fhat,
+                           (long long)p.G, (long long)p.M);
+        return hipGetLastError();
+    }
 }
 
 // Every grid point is written (zeros where no node reaches), so the grid needs

@@ -537,7 +537,8 @@ int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M,
     if (vrc != NFFT_OK) return vrc;
     nfft_options base{};
     if (opts) base = *opts;
-    if (base.tile[0] || base.tile[1] || base.tile[2] || base.tile[3])  // tiles fixed by the caller
+    // tiles fixed by the caller, or D >= 5 (whose tiles are always automatic)
+    if (base.tile[0] || base.tile[1] || base.tile[2] || base.tile[3] || D > 4)
         return nfft_plan_create_ex(out, D, N, M, x, m, sigma, dtype, opts, stream);
     std::vector<std::vector<int>> tiles;
     if (D == 1) tiles = {{128}, {256}, {512}, {1024}};
@@ -605,7 +606,7 @@ int nfft_plan_create_tuned(nfft_plan_t *out, int D, const int64_t *N, int64_t M,
         try_one(o);
     }
     if (best && rc == NFFT_OK && base.max_block_nodes == 0) {
-        int bt[4] = {0, 0, 0, 0};
+        int bt[nfft::kMaxD] = {};
         (void)nfft_plan_info(best, nullptr, nullptr, bt);
         for (int cap : {256, 512, 1024, 2048}) {
             if (rc != NFFT_OK) break;

@@ -39,7 +39,7 @@ int main(void) {
     nfft_plan_t q = 0;
     if (nfft_plan_create(&q, 0, N, 10, fake, 4, 2.0, NFFT_C64, 0) != NFFT_ERR_ARG) ++fails;
     if (nfft_plan_create(&q, 2, N, 10, fake, 4, 1.0, NFFT_C64, 0) != NFFT_ERR_ARG) ++fails;
-    if (nfft_plan_create(&q, 5, N, 10, fake, 4, 2.0, NFFT_C64, 0) != NFFT_ERR_UNSUPPORTED) ++fails;
+    if (nfft_plan_create(&q, 7, N, 10, fake, 4, 2.0, NFFT_C64, 0) != NFFT_ERR_UNSUPPORTED) ++fails;
     if (q) ++fails;
     for (int k = 1; k < 64; ++k) {
         nfft_plan_t p = 0;

@@ -50,10 +50,11 @@ FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(D=0), -1), (dict(D=5, N=(8,) * 5), -2), (dict(N=None), -1),
+    (dict(D=0), -1), (dict(D=7, N=(8,) * 7), -2), (dict(N=None), -1),
     (dict(M=-1), -1), (dict(M=5, x=None), -1), (dict(m=0, x=FAKE), -1), (dict(m=11, x=FAKE), -2),
     (dict(sigma=1.0, x=FAKE), -1), (dict(sigma=float("nan"), x=FAKE), -1),
-    (dict(dtype=7, x=FAKE), -1), (dict(D=5, N=(8,) * 5, x=FAKE), -2), (dict(N=(1, 64), x=FAKE), -1),
+    (dict(dtype=7, x=FAKE), -1), (dict(D=7, N=(8,) * 7, x=FAKE), -2), (dict(N=(1, 64), x=FAKE), -1),
+    (dict(D=6, N=(8,) * 6, m=5, x=FAKE), -1),  # Ntilde = 16 < twice the stencil of m = 5
     (dict(D=4, N=(8, 8, 8, 1), x=FAKE), -1), (dict(D=4, N=(8, 8, 8, 4), m=4, x=FAKE), -1),
     (dict(N=(4, 64), m=4, x=FAKE), -1), (dict(N=(4096, 64), x=FAKE), -2),
 ])
@@ -77,6 +78,12 @@ def test_option_errors(lib):
     o = _lib.Options()
     o.tile[3] = 8
     assert _create(lib, M=0, opts=ctypes.byref(o))[0] == -1
+    o = _lib.Options()
+    o.tile[0] = 8  # the options' four tile edges do not reach D = 5: automatic tiles only
+    assert _create(lib, D=5, N=(8,) * 5, M=0, opts=ctypes.byref(o))[0] == -2
+    o = _lib.Options()
+    o.wide = 1  # D >= 4: D * taps <= 128 (6 * 22 is not)
+    assert _create(lib, D=6, N=(64,) * 6, M=0, m=10, opts=ctypes.byref(o))[0] == -2
     o = _lib.Options()
     o.window = _lib.NFFT_WINDOW_FULL  # (2m)^D products per node: D <= 2 only
     assert _create(lib, D=3, N=(16, 16, 16), M=0, opts=ctypes.byref(o))[0] == -2
@@ -115,8 +122,8 @@ def test_batch_and_tuner_argument_errors(lib):
     # sigma <= 1, D > 4, reps < 1
     assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(1.0), 0,
                                       None, 2, None, ctypes.byref(ms)) == -1
-    N5 = (ctypes.c_int64 * 5)(8, 8, 8, 8, 8)
-    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 5, N5, 0, None, 4, ctypes.c_double(2.0),
+    N7 = (ctypes.c_int64 * 7)(8, 8, 8, 8, 8, 8, 8)
+    assert lib.nfft_plan_create_tuned(ctypes.byref(out), 7, N7, 0, None, 4, ctypes.c_double(2.0),
                                       0, None, 2, None, ctypes.byref(ms)) == -2
     assert lib.nfft_plan_create_tuned(ctypes.byref(out), 2, N, 0, None, 4, ctypes.c_double(2.0), 0,
                                       None, 0, None, ctypes.byref(ms)) == -1

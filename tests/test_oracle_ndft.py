@@ -58,7 +58,8 @@ def test_golden_hand_values():
             assert abs(y[int(r[2])] - want) < 1e-14, (r, y[int(r[2])])
 
 
-@pytest.mark.parametrize("N", [(6,), (8,), (4, 6), (2, 4, 4), (5,), (3, 4), (3, 5, 2), (2, 3, 2, 3)])
+@pytest.mark.parametrize("N", [(6,), (8,), (4, 6), (2, 4, 4), (5,), (3, 4), (3, 5, 2), (2, 3, 2, 3),
+                               (2, 3, 2, 2, 3), (2, 2, 3, 2, 2, 2)])
 def test_bruteforce_dense_matrix(N):
     D = len(N)
     x = wl.uniform_nodes(17, D, config=90, stream=0)
@@ -70,7 +71,8 @@ def test_bruteforce_dense_matrix(N):
     assert _rel(y.reshape(-1), A.conj().T @ fh) < 1e-13
 
 
-@pytest.mark.parametrize("N", [(16,), (8, 12), (4, 6, 8), (15,), (7, 6), (3, 5, 4), (3, 4, 2, 5)])
+@pytest.mark.parametrize("N", [(16,), (8, 12), (4, 6, 8), (15,), (7, 6), (3, 5, 4), (3, 4, 2, 5),
+                               (2, 3, 4, 2, 3), (2, 2, 3, 2, 2, 3)])
 def test_equispaced_nodes_give_the_dft(N):
     """Nodes on the grid I_N / N: the NDFT is the centred DFT, the adjoint the unnormalised inverse."""
     D = len(N)

@@ -224,3 +224,19 @@ def test_four_dimensional_against_ndft(N, m, gate):
     assert _rel2(y, ndft.ndft_forward(x, f)) < gate
     assert _rel2(a, ndft.ndft_adjoint(x, fh, N)) < gate
     assert abs(np.vdot(fh, y) - np.vdot(a, f)) < 1e-13 * np.linalg.norm(fh) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("N,m,gate", [((6, 6, 6, 6, 6), 3, 3e-5), ((5, 4, 6, 4, 3), 2, 3e-3),
+                                      ((4, 4, 4, 4, 4, 4), 2, 3e-3)])
+def test_five_and_six_dimensional_against_ndft(N, m, gate):
+    """D = 5 and 6 (dimension-agnostic, subsection "Direct NFFT"): the NFFT oracle within the
+    Kaiser-Bessel gates of its m against the NDFT, and the approximate pair exactly adjoint."""
+    D = len(N)
+    x = wl.uniform_nodes(200, D, config=75, stream=0)
+    f = wl.cn01(N, config=75, stream=1)
+    fh = wl.cn01((200,), config=75, stream=2)
+    y = na.forward(x, f, m, 2.0)
+    a = na.adjoint(x, fh, N, m, 2.0)
+    assert _rel2(y, ndft.ndft_forward(x, f)) < gate
+    assert _rel2(a, ndft.ndft_adjoint(x, fh, N)) < gate
+    assert abs(np.vdot(fh, y) - np.vdot(a, f)) < 1e-13 * np.linalg.norm(fh) * np.linalg.norm(y)
