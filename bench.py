@@ -37,6 +37,7 @@ WORKLOADS = {
     "3d_n128_m2097152_uniform": dict(D=3, N=(128, 128, 128), M=2097152, nodes="uniform", config=2),
     "1d_n256_m512_uniform": dict(D=1, N=(256,), M=512, nodes="uniform", config=0),
     "4d_n16_m65536_uniform": dict(D=4, N=(16, 16, 16, 16), M=65536, nodes="uniform", config=5),
+    "5d_n8_m32768_uniform": dict(D=5, N=(8, 8, 8, 8, 8), M=32768, nodes="uniform", config=6),
     # the runtime around the plans: K channels through one node set, and a batch of 64
     # independent transforms of random sizes run as one HIP graph
     "2d_n256_radial256x256_k32": dict(D=2, N=(256, 256), M=65536, nodes="radial256", config=3,
