@@ -558,8 +558,9 @@ def bench_grad(args, w):
 
 
 def bench_batch(args, w):
-    """64 independent 2-D transforms of random sizes: one graph launch for all forwards and
-    one for all adjoints per step, against the same calls issued one after another."""
+    """64 independent 2-D transforms of random sizes: one launch per stage over all of them
+    (fused batch, replayed as a graph per direction), against the same calls issued one after
+    another."""
     import torch
     import nfft_workloads as wl
     from paper_2208_00049_amd import Batch, Plan
@@ -624,7 +625,7 @@ def bench_batch(args, w):
         "dtype": "f32" if args.dtype == "c64" else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "transforms": len(specs), "total_M": total,
                    "N_choices": [64, 128, 256, 512], "m": args.m, "sigma": args.sigma,
-                   "nodes": "uniform", "graph_streams": 8},
+                   "nodes": "uniform", "batch": batch.info()},
         "roofline": None,
         "eager_calls_ms_per_step": round(ms_eager, 5),
         "speedup_vs_eager_calls": round(ms_eager / ms, 2),
