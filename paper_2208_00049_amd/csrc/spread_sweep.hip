@@ -50,15 +50,16 @@ constexpr int kSweepFixedNodes = 2048;
 // words are fixed-point sums (always in complex64), else FP64 sums
 template <typename T> struct SweepAcc {
     using W = unsigned long long;
-    __device__ static inline void add(W *a, int im, T cr, T ci, bool fixed) {
+    // the contributions w * pr, w * pi
+    __device__ static inline void add_prod(W *a, int im, T w, T pr, T pi, bool fixed) {
         if constexpr (sizeof(T) == 8) {
             if (!fixed) {
-                atomicAdd(reinterpret_cast<double *>(a), (double)cr);
-                atomicAdd(reinterpret_cast<double *>(a + im), (double)ci);
+                atomicAdd(reinterpret_cast<double *>(a), (double)(w * pr));
+                atomicAdd(reinterpret_cast<double *>(a + im), (double)(w * pi));
                 return;
             }
         }
-        FixedPoint<T>::add(a, im, cr, ci);
+        FixedPoint<T>::add_prod(a, im, w, pr, pi);
     }
     __device__ static inline T get(const W *a, double inv, bool fixed) {
         if constexpr (sizeof(T) == 8)
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     #pragma unroll
                         for (int b = 0; b < M2; ++b) {
                             const T wb = lane_value(h1, b);  // lane b holds axis-1 tap b
-                            A::add(pl + b * P, PP, wb * ar, wb * ai, kFixed);
+                            A::add_prod(pl + b * P, PP, wb, ar, ai, kFixed);
                         }
                     }
                 } else {
@@ -315,7 +316,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
                         W *pl = cell + r * SP;
                         const T ar = w0[a] * pr, ai = w0[a] * pi;
     #pragma unroll
-                        for (int b = 0; b < M2; ++b) A::add(pl + b * P, PP, w1[b] * ar, w1[b] * ai, kFixed);
+                        for (int b = 0; b < M2; ++b) A::add_prod(pl + b * P, PP, w1[b], ar, ai, kFixed);
                     }
                 }
                 }
