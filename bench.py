@@ -92,12 +92,12 @@ PROFILE_TAG = {("2d_n512_m262144_uniform", "c64"): "n512_m262144_c64_uniform",
 # FFT pass)
 STAGE_KERNEL = {
     (2, "c64"): {"spread": ["nfft::k_spread<float, 2, 8, false, 256>"],
-                 "interp": ["nfft::k_interp<float, 2, 8, false, false, 256>"]},
+                 "interp": ["nfft::k_interp<float, 2, 8, false, false, 256, 1>"]},
     (3, "c64"): {"spread": ["nfft::k_sweep_gather<float>", "nfft::k_spread_sweep<float, 8, false>"],
-                 "interp": ["nfft::k_interp<float, 3, 8, false, false, 512>"]},
+                 "interp": ["nfft::k_interp<float, 3, 8, false, false, 512, 1>"]},
     (3, "c128"): {"spread": ["nfft::k_sweep_gather<double>",
                              "nfft::k_spread_sweep<double, 8, false>"],
-                  "interp": ["nfft::k_interp_sweep<double, 8, false>"]},
+                  "interp": ["nfft::k_interp_sweep<double, 8, false, true>"]},
     (4, "c64"): {"spread": ["nfft::k_spread_owner<float, 4, 8>"],
                  "interp": ["nfft::k_interp_node<float, 4, 8>"]},
 }
