@@ -823,6 +823,21 @@ def main():
                     "rows_of_8_rate": round(lds_rows / 1e12, 4),
                     "achieved": round(rate / 1e12, 4), "peak": round(lds_peak / 1e12, 4),
                     "unit": "T lane-ops/s", "frac": round(rate / lds_peak, 4)}
+    # interpolation's own roof (D <= 3, whose kernels read the grid from LDS): its LDS loads
+    # (one grid value per tap, 8 bytes in complex64, 16 in complex128) per second against the
+    # same calibration, for the unit's best pattern and for rows of eight values at random
+    # starts -- the shape of one interpolation load, eight lanes on a node's row
+    lds_read_roof = None
+    interp_ms = b2b.get("interp", avg_ms.get("interp"))
+    if w["D"] <= 3 and interp_ms:
+        rop = "ds_read_b64" if args.dtype == "c64" else "ds_read_b128"
+        reads = w["M"] * taps ** w["D"]
+        rate = reads / (interp_ms * 1e-3)
+        rpeak, rrows = calibrate_lds(rop, 0), calibrate_lds(rop, 2)
+        lds_read_roof = {"kernel": "interp", "bound": "lds_read", "lane_reads": reads, "op": rop,
+                         "achieved": round(rate / 1e12, 4), "peak": round(rpeak / 1e12, 4),
+                         "rows_of_8_rate": round(rrows / 1e12, 4), "unit": "T lane-reads/s",
+                         "frac": round(rate / rpeak, 4), "frac_of_rows_of_8": round(rate / rrows, 4)}
     fwd_fft_ms = sum(v for k, v in avg_ms.items() if k.startswith("fwd_"))
     rocfft = None
     if not args.profile_only:
@@ -865,6 +880,7 @@ def main():
         "rocfft_reference": rocfft,
         "fft_floor": fft_floor,
         "lds_roof": lds_roof,
+        "lds_read_roof": lds_read_roof,
     }
 
     if not args.profile_only:

@@ -363,19 +363,24 @@ int nfft_plan_bench_stage(nfft_plan_t p, int stage, int reps, const void *in, vo
 
 /*
  * LDS operation rate of the current device (a measurement aid: the roof the
- * spreading kernels' LDS atomics are reported against; the paper's adjoint
- * resampling, subsection "Block-Partitioned Adjoint Resampling", accumulates
- * into a block-local grid, which here lives in LDS).  Launches 8 workgroups
+ * spreading kernels' LDS atomics and the interpolation's LDS reads are reported
+ * against; the paper's resampling, subsections "Block-Partitioned Resampling"
+ * and "Block-Partitioned Adjoint Resampling", works on a block-local copy of the
+ * grid, which here lives in LDS).  Launches 8 workgroups
  * of 256 threads per compute unit, each thread performing 2048 operations of
  * kind `op` on a 16 KiB LDS buffer, `reps` times between two HIP events on
  * `stream` (after one untimed launch), and stores the lane operations per
  * second in *lane_ops_per_s.
  *   op:      NFFT_LDS_ADD_U32 / _ADD_U64 / _ADD_F32 / _ADD_F64 (atomic add,
  *            no return), NFFT_LDS_WRITE_B64 (plain 8-byte store),
- *            NFFT_LDS_RMW_B64 (8-byte load, add, store; not atomic).
+ *            NFFT_LDS_RMW_B64 (8-byte load, add, store; not atomic),
+ *            NFFT_LDS_READ_B64 / _READ_B128 (8- and 16-byte loads, summed:
+ *            a complex64 / complex128 grid value).
  *   pattern: 0 consecutive words across the lanes, 1 a random word per lane,
  *            2 groups of 8 lanes on 8 consecutive words from a random start
- *            (the shape of one spreading instruction).
+ *            (the shape of one spreading instruction, and of one interpolation
+ *            load: eight lanes read a node's row of 2m = 8 grid values).  A
+ *            word is the operation's width.
  * Allocates and frees a small device buffer (one word per thread).
  * Errors: NFFT_ERR_ARG for an unknown op or pattern, reps < 1 or a NULL
  * output; NFFT_ERR_HIP / NFFT_ERR_NOMEM for a failed HIP call.
@@ -387,7 +392,9 @@ enum {
     NFFT_LDS_ADD_F64 = 3,
     NFFT_LDS_WRITE_B64 = 4,
     NFFT_LDS_RMW_B64 = 5,
-    NFFT_LDS_OPS = 6
+    NFFT_LDS_READ_B64 = 6,
+    NFFT_LDS_READ_B128 = 7,
+    NFFT_LDS_OPS = 8
 };
 int nfft_calibrate_lds(int op, int pattern, int reps, void *stream, double *lane_ops_per_s);
 

@@ -39,7 +39,7 @@ EXPORTS = ["nfft_plan_create", "nfft_plan_create_ex", "nfft_plan_destroy", "nfft
 SPREAD = {"auto": 0, "tiled": 1, "sweep": 2}
 NFFT_NUM_STAGES = 8
 LDS_OPS = {"ds_add_u32": 0, "ds_add_u64": 1, "ds_add_f32": 2, "ds_add_f64": 3,
-           "ds_write_b64": 4, "rmw_b64": 5}
+           "ds_write_b64": 4, "rmw_b64": 5, "ds_read_b64": 6, "ds_read_b128": 7}
 STAGES = ["fwd_deconv_fft_last", "fwd_fft_axis1", "fwd_fft_axis0", "interp", "spread",
           "adj_fft_axis0", "adj_fft_axis1", "adj_fft_last_deconv"]
 

@@ -40,11 +40,29 @@ __device__ inline unsigned first_word(int pattern, unsigned W, unsigned salt) {
     return ((hash32((t >> 3) * 2246822519U + salt) & (W - 1)) & ~7U) + (t & 7);
 }
 
+// OP 0: atomic add; 1: store; 2: load, add, store; 3: load (summed in registers, V a
+// vector of 64-bit words for the wide loads)
 template <typename V, int OP>
 __global__ void __launch_bounds__(kCalThreads)
     k_lds_rate(int pattern, int iters, unsigned long long *sink) {
     __shared__ V buf[kCalBytes / sizeof(V)];
     constexpr unsigned W = kCalBytes / sizeof(V);
+    if constexpr (OP == 3) {
+        for (unsigned i = threadIdx.x; i < W; i += kCalThreads) buf[i] = V{i, i};
+        __syncthreads();
+        const unsigned off = first_word(pattern, W, blockIdx.x * 0x9e3779b9U);
+        const unsigned step = pattern == 0 ? kCalThreads : 8u * 97u;
+        unsigned long long s = 0;
+        for (int k = 0; k < iters; k += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const V v = buf[(off + (unsigned)(k + u) * step) & (W - 1)];
+                s += v.x + v.y;
+            }
+        }
+        sink[(size_t)blockIdx.x * kCalThreads + threadIdx.x] = s;
+        return;
+    } else {
     for (unsigned i = threadIdx.x; i < W; i += kCalThreads) buf[i] = (V)0;
     __syncthreads();
     const unsigned off = first_word(pattern, W, blockIdx.x * 0x9e3779b9U);
@@ -63,7 +81,16 @@ __global__ void __launch_bounds__(kCalThreads)
     __syncthreads();
     sink[(size_t)blockIdx.x * kCalThreads + threadIdx.x] =
         (unsigned long long)buf[(threadIdx.x * 37u) & (W - 1)];
+    }
 }
+
+// an 8-byte load: one 64-bit word (the .y half reads as 0)
+struct Word1 {
+    unsigned long long x;
+    static constexpr unsigned long long y = 0;
+    __device__ Word1() = default;
+    __device__ Word1(unsigned long long a, unsigned long long) : x(a) {}
+};
 
 template <typename V, int OP>
 hipError_t time_rate(int pattern, int iters, int blocks, int reps, unsigned long long *sink,
@@ -117,7 +144,9 @@ extern "C" int nfft_calibrate_lds(int op, int pattern, int reps, void *stream,
         case NFFT_LDS_ADD_F32: e = time_rate<float, 0>(pattern, iters, blocks, reps, sink, s, &ms); break;
         case NFFT_LDS_ADD_F64: e = time_rate<double, 0>(pattern, iters, blocks, reps, sink, s, &ms); break;
         case NFFT_LDS_WRITE_B64: e = time_rate<unsigned long long, 1>(pattern, iters, blocks, reps, sink, s, &ms); break;
-        default: e = time_rate<unsigned long long, 2>(pattern, iters, blocks, reps, sink, s, &ms); break;
+        case NFFT_LDS_RMW_B64: e = time_rate<unsigned long long, 2>(pattern, iters, blocks, reps, sink, s, &ms); break;
+        case NFFT_LDS_READ_B64: e = time_rate<Word1, 3>(pattern, iters, blocks, reps, sink, s, &ms); break;
+        default: e = time_rate<ulonglong2, 3>(pattern, iters, blocks, reps, sink, s, &ms); break;
     }
     (void)hipFree(sink);
     if (e != hipSuccess) return NFFT_ERR_HIP;
