@@ -213,6 +213,10 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     } else {
         lw.load(coef, li, wp.m);
     }
+    // the coefficients in registers before any node load is issued (vmcnt(0)): otherwise
+    // the compiler waits for every load in flight, the prefetch of the next chunk
+    // included, at each pass through the node loop
+    __builtin_amdgcn_s_waitcnt(0x0f70);
     const T nan = (T)__builtin_nan("");
 
     // the chunk after (t, c0): the rest of tile t, else the first chunk of the next
@@ -266,12 +270,32 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             auto accumulate = [&](auto fixed_tag) {
                 constexpr bool kFixed = decltype(fixed_tag)::value;
                 if constexpr (WN) {
-                    // one node per wavefront: lane (grp, li) adds the taps (grp, b, li), b = 0..7
-                    for (int k = wave; k < n; k += NT / 64) {
-                        const int pk = st.pk[k];
+                    // one node per wavefront: lane (grp, li) adds the taps (grp, b, li), b = 0..7.
+                    // The next node's staged fields are read before this node's atomics are
+                    // issued: LDS operations of a wavefront complete in order, so read after
+                    // them they would wait for all of its atomics to drain.
+                    constexpr int NW = NT / 64;
+                    int pk_n = 0;
+                    T z0_n = (T)0, z1_n = (T)0, z2_n = (T)0, vr_n = (T)0, vi_n = (T)0;
+                    auto fetch = [&](int k) {
+                        pk_n = st.pk[k];
+                        z0_n = st.fr[0][k];
+                        z1_n = st.fr[1][k];
+                        z2_n = st.fr[2][k];
+                        vr_n = st.vr[k];
+                        vi_n = st.vi[k];
+                    };
+                    if (wave < n) fetch(wave);
+                    // wait for the first reads here (lgkmcnt(0)): a read still in flight at
+                    // the loop entry would make every iteration wait for its atomics
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    for (int k = wave; k < n; k += NW) {
+                        const int pk = pk_n;
+                        const T z0 = z0_n - (T)0.5, z1 = z1_n - (T)0.5, z2 = z2_n - (T)0.5;
+                        const T vr = vr_n, vi = vi_n;
+                        fetch(min(k + NW, n - 1));  // (the last node re-reads itself)
+                        __builtin_amdgcn_sched_barrier(0);  // the reads stay ahead of the atomics
                         const int r0 = pk & 0xff, l1 = (pk >> 8) & 0xff, l2 = pk >> 16;
-                        const T z0 = st.fr[0][k] - (T)0.5, z1 = st.fr[1][k] - (T)0.5,
-                                z2 = st.fr[2][k] - (T)0.5;
                         T h0 = lw.cf[0][M2], h1 = lw.cf[1][M2], h2 = lw.cf[2][M2];
     #pragma unroll
                         for (int z = M2 - 1; z >= 0; --z) {
@@ -281,7 +305,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
                         }
                         // the products in the order of the other mapping (bit-identical terms)
                         const T ws = h2 * scale;
-                        const T pr = st.vr[k] * ws, pi = st.vi[k] * ws;
+                        const T pr = vr * ws, pi = vi * ws;
                         const T ar = h0 * pr, ai = h0 * pi;
                         int r = r0 + grp;
                         if (r >= R) r -= R;
@@ -429,6 +453,11 @@ __global__ void __launch_bounds__(256)
 template <typename T> constexpr int interp_sweep_threads() { return 512; }
 template <typename T> constexpr int interp_sweep_chunk() { return interp_sweep_threads<T>(); }
 
+// Whether the tap loop double-buffers its LDS reads: where the second buffer's
+// registers are free (the configurations that would otherwise spill keep one buffer).
+template <typename T, int M2, bool GW, bool ISO>
+constexpr bool kInterpPipe = sizeof(T) == 4 ? M2 <= 8 : ISO ? M2 <= 8 : GW ? M2 <= 4 : M2 <= 6;
+
 template <typename T, int CH> struct InterpStage {
     int pk[CH];
     T fr[3][CH];
@@ -508,6 +537,8 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
     const int grp = lane / M2, li = lane - grp * M2, gbase = grp * M2;
     LaneWindow<T, ISO ? 1 : 3, M2> lw;
     lw.load(coef, li, wp.m);
+    // (in registers before the node and plane loads are issued, as in spreading)
+    __builtin_amdgcn_s_waitcnt(0x0f70);
 
     auto next_chunk = [&](int &t, int &c0) {
         c0 += CH;
@@ -541,19 +572,10 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
         const int pn = (tb + t) * Q0 + R;
         const bool more = t + 1 < nt;
         T pre_x[PF], pre_y[PF];  // (real and imaginary parts: kept in registers)
-        if (more) {
-#pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int idx = u * NT + tid;
-                const int ic = idx < Q0 * PP ? idx : 0;
-                const int kk = ic / PP, q = ic - kk * PP;
-                const C v = grid[src(pn + kk, q)];
-                pre_x[u] = v.x;
-                pre_y[u] = v.y;
-            }
-        }
-        while (ct == t) {
-            const int c0 = cc0, n = min(CH, seg_end[t] - c0);
+        // The first chunk is staged before the planes are requested: loads complete in
+        // order, so a staging that waits for its chunk's loads would otherwise wait for
+        // the planes too.
+        auto stage = [&](int c0, int n) {
             if (tid < n) {
                 st.pk[tid] = (rec.o[0] % R) | ((rec.o[1] - t1 * kSweepQ) << 8) |
                              ((rec.o[2] - t2 * kSweepQ) << 16);
@@ -562,6 +584,8 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
                 st.idx[tid] = pm;
             }
             __syncthreads();
+        };
+        auto run = [&](int c0, int n) {
             next_chunk(ct, cc0);
             if (ct < nt) load_chunk(ct, cc0);
             else ct = -1;
@@ -595,19 +619,43 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
                     po[a] = (r >= R ? r - R : r) * PP + cell;
                 }
                 T ar = (T)0, ai = (T)0;
+                if constexpr (kInterpPipe<T, M2, GW, ISO>) {
+                    // plane a + 1's rows are read while plane a's are summed (two buffers),
+                    // so the LDS latency is not exposed once per plane
+                    C v[2][M2];
 #pragma unroll
-                for (int a = 0; a < M2; ++a) {
-                    C v[M2];
+                    for (int b = 0; b < M2; ++b) v[0][b] = ring[po[0] + b * P];
 #pragma unroll
-                    for (int b = 0; b < M2; ++b) v[b] = ring[po[a] + b * P];
-                    T sr = (T)0, si = (T)0;
+                    for (int a = 0; a < M2; ++a) {
+                        if (a + 1 < M2) {
 #pragma unroll
-                    for (int b = 0; b < M2; ++b) {
-                        sr = fma(w1[b], v[b].x, sr);
-                        si = fma(w1[b], v[b].y, si);
+                            for (int b = 0; b < M2; ++b) v[(a + 1) & 1][b] = ring[po[a + 1] + b * P];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the sums
+                        T sr = (T)0, si = (T)0;
+#pragma unroll
+                        for (int b = 0; b < M2; ++b) {
+                            sr = fma(w1[b], v[a & 1][b].x, sr);
+                            si = fma(w1[b], v[a & 1][b].y, si);
+                        }
+                        ar = fma(w0[a], sr, ar);
+                        ai = fma(w0[a], si, ai);
                     }
-                    ar = fma(w0[a], sr, ar);
-                    ai = fma(w0[a], si, ai);
+                } else {
+#pragma unroll
+                    for (int a = 0; a < M2; ++a) {
+                        C v[M2];
+#pragma unroll
+                        for (int b = 0; b < M2; ++b) v[b] = ring[po[a] + b * P];
+                        T sr = (T)0, si = (T)0;
+#pragma unroll
+                        for (int b = 0; b < M2; ++b) {
+                            sr = fma(w1[b], v[b].x, sr);
+                            si = fma(w1[b], v[b].y, si);
+                        }
+                        ar = fma(w0[a], sr, ar);
+                        ai = fma(w0[a], si, ai);
+                    }
                 }
                 ar *= w[2];
                 ai *= w[2];
@@ -616,6 +664,29 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
                 if (valid && li == 0) fhat[st.idx[ks]] = cmake<C>(ar, ai);
             }
             __syncthreads();
+        };
+        const bool have = ct == t;
+        int c0 = cc0, n = have ? min(CH, seg_end[t] - c0) : 0;
+        if (have) stage(c0, n);
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int idx = u * NT + tid;
+                const int ic = idx < Q0 * PP ? idx : 0;
+                const int kk = ic / PP, q = ic - kk * PP;
+                const C v = grid[src(pn + kk, q)];
+                pre_x[u] = v.x;
+                pre_y[u] = v.y;
+            }
+        }
+        if (have) {
+            run(c0, n);
+            while (ct == t) {
+                c0 = cc0;
+                n = min(CH, seg_end[t] - c0);
+                stage(c0, n);
+                run(c0, n);
+            }
         }
         if (more) {
             // the tile's first Q_0 planes are no longer needed: the next tile's take their slots
