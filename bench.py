@@ -88,14 +88,14 @@ PROFILE_TAG = {("2d_n512_m262144_uniform", "c64"): "n512_m262144_c64_uniform",
                ("4d_n16_m65536_uniform", "c64"): "n16_m65536_c64_uniform"}
 
 # stage name -> the kernels one back-to-back launch of the stage runs (3-D column sweeps:
-# the fhat gather and the sweep; in 2-D and 3-D the merge is part of the adjoint's first
+# the fhat maximum and the sweep; in 2-D and 3-D the merge is part of the adjoint's first
 # FFT pass)
 STAGE_KERNEL = {
     (2, "c64"): {"spread": ["nfft::k_spread<float, 2, 8, false, 256>"],
                  "interp": ["nfft::k_interp<float, 2, 8, false, false, 256, 1>"]},
-    (3, "c64"): {"spread": ["nfft::k_sweep_gather<float>", "nfft::k_spread_sweep<float, 8, false>"],
+    (3, "c64"): {"spread": ["nfft::k_sweep_amax<float>", "nfft::k_spread_sweep<float, 8, false>"],
                  "interp": ["nfft::k_interp<float, 3, 8, false, false, 512, 1>"]},
-    (3, "c128"): {"spread": ["nfft::k_sweep_gather<double>",
+    (3, "c128"): {"spread": ["nfft::k_sweep_amax<double>",
                              "nfft::k_spread_sweep<double, 8, false>"],
                   "interp": ["nfft::k_interp_sweep<double, 8, false, true>"]},
     (4, "c64"): {"spread": ["nfft::k_spread_owner<float, 4, 8>"],

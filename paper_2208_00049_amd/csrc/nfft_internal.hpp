@@ -121,11 +121,11 @@ template <typename T, int D> struct NodeRec {
 // of L tiles along axis 0; a segment's workgroup keeps a ring of R = Q_0 + taps - 1
 // padded planes in LDS.  Scratch per channel: main_cells values (every grid plane
 // of every column, padded to (kSweepQ + taps - 1)^2 points), then per segment its
-// taps - 1 trailing halo planes, then fhat in sorted node order (M values) and the
-// gather's kSweepParts block maxima (doubles, one per complex slot).
+// taps - 1 trailing halo planes, then the kSweepParts block maxima of |Re|, |Im| of
+// fhat (doubles, one per complex slot).
 constexpr int kSweepQ = 16;
 constexpr int kSweepMaxSegTiles = 64;
-constexpr int kSweepParts = 256;  // blocks of the fhat gather
+constexpr int kSweepParts = 256;  // blocks of the fhat maximum
 struct SweepGeom {
     int on;              // 1: the plan spreads by column sweeps
     int ncols;           // columns (T_1 T_2)
@@ -133,8 +133,7 @@ struct SweepGeom {
     int L;               // tiles per segment (divides T_0)
     int R;               // ring planes
     long long main_cells;
-    long long sorted_off;  // offset of the sorted fhat (main + halo values)
-    long long part_off;    // offset of the block maxima (sorted_off + M)
+    long long part_off;    // offset of the block maxima (main + halo values)
 };
 
 // Factorisation of one FFT line length and its twiddle table exp(-2 pi i t / L).

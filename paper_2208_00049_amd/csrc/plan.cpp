@@ -349,9 +349,8 @@ bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q)
     p.sweep.nsc = T0 / L;
     p.sweep.R = q0 + taps - 1;
     p.sweep.main_cells = (long long)p.Nt[0] * ncols * sweep_plane_cells(taps);
-    p.sweep.sorted_off = p.sweep.main_cells +
-                         (long long)ncols * p.sweep.nsc * (taps - 1) * sweep_plane_cells(taps);
-    p.sweep.part_off = p.sweep.sorted_off + p.M;
+    p.sweep.part_off = p.sweep.main_cells +
+                       (long long)ncols * p.sweep.nsc * (taps - 1) * sweep_plane_cells(taps);
     Q[0] = q0;
     Q[1] = Q[2] = kSweepQ;
     return true;

@@ -22,11 +22,11 @@
 // loads its lines (fft.hip); the merge kernel here serves the single
 // resampling step.
 //
-// Before the sweep, a gather kernel puts fhat into the sorted node order (the one
-// random access to fhat) and records per block the largest |Re|, |Im|, from which
-// every sweep workgroup takes the transform's fixed-point scale; the sweep then
-// reads node records and values as consecutive runs and loads the next chunk of
-// nodes while it accumulates the current one.
+// Before the sweep, a reduction records per block of fhat the largest |Re|, |Im|,
+// from which every sweep workgroup takes the transform's fixed-point scale.  The
+// sweep reads node records as consecutive runs and their values through the sort's
+// permutation, and loads the next chunk of nodes while it accumulates the current
+// one (the permutation one chunk further ahead, so that no load waits for another).
 //
 // Accumulation in LDS: 64-bit fixed point per component (the tiled kernels'
 // scheme, resample_impl.hpp) with a scale from the transform's largest |Re|, |Im|:
@@ -91,40 +91,29 @@ __device__ inline float lane_value(float v, int l) {
 template <typename T> constexpr int sweep_chunk() { return sizeof(T) == 4 ? 1024 : 512; }
 template <typename T> constexpr int sweep_threads() { return 1024; }
 
-// fsorted[s] = fhat[perm[s]] for the sorted positions s of block b's range, and
-// part[b] = the largest max(|Re|, |Im|) among them (+infinity if one is not finite).
+// part[b] = the largest max(|Re|, |Im|) of fhat over block b's range of positions
+// (+infinity if one is not finite).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_sweep_gather(const cplx<T> *__restrict__ fhat, const int *__restrict__ perm, int M,
-                   cplx<T> *__restrict__ scr, long long sorted_off, long long part_off,
-                   long long fstride, long long sstride) {
+    k_sweep_amax(const cplx<T> *__restrict__ fhat, int M, cplx<T> *__restrict__ scr,
+                 long long part_off, long long fstride, long long sstride) {
     using C = cplx<T>;
     fhat += blockIdx.y * fstride;  // channel
     scr += blockIdx.y * sstride;
-    C *fsorted = scr + sorted_off;
     double *part = reinterpret_cast<double *>(scr + part_off);
     __shared__ double wmax[4];
     const int per = (M + gridDim.x - 1) / gridDim.x;
     const int b0 = blockIdx.x * per, b1 = min(M, b0 + per);
     T mx = (T)0;
     for (int s0 = b0; s0 < b1; s0 += 4 * 256) {
-        int pm[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int s = s0 + u * 256 + threadIdx.x;
-            pm[u] = perm[s < b1 ? s : b0];
-        }
         C v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = fhat[pm[u]];
-#pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int s = s0 + u * 256 + threadIdx.x;
-            if (s < b1) {
-                fsorted[s] = v[u];
-                mx = fmax(mx, scale_mag(v[u].x, v[u].y));
-            }
+            v[u] = fhat[s < b1 ? s : b0];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mx = fmax(mx, scale_mag(v[u].x, v[u].y));
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
@@ -135,10 +124,11 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int M2, bool GW>
 __global__ void __launch_bounds__(sweep_threads<T>())
-    k_spread_sweep(cplx<T> *__restrict__ scr, Geom g, SweepGeom sg,
+    k_spread_sweep(const cplx<T> *__restrict__ fhat, const int *__restrict__ perm,
+                   cplx<T> *__restrict__ scr, Geom g, SweepGeom sg,
                    const NodeRec<T, 3> *__restrict__ nodes, const int *__restrict__ key_start,
                    const T *__restrict__ coef, int window, WinParams<T> wp, T wmax_prod,
-                   long long sstride) {
+                   long long fstride, long long sstride) {
     using C = cplx<T>;
     using A = SweepAcc<T>;
     using W = typename A::W;
@@ -149,7 +139,7 @@ __global__ void __launch_bounds__(sweep_threads<T>())
     constexpr bool WN = sweep_wave_node(M2, !GW);  // one node per wavefront
     constexpr int SP = sweep_plane_stride(M2, WN);                   // words per ring plane
     scr += blockIdx.y * sstride;              // channel
-    const C *fsorted = scr + sg.sorted_off;
+    fhat += blockIdx.y * fstride;
     const double *part = reinterpret_cast<const double *>(scr + sg.part_off);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     W *acc = reinterpret_cast<W *>(smem_raw);  // [R][Re, Im][PP]
@@ -228,26 +218,36 @@ __global__ void __launch_bounds__(sweep_threads<T>())
         }
         c0 = t < nt ? seg_beg[t] : 0;
     };
-    // one node per staging thread in registers: all loads issued at once
+    // one node per staging thread in registers: all loads issued at once; the value
+    // through the permutation entry loaded with the chunk before
     NodeRec<T, 3> rec;
     C val;
+    int pmn = 0;  // permutation entry of the chunk after the one in registers
+    auto load_perm = [&](int t, int c0) {
+        const int n = min(CH, seg_end[t] - c0);
+        pmn = perm[c0 + (tid < n ? tid : n - 1)];
+    };
     auto load_chunk = [&](int t, int c0) {
         const int n = min(CH, seg_end[t] - c0);
-        const int k = c0 + (tid < n ? tid : n - 1);
-        rec = nodes[k];
-        val = fsorted[k];
+        rec = nodes[c0 + (tid < n ? tid : n - 1)];
+        val = fhat[pmn];
     };
     int ct = -1, cc0 = 0;  // the chunk held in registers
+    int bt = -1, bc0 = 0;  // the chunk after it
     {
-        int t = -1, c0 = 0;
-        for (++t; t < nt && seg_beg[t] == seg_end[t]; ++t) {
+        int t = 0;
+        for (; t < nt && seg_beg[t] == seg_end[t]; ++t) {
         }
         if (t < nt && !poisoned) {
             ct = t;
             cc0 = seg_beg[t];
+            load_perm(ct, cc0);
             load_chunk(ct, cc0);
+            bt = ct;
+            bc0 = cc0;
+            next_chunk(bt, bc0);
+            if (bt < nt) load_perm(bt, bc0);
         }
-        (void)c0;
     }
 
     for (int t = 0; t < nt; ++t) {
@@ -263,9 +263,15 @@ __global__ void __launch_bounds__(sweep_threads<T>())
             }
             __syncthreads();
             // the next chunk's loads overlap the accumulation of this one
-            next_chunk(ct, cc0);
-            if (ct < nt) load_chunk(ct, cc0);
-            else ct = -1;
+            ct = bt;
+            cc0 = bc0;
+            if (ct < nt) {
+                load_chunk(ct, cc0);
+                next_chunk(bt, bc0);
+                if (bt < nt) load_perm(bt, bc0);
+            } else {
+                ct = -1;
+            }
             // the accumulation, with the segment's kind of sum fixed at compile time
             auto accumulate = [&](auto fixed_tag) {
                 constexpr bool kFixed = decltype(fixed_tag)::value;
@@ -728,9 +734,9 @@ hipError_t run_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, 
     const long long sstride = (long long)sweep_scratch_cells(p);
     const SweepGeom &sg = p.sweep;
     if (p.M == 0) return launch_fill_zero_complex(grid, (int64_t)K * p.G, sizeof(T) == 8, s);
-    hipLaunchKernelGGL(k_sweep_gather<T>, dim3(kSweepParts, K), dim3(256), 0, s,
-                       (const cplx<T> *)fhat, p.perm, (int)p.M, (cplx<T> *)pad, sg.sorted_off,
-                       sg.part_off, (long long)p.M, sstride);
+    hipLaunchKernelGGL(k_sweep_amax<T>, dim3(kSweepParts, K), dim3(256), 0, s,
+                       (const cplx<T> *)fhat, (int)p.M, (cplx<T> *)pad, sg.part_off,
+                       (long long)p.M, sstride);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t shm = sweep_ring_bytes(p);
@@ -739,8 +745,9 @@ hipError_t run_spread_sweep(const nfft_plan_s &p, const void *fhat, void *grid, 
     e = allow_lds(kern, shm, sizeof(SweepStage<T, sweep_chunk<T>()>) + 1024);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(sg.ncols * sg.nsc, K), dim3(sweep_threads<T>()), shm, s,
-                       (cplx<T> *)pad, p.geom, sg, (const NodeRec<T, 3> *)p.nodes, p.key_start,
-                       (const T *)p.coef, p.window, win_params<T>(p), (T)window_bound(3), sstride);
+                       (const cplx<T> *)fhat, p.perm, (cplx<T> *)pad, p.geom, sg,
+                       (const NodeRec<T, 3> *)p.nodes, p.key_start, (const T *)p.coef, p.window,
+                       win_params<T>(p), (T)window_bound(3), (long long)p.M, sstride);
     e = hipGetLastError();
     if (e != hipSuccess || !merge) return e;
     hipLaunchKernelGGL((k_sweep_merge<T, M2>), dim3(p.geom.Nt[0] * sg.ncols, K), dim3(256), 0, s,
