@@ -187,6 +187,117 @@ __device__ inline void line_fft(C *line, bool active, int t, const FftLine &fl, 
     }
 }
 
+// First Stockham pass (p = 1: no twiddles) of a line whose values come from memory:
+// butterfly i takes rows i + r L/R from ld(row) and writes y_r to line[i R + r].  No
+// barrier before: the line is not read until the caller's barrier after it.
+template <typename C, int R, int DIR, typename LD>
+__device__ inline void first_pass_in(C *line, bool active, int L, int t, int tpl, LD &ld) {
+    constexpr int NB = (8 + R - 1) / R;
+    const int nbf = L / R;
+    C x[NB][R];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int i = t + q * tpl;
+        if (active && i < nbf) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[q][r] = ld(i + r * nbf);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int i = t + q * tpl;
+        if (active && i < nbf) {
+            Dft<C, R>::run(x[q], DIR);
+#pragma unroll
+            for (int r = 0; r < R; ++r) line[i * R + r] = x[q][r];
+        }
+    }
+}
+
+// Last Stockham pass (p = L/R, so k = i) of a line in LDS whose outputs go to
+// memory: butterfly i reads line[i + r p], applies W^(r i), and hands y_r for row
+// i + r p to st(row, value).
+template <typename C, int R, int DIR, typename ST>
+__device__ inline void last_pass_out(const C *line, bool active, int L, int t, int tpl, const C *tw,
+                                     ST &st) {
+    constexpr int NB = (8 + R - 1) / R;
+    const int p = L / R;
+    C x[NB][R];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int i = t + q * tpl;
+        if (active && i < p) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[q][r] = line[i + r * p];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int i = t + q * tpl;
+        if (active && i < p) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C w = tw[r * i];
+                x[q][r] = DIR < 0 ? cmul(x[q][r], w) : cmulc(x[q][r], w);
+            }
+            Dft<C, R>::run(x[q], DIR);
+#pragma unroll
+            for (int r = 0; r < R; ++r) st(i + r * p, x[q][r]);
+        }
+    }
+}
+
+// A line FFT (at least two passes) whose first pass loads from memory and whose last
+// pass stores to memory, the passes between them in LDS: half the LDS traffic and
+// three fewer barriers than loading the line into LDS first and storing it from there.
+// The line must not be in use (the caller's barrier); the table tw must be ready
+// by the first pass's barrier.
+template <typename C, int DIR, bool POW2, typename LD, typename ST>
+__device__ inline void line_fft_io(C *line, bool active, int t, const FftLine &fl, const C *tw, LD &ld,
+                                   ST &st) {
+    const int L = fl.L, tpl = fl.tpl;
+    switch (fl.rad[0]) {
+        case 8: first_pass_in<C, 8, DIR>(line, active, L, t, tpl, ld); break;
+        case 4: first_pass_in<C, 4, DIR>(line, active, L, t, tpl, ld); break;
+        case 2: first_pass_in<C, 2, DIR>(line, active, L, t, tpl, ld); break;
+        case 5:
+            if constexpr (!POW2) first_pass_in<C, 5, DIR>(line, active, L, t, tpl, ld);
+            break;
+        default:
+            if constexpr (!POW2) first_pass_in<C, 3, DIR>(line, active, L, t, tpl, ld);
+            break;
+    }
+    __syncthreads();
+    int p = fl.rad[0];
+    for (int s = 1; s + 1 < fl.npass; ++s) {
+        const int R = fl.rad[s];
+        const int twstep = L / (p * R);
+        switch (R) {
+            case 8: stockham_pass<C, 8, DIR, POW2>(line, active, L, p, twstep, t, tpl, tw); break;
+            case 4: stockham_pass<C, 4, DIR, POW2>(line, active, L, p, twstep, t, tpl, tw); break;
+            case 2: stockham_pass<C, 2, DIR, POW2>(line, active, L, p, twstep, t, tpl, tw); break;
+            case 5:
+                if constexpr (!POW2) stockham_pass<C, 5, DIR, POW2>(line, active, L, p, twstep, t, tpl, tw);
+                break;
+            default:
+                if constexpr (!POW2) stockham_pass<C, 3, DIR, POW2>(line, active, L, p, twstep, t, tpl, tw);
+                break;
+        }
+        p *= R;
+    }
+    switch (fl.rad[fl.npass - 1]) {
+        case 8: last_pass_out<C, 8, DIR>(line, active, L, t, tpl, tw, st); break;
+        case 4: last_pass_out<C, 4, DIR>(line, active, L, t, tpl, tw, st); break;
+        case 2: last_pass_out<C, 2, DIR>(line, active, L, t, tpl, tw, st); break;
+        case 5:
+            if constexpr (!POW2) last_pass_out<C, 5, DIR>(line, active, L, t, tpl, tw, st);
+            break;
+        default:
+            if constexpr (!POW2) last_pass_out<C, 3, DIR>(line, active, L, t, tpl, tw, st);
+            break;
+    }
+}
+
 // Strided axis pass: the workgroup owns B consecutive inner columns of one outer
 // position; rows are read and written B complex values at a time.
 // bx: the workgroup's block among the nbx blocks of this grid's pass.
@@ -220,6 +331,27 @@ __device__ inline void fft_strided_body(cplx<T> *grid, const FftLine &fl, const 
     // twiddle table after the B lines (when it fits)
     C *twl = lds + B * LP;
     if (fl.tw_lds) copy_table(twl, (const C *)fl.tw, L, tid, nthr);
+    if (fl.npass >= 2) {
+        // thread (b, t), b the faster: the B columns of a row are B consecutive values
+        const int b = tid & (B - 1), t = tid >> lgB;
+        const bool active = t < fl.tpl;
+        const bool col_ok = i0 + b < inner;
+        const long long cb = obase + (col_ok ? i0 + b : i0);
+        const int bi = a.in_band_N, bo = a.out_band_N;
+        // rows of the band of I_N: 0 .. ceil(N/2) - 1 and L - floor(N/2) .. L - 1
+        auto ld = [&](int row) -> C {
+            const bool in = col_ok && (!bi || row < bi - bi / 2 || row >= L - bi / 2);
+            return in ? grid[cb + (long long)row * inner] : cmake<C>((T)0, (T)0);
+        };
+        auto st = [&](int row, C v) {
+            if (col_ok && (!bo || row < bo - bo / 2 || row >= L - bo / 2))
+                grid[cb + (long long)row * inner] = v;
+        };
+        C *line = lds + b * LP;
+        if (fl.tw_lds) line_fft_io<C, DIR, POW2>(line, active, t, fl, twl, ld, st);
+        else line_fft_io<C, DIR, POW2>(line, active, t, fl, (const C *)fl.tw, ld, st);
+        return;
+    }
     // load the band (or the whole lines): U loads per thread in flight at once
     const int nin = a.in_band_N ? a.in_band_N : L;
     {
