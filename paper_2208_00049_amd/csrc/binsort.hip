@@ -5,8 +5,10 @@
 // or m (the wide stencil of 2m + 2 points).  The stencil of the node covers grid
 // points o .. o+taps-1 (mod Nt) on that axis.  The node is binned by
 // the tile that holds its origin, and by a class bit per axis that says whether
-// its stencil runs past the end of that tile into the next one.  Sort key =
-// tile << D | class.  The bin boundaries come from a histogram and an exclusive
+// its stencil runs past the end of that tile into the next one: sort key =
+// tile << D | class.  (Complex128 column sweeps order a tile's nodes by the LDS bank
+// slot of their first value in the interpolation ring instead, 4 bits: see
+// Geom::kbits.)  The bin boundaries come from a histogram and an exclusive
 // scan; the order is a stable sort of (key, node index) pairs -- least-significant
 // digit first, 8 bits per pass, each pass a stable counting sort -- so nodes of
 // one bin keep the caller's order and a plan is a deterministic function of its
@@ -58,7 +60,7 @@ template <typename T, int D>
 __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, int *bad) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
-    int tile = 0, cls = 0;
+    int tile = 0, cls = 0, slot = 0;
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -72,13 +74,20 @@ __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, i
         const int loc = c.o - p * g.Q[d];
         tile = tile * g.T[d] + p;
         cls |= (loc >= g.Q[d] - (g.taps - 1)) ? (1 << d) : 0;
+        if (g.pair_R > 0 && D == 3) {
+            // the bank slot: ((o_0 mod R) P^2 + (o_1 mod 16) P + o_2 mod 16) mod 16
+            const int P = kSweepQ + g.taps - 1;
+            const int v = d == 0 ? (c.o % g.pair_R) * P * P : d == 1 ? (c.o % kSweepQ) * P : c.o % kSweepQ;
+            slot += v;
+        }
     }
+    if (g.pair_R > 0) cls = slot & 15;
     if (!ok) {
         *bad = 1;
         tile = 0;
         cls = 0;
     }
-    const int key = (tile << D) | cls;
+    const int key = (tile << g.kbits) | cls;
     keys[j] = key;
     atomicAdd(&counts[key], 1);
 }
@@ -133,19 +142,19 @@ __global__ void __launch_bounds__(1024) k_exclusive_scan(const int *in, int *out
 }
 
 // Interpolation work items: tile p is cut into ceil(count / maxn) items of <= maxn nodes.
-__global__ void k_subprob_count(const int *key_start, int ntiles, int D, int maxn, int *counts) {
+__global__ void k_subprob_count(const int *key_start, int ntiles, int kbits, int maxn, int *counts) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntiles) return;
-    const int n = key_start[(p + 1) << D] - key_start[p << D];
+    const int n = key_start[(p + 1) << kbits] - key_start[p << kbits];
     counts[p] = (n + maxn - 1) / maxn;
 }
 
-__global__ void k_subprob_fill(const int *key_start, const int *sub_start, int ntiles, int D,
+__global__ void k_subprob_fill(const int *key_start, const int *sub_start, int ntiles, int kbits,
                                int maxn, int4 *subs) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= ntiles) return;
-    const int b = key_start[p << D];
-    const int e = key_start[(p + 1) << D];
+    const int b = key_start[p << kbits];
+    const int e = key_start[(p + 1) << kbits];
     int w = sub_start[p];
     for (int s = b; s < e; s += maxn) subs[w++] = make_int4(p, s, min(e, s + maxn), 0);
 }
@@ -349,13 +358,13 @@ hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int 
 
 hipError_t launch_subprob_count(const nfft_plan_s &p, int *counts, hipStream_t s) {
     hipLaunchKernelGGL(k_subprob_count, grid1d(p.geom.ntiles, 256), dim3(256), 0, s, p.key_start,
-                       p.geom.ntiles, p.D, p.max_block_nodes, counts);
+                       p.geom.ntiles, p.geom.kbits, p.max_block_nodes, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_subprob_fill(nfft_plan_s &p, const int *sub_start, hipStream_t s) {
     hipLaunchKernelGGL(k_subprob_fill, grid1d(p.geom.ntiles, 256), dim3(256), 0, s, p.key_start,
-                       sub_start, p.geom.ntiles, p.D, p.max_block_nodes, p.subs);
+                       sub_start, p.geom.ntiles, p.geom.kbits, p.max_block_nodes, p.subs);
     return hipGetLastError();
 }
 

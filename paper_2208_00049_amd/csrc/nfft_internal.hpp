@@ -43,6 +43,12 @@ struct Geom {
     int ntiles;      // prod T
     int taps;        // stencil points per axis: 2m, or 2m + 2 with the wide stencil
     int lo;          // stencil points before the node's cell: taps/2 - 1
+    // Sort key of a node: tile << kbits | sub-key.  The sub-key is the class (a bit
+    // per axis, kbits = D) or, for the complex128 column sweeps (pair_R > 0, kbits =
+    // 4), the LDS bank slot of the node's first value in the interpolation ring
+    // (pair_R planes of P^2 values, P = kSweepQ + taps - 1), modulo 16.
+    int kbits;
+    int pair_R;
 };
 
 // Tile-owner spreading (D >= 4): a workgroup owns one tile and visits the nodes
@@ -218,7 +224,7 @@ struct nfft_plan_s {
     nfft::Geom geom;
     int64_t G;            // prod Nt
     int64_t NN;           // prod N
-    int nkeys;            // ntiles << D
+    int nkeys;            // ntiles << geom.kbits
     int nsub;             // resampling work items
     int device;
     int lds_limit;        // LDS per workgroup of the device, bytes

@@ -610,7 +610,11 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
             p->geom.T[d] = d < D ? (int)(p->Nt[d] / Q[d]) : 1;
             p->geom.ntiles *= p->geom.T[d];
         }
-        p->nkeys = p->geom.ntiles << D;
+        // complex128 column sweeps: a tile's nodes ordered by their interpolation ring's
+        // bank slot (the interpolation pairs nodes whose slots differ by 8)
+        p->geom.pair_R = p->sweep.on && dtype == NFFT_C128 ? p->sweep.R : 0;
+        p->geom.kbits = p->geom.pair_R > 0 ? 4 : D;
+        p->nkeys = p->geom.ntiles << p->geom.kbits;
         if (!(opts && opts->max_block_nodes) && D <= 2 && M <= (int64_t)kSparseBlockNodes * p->geom.ntiles)
             p->max_block_nodes = kSparseBlockNodes;
         subs_cap = p->geom.ntiles + M / p->max_block_nodes + 1;
