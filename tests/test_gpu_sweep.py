@@ -13,7 +13,11 @@ Algorithms 1 and 2) at the rounding gate of the type:
 * the multi-channel call, bit for bit the single-channel one (the fixed-point
   sums are exact in both types), and repeated adjoints, bit for bit each other;
 * the padded-tile scheme on the same nodes (spread="tiled") and the errors of a
-  plan that asks for sweeps where they are not available.
+  plan that asks for sweeps where they are not available;
+* the order of the nodes: a plan of the permuted nodes gives the permuted forward
+  values and the same adjoint, bit for bit (each node's value is summed by one group
+  of lanes in a fixed order wherever the sort and the bank-slot pairing of complex128
+  place it, and the spreading sums are exact).
 """
 import numpy as np
 import pytest
@@ -113,3 +117,21 @@ def test_sweep_not_available(device):
     assert p.info()["spread"] == "tiled"
     p, _ = make_plan(device, x, (16, 16, 16), 3, 2.0, "c64", wide=True)
     assert p.info()["spread"] == "tiled"
+
+
+@pytest.mark.parametrize("N,M,m", [((32, 32, 32), 9000, 4), ((24, 32, 16), 5000, 3)])
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_sweep_node_order(device, N, M, m, dt):
+    x = wl.uniform_nodes(M, 3, config=155, stream=0)
+    perm = wl.rng(155, 3).permutation(M)
+    f, fh = wl.cn01(N, config=155, stream=1), wl.cn01((M,), config=155, stream=2)
+    pa, _ = make_plan(device, x, N, m, 2.0, dt)
+    pb, _ = make_plan(device, np.asarray(x)[perm], N, m, 2.0, dt)
+    assert pa.info()["spread"] == "sweep" and pb.info()["spread"] == "sweep"
+    fd = to_dev(f, dt, device)
+    fa, fb = pa.forward(fd), pb.forward(fd)
+    assert torch.equal(fb, fa[torch.as_tensor(perm, device=device)])
+    fhd = to_dev(fh, dt, device)
+    ya = pa.adjoint(fhd)
+    yb = pb.adjoint(fhd[torch.as_tensor(perm, device=device)].contiguous())
+    assert torch.equal(ya, yb)
