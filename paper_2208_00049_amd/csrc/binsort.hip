@@ -6,15 +6,17 @@
 // points o .. o+taps-1 (mod Nt) on that axis.  The node is binned by
 // the tile that holds its origin, and by a class bit per axis that says whether
 // its stencil runs past the end of that tile into the next one: sort key =
-// tile << D | class.  (Complex128 column sweeps order a tile's nodes by the LDS bank
-// slot of their first value in the interpolation ring instead, 4 bits: see
-// Geom::kbits.)  The bin boundaries come from a histogram and an exclusive
+// tile << D | class.  (Complex128 column sweeps key a tile's nodes by the LDS bank
+// slot of their first value in the interpolation ring instead, 5 bits, and then
+// interleave the slots in quadruples by a second sort: see launch_node_sort.)  The bin boundaries come from a histogram and an exclusive
 // scan; the order is a stable sort of (key, node index) pairs -- least-significant
 // digit first, 8 bits per pass, each pass a stable counting sort -- so nodes of
 // one bin keep the caller's order and a plan is a deterministic function of its
 // nodes (its work items, and with them every summation order, do not depend on
 // the scheduling of the plan-time kernels).
 #include <math.h>
+
+#include <algorithm>
 
 #include <string.h>
 
@@ -75,13 +77,13 @@ __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, i
         tile = tile * g.T[d] + p;
         cls |= (loc >= g.Q[d] - (g.taps - 1)) ? (1 << d) : 0;
         if (g.pair_R > 0 && D == 3) {
-            // the bank slot: ((o_0 mod R) P^2 + (o_1 mod 16) P + o_2 mod 16) mod 16
+            // the bank slot: ((o_0 mod R) P^2 + (o_1 mod 16) P + o_2 mod 16) mod 32
             const int P = kSweepQ + g.taps - 1;
             const int v = d == 0 ? (c.o % g.pair_R) * P * P : d == 1 ? (c.o % kSweepQ) * P : c.o % kSweepQ;
             slot += v;
         }
     }
-    if (g.pair_R > 0) cls = slot & 15;
+    if (g.pair_R > 0) cls = slot & 31;
     if (!ok) {
         *bad = 1;
         tile = 0;
@@ -310,8 +312,52 @@ hipError_t node_sort_bytes(const nfft_plan_s &p, size_t *bytes) {
     return hipSuccess;
 }
 
-hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int *keys_sorted,
-                            int *idx, void *tmp, size_t tmp_bytes, hipStream_t s) {
+// Radix passes over `bits` key bits of (kin, iin): intermediate sequences alternate
+// between (kb, ib) and (k2, i2); the last pass writes the indices to iout and, when
+// kout is not NULL, the keys to kout (neither aliasing that pass's input).
+static hipError_t radix_passes(const int *kin, const int *iin, int M, unsigned bits, int *kb, int *ib,
+                               int *k2, int *i2, int *hist, int *start, int *kout, int *iout,
+                               hipStream_t s) {
+    const int run = sort_run(M);
+    const int nb = (M + run - 1) / run;
+    const int nh = kSortBins * nb;
+    const int passes = (int)(bits + 7) / 8;
+    hipError_t e = hipSuccess;
+    for (int pass = 0; pass < passes; ++pass) {
+        const bool last = pass == passes - 1;
+        int *ko = last ? kout : (pass % 2 == 0 ? kb : k2);
+        int *io = last ? iout : (pass % 2 == 0 ? ib : i2);
+        hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortThreads), 0, s, kin, M, 8 * pass, run,
+                           hist);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_exclusive_scan(hist, start, nh, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, kin, iin, M,
+                           8 * pass, run, start, ko, io);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        kin = ko;
+        iin = io;
+    }
+    return e;
+}
+
+// Second sort key of the complex128 column sweeps, per sorted position: (tile, bank
+// slot mod 8, rank of the node among the tile's nodes of its slot, slot / 8), so that
+// after the second stable sort four consecutive nodes of a tile have the slots s,
+// s + 8, s + 16, s + 24 (mod 32) wherever the four slots have a node of that rank.
+__global__ void k_quad_keys(const int *__restrict__ ks, const int *__restrict__ key_start, int M,
+                            int kbits, int rbits, int *__restrict__ key2) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= M) return;
+    const int key = ks[pos];
+    const int tile = key >> kbits, slot = key & ((1 << kbits) - 1);
+    const int rank = min(pos - key_start[key], (1 << rbits) - 1);
+    key2[pos] = (((((tile << 3) | (slot & 7)) << rbits) | rank) << 2) | (slot >> 3);
+}
+
+hipError_t launch_node_sort(nfft_plan_s &p, const void *x, int *keys, int *keys_sorted, int *idx,
+                            void *tmp, size_t tmp_bytes, hipStream_t s) {
     if (p.M == 0) return hipSuccess;
     const int M = (int)p.M;
     const int run = sort_run(M);
@@ -324,24 +370,34 @@ hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int 
     hipLaunchKernelGGL(k_iota, grid1d(M, 256), dim3(256), 0, s, idx, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int passes = (int)(key_bits(p.nkeys) + 7) / 8;
-    const int *kin = keys, *iin = idx;
-    for (int pass = 0; pass < passes; ++pass) {
-        const bool last = pass == passes - 1;
-        // intermediate sequences alternate between (kb, ib) and (keys_sorted, idx)
-        int *kout = last ? nullptr : (pass % 2 == 0 ? kb : keys_sorted);
-        int *iout = last ? p.perm : (pass % 2 == 0 ? ib : idx);
-        hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortThreads), 0, s, kin, M, 8 * pass, run,
-                           hist);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = launch_exclusive_scan(hist, start, nh, s);
+    const unsigned bits = key_bits(p.nkeys);
+    if (p.geom.pair_R <= 0) {
+        e = radix_passes(keys, idx, M, bits, kb, ib, keys_sorted, idx, hist, start, nullptr, p.perm, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortThreads), 0, s, kin, iin, M,
-                           8 * pass, run, start, kout, iout);
-        e = hipGetLastError();
+    } else {
+        // (tile, slot) first, keeping the sorted keys: pass i reads (keys, idx) for i = 0,
+        // else (kb, ib) for odd i and (keys_sorted, idx) for even i, so the last pass
+        // writes its keys to the pair it does not read
+        const int passes1 = (int)(bits + 7) / 8;
+        int *ks = passes1 % 2 == 0 ? keys_sorted : kb;
+        e = radix_passes(keys, idx, M, bits, kb, ib, keys_sorted, idx, hist, start, ks, p.perm, s);
         if (e != hipSuccess) return e;
-        kin = kout;
-        iin = iout;
+        unsigned tbits = 1;
+        while (tbits < 31 && (1u << tbits) < (unsigned)p.geom.ntiles) ++tbits;
+        // ranks past 31 keep their order (a bin holds a handful of nodes unless the
+        // nodes cluster); the fewer key bits, the fewer passes
+        const int rbits = std::min(5, 31 - (int)tbits - 5);
+        if (rbits < 1) return hipErrorInvalidValue;
+        // then the quadruple key (into keys, free now), carrying the permutation
+        hipLaunchKernelGGL(k_quad_keys, grid1d(M, 256), dim3(256), 0, s, ks, p.key_start, M,
+                           p.geom.kbits, rbits, keys);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(idx, p.perm, (size_t)M * sizeof(int), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = radix_passes(keys, idx, M, tbits + 5 + (unsigned)rbits, kb, ib, keys_sorted, idx,
+                             hist, start, nullptr, p.perm, s);
+        if (e != hipSuccess) return e;
     }
     const bool f = p.dtype == NFFT_C64;
     switch (p.D) {

@@ -45,8 +45,10 @@ struct Geom {
     int lo;          // stencil points before the node's cell: taps/2 - 1
     // Sort key of a node: tile << kbits | sub-key.  The sub-key is the class (a bit
     // per axis, kbits = D) or, for the complex128 column sweeps (pair_R > 0, kbits =
-    // 4), the LDS bank slot of the node's first value in the interpolation ring
-    // (pair_R planes of P^2 values, P = kSweepQ + taps - 1), modulo 16.
+    // 5), the LDS bank slot of the node's first value in the interpolation ring
+    // (pair_R planes of P^2 values, P = kSweepQ + taps - 1): its 16-byte offset modulo
+    // 32, a 512-byte row of the banks.  (Those plans sort a second time inside each
+    // tile: see launch_node_sort.)
     int kbits;
     int pair_R;
 };
@@ -301,7 +303,7 @@ hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int 
 hipError_t launch_exclusive_scan(const int *in, int *out, int n, hipStream_t s);
 // Stable bin sort: keys_sorted and idx hold M ints; tmp is node_sort_bytes() bytes.
 hipError_t node_sort_bytes(const nfft_plan_s &p, size_t *bytes);
-hipError_t launch_node_sort(nfft_plan_s &p, const void *x, const int *keys, int *keys_sorted,
+hipError_t launch_node_sort(nfft_plan_s &p, const void *x, int *keys, int *keys_sorted,
                             int *idx, void *tmp, size_t tmp_bytes, hipStream_t s);
 hipError_t launch_subprob_count(const nfft_plan_s &p, int *counts, hipStream_t s);
 hipError_t launch_subprob_fill(nfft_plan_s &p, const int *sub_start, hipStream_t s);

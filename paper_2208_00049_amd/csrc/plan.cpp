@@ -610,10 +610,10 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
             p->geom.T[d] = d < D ? (int)(p->Nt[d] / Q[d]) : 1;
             p->geom.ntiles *= p->geom.T[d];
         }
-        // complex128 column sweeps: a tile's nodes ordered by their interpolation ring's
-        // bank slot (the interpolation pairs nodes whose slots differ by 8)
+        // complex128 column sweeps: a tile's nodes keyed by their interpolation ring's bank
+        // slot and ordered in quadruples of slots 8 apart (see launch_node_sort)
         p->geom.pair_R = p->sweep.on && dtype == NFFT_C128 ? p->sweep.R : 0;
-        p->geom.kbits = p->geom.pair_R > 0 ? 4 : D;
+        p->geom.kbits = p->geom.pair_R > 0 ? 5 : D;
         p->nkeys = p->geom.ntiles << p->geom.kbits;
         if (!(opts && opts->max_block_nodes) && D <= 2 && M <= (int64_t)kSparseBlockNodes * p->geom.ntiles)
             p->max_block_nodes = kSparseBlockNodes;

@@ -494,7 +494,6 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
     __shared__ InterpStage<T, CH> st;
     __shared__ int seg_beg[kSweepMaxSegTiles + 1];
     __shared__ int seg_end[kSweepMaxSegTiles + 1];
-    __shared__ int seg_mid[kSweepMaxSegTiles + 1];
 
     const int seg = blockIdx.x;
     const int col = seg / sg.nsc, kseg = seg - col * sg.nsc;
@@ -518,8 +517,6 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
         const int tile = ((tb + tid) * g.T[1] + t1) * g.T[2] + t2;
         seg_beg[tid] = key_start[tile << g.kbits];
         seg_end[tid] = key_start[(tile + 1) << g.kbits];
-        // with the bank-slot sub-key, the tile's nodes of slots 0..7 come first
-        seg_mid[tid] = g.pair_R > 0 ? key_start[(tile << g.kbits) + 8] : seg_end[tid];
     }
     // the first R planes, eight loads per thread in flight
     {
@@ -598,16 +595,13 @@ __global__ void __launch_bounds__(interp_sweep_threads<T>())
             next_chunk(ct, cc0);
             if (ct < nt) load_chunk(ct, cc0);
             else ct = -1;
-            // Groups 2p and 2p + 1 of a wavefront share the LDS's passes over their
-            // reads; with the nodes of a tile ordered by bank slot they take the p-th
-            // node of slots 0..7 and the p-th of slots 8..15 (offsets about 8 slots,
-            // half the banks, apart), then the remaining nodes in order.
-            const int nl = min(max(seg_mid[t] - c0, 0), n);  // chunk nodes of slots 0..7
-            const int npair = min(nl, n - nl);
+            // Groups 4p .. 4p + 3 of a wavefront share an LDS pass over their 16-byte
+            // reads (32 lanes, a 512-byte row of banks); complex128 plans order a tile's
+            // nodes so that four consecutive ones have bank slots 8 apart (mod 32), and
+            // their rows of eight values then fall on disjoint banks.
             for (int base = wave * NPW; base < n; base += (NT / 64) * NPW) {
                 const int v = base + grp;
-                const int k = v < 2 * npair ? ((v & 1) ? nl + (v >> 1) : (v >> 1))
-                                            : (nl > npair ? v - npair : nl + v - npair);
+                const int k = v;
                 const bool valid = grp < NPW && v < n;
                 const int ks = valid ? k : 0;
                 const int pk = st.pk[ks];
