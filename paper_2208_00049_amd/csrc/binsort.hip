@@ -207,8 +207,94 @@ hipError_t launch_node_keys(const nfft_plan_s &p, const void *x, int *keys, int 
     return hipGetLastError();
 }
 
+// Exclusive scan of large n in three launches, without scratch: the sum of every block
+// of kScanBlock inputs goes to the block's first output slot, one workgroup scans
+// those slots in place (and writes the total to out[n]), and every block then scans
+// its inputs from the offset it finds there.
+constexpr int kScanBlock = 2048;  // 256 threads x 8 consecutive inputs
+
+__global__ void __launch_bounds__(256) k_scan_sums(const int *__restrict__ in, int n, int *out) {
+    __shared__ int ws[4];
+    const int base = blockIdx.x * kScanBlock, end = min(n, base + kScanBlock);
+    int v = 0;
+    for (int i = base + threadIdx.x; i < end; i += 256) v += in[i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[base] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// out[b * stride] for b < nb: block sums -> their exclusive prefix sums; out[n] = total.
+__global__ void __launch_bounds__(1024) k_scan_offsets(int *out, int nb, int stride, int n) {
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int chunk = (nb + 1023) / 1024;
+    const int b = tid * chunk, e = min(nb, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += out[(size_t)i * stride];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = tid > 0 ? part[tid - 1] : 0;
+    for (int i = b; i < e; ++i) {
+        const int v = out[(size_t)i * stride];
+        out[(size_t)i * stride] = run;
+        run += v;
+    }
+    if (tid == 1023) out[n] = part[1023];
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int *__restrict__ in, int n, int *out) {
+    __shared__ int ws[4];
+    __shared__ int offset;
+    const int base = blockIdx.x * kScanBlock;
+    if (threadIdx.x == 0) offset = out[base];  // (read before the block overwrites it)
+    const int i0 = base + threadIdx.x * 8;
+    int v[8];
+    int tsum = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        v[u] = i0 + u < n ? in[i0 + u] : 0;
+        tsum += v[u];
+    }
+    // exclusive prefix of the thread sums: wavefront scan, then the wavefronts' totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = tsum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    int run = offset + incl - tsum;
+    for (int w = 0; w < wave; ++w) run += ws[w];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (i0 + u < n) out[i0 + u] = run;
+        run += v[u];
+    }
+}
+
 hipError_t launch_exclusive_scan(const int *in, int *out, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, s, in, out, n);
+    if (n <= 4 * kScanBlock) {
+        hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, s, in, out, n);
+        return hipGetLastError();
+    }
+    const int nb = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, s, in, n, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, out, nb, kScanBlock, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, in, n, out);
     return hipGetLastError();
 }
 
