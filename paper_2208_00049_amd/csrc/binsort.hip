@@ -4,12 +4,13 @@
 // frac = y - c, stencil origin o = (c - lo) mod Nt with lo = m - 1 (2m points)
 // or m (the wide stencil of 2m + 2 points).  The stencil of the node covers grid
 // points o .. o+taps-1 (mod Nt) on that axis.  The node is binned by
-// the tile that holds its origin, and by a class bit per axis that says whether
-// its stencil runs past the end of that tile into the next one: sort key =
-// tile << D | class.  (Complex128 column sweeps key a tile's nodes by the LDS bank
-// slot of their first value in the interpolation ring instead, 5 bits, and then
-// interleave the slots in quadruples by a second sort: see launch_node_sort.)  The bin boundaries come from a histogram and an exclusive
-// scan; the order is a stable sort of (key, node index) pairs -- least-significant
+// the tile that holds its origin and, inside the tile, by a sub-key: for D <= 3 the
+// LDS bank slot of the node's first value in the interpolation's LDS (the plans
+// then interleave the slots by a second sort, see launch_node_sort), for D >= 4 a
+// class bit per axis that says whether its stencil runs past the end of that tile
+// into the next one.  Sort key = tile << kbits | sub-key (Geom::kbits).  The bin
+// boundaries come from a histogram and an exclusive scan; the order is a stable
+// sort of (key, node index) pairs -- least-significant
 // digit first, 8 bits per pass, each pass a stable counting sort -- so nodes of
 // one bin keep the caller's order and a plan is a deterministic function of its
 // nodes (its work items, and with them every summation order, do not depend on
@@ -77,13 +78,15 @@ __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, i
         tile = tile * g.T[d] + p;
         cls |= (loc >= g.Q[d] - (g.taps - 1)) ? (1 << d) : 0;
         if (g.pair_R > 0 && D == 3) {
-            // the bank slot: ((o_0 mod R) P^2 + (o_1 mod 16) P + o_2 mod 16) mod 32
+            // the bank slot in the sweep's ring: (o_0 mod R) P^2 + (o_1 mod 16) P + o_2 mod 16
             const int P = kSweepQ + g.taps - 1;
-            const int v = d == 0 ? (c.o % g.pair_R) * P * P : d == 1 ? (c.o % kSweepQ) * P : c.o % kSweepQ;
-            slot += v;
+            slot += d == 0 ? (c.o % g.pair_R) * P * P : d == 1 ? (c.o % kSweepQ) * P : c.o % kSweepQ;
+        } else {
+            // in the tile with its trailing halo: the row-major offset of the local cell
+            slot = slot * (g.Q[d] + g.taps - 1) + loc;
         }
     }
-    if (g.pair_R > 0) cls = slot & 31;
+    if (g.slot_mod > 0) cls = slot & (g.slot_mod - 1);
     if (!ok) {
         *bad = 1;
         tile = 0;
@@ -428,10 +431,11 @@ static hipError_t radix_passes(const int *kin, const int *iin, int M, unsigned b
     return e;
 }
 
-// Second sort key of the complex128 column sweeps, per sorted position: (tile, bank
-// slot mod 8, rank of the node among the tile's nodes of its slot, slot / 8), so that
-// after the second stable sort four consecutive nodes of a tile have the slots s,
-// s + 8, s + 16, s + 24 (mod 32) wherever the four slots have a node of that rank.
+// Second sort key of the bank-slot plans, per sorted position: (tile, bank slot mod 8,
+// rank of the node among the tile's nodes of its slot, slot / 8), so that after the
+// second stable sort 2^(kbits - 3) consecutive nodes of a tile -- four (complex128,
+// slots mod 32) or eight (complex64, mod 64) -- have slots 8 apart wherever those
+// slots have a node of that rank.
 __global__ void k_quad_keys(const int *__restrict__ ks, const int *__restrict__ key_start, int M,
                             int kbits, int rbits, int *__restrict__ key2) {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,7 +443,7 @@ __global__ void k_quad_keys(const int *__restrict__ ks, const int *__restrict__ 
     const int key = ks[pos];
     const int tile = key >> kbits, slot = key & ((1 << kbits) - 1);
     const int rank = min(pos - key_start[key], (1 << rbits) - 1);
-    key2[pos] = (((((tile << 3) | (slot & 7)) << rbits) | rank) << 2) | (slot >> 3);
+    key2[pos] = (((((tile << 3) | (slot & 7)) << rbits) | rank) << (kbits - 3)) | (slot >> 3);
 }
 
 hipError_t launch_node_sort(nfft_plan_s &p, const void *x, int *keys, int *keys_sorted, int *idx,
@@ -457,7 +461,7 @@ hipError_t launch_node_sort(nfft_plan_s &p, const void *x, int *keys, int *keys_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned bits = key_bits(p.nkeys);
-    if (p.geom.pair_R <= 0) {
+    if (p.geom.slot_mod == 0) {
         e = radix_passes(keys, idx, M, bits, kb, ib, keys_sorted, idx, hist, start, nullptr, p.perm, s);
         if (e != hipSuccess) return e;
     } else {
@@ -472,18 +476,20 @@ hipError_t launch_node_sort(nfft_plan_s &p, const void *x, int *keys, int *keys_
         while (tbits < 31 && (1u << tbits) < (unsigned)p.geom.ntiles) ++tbits;
         // ranks past 31 keep their order (a bin holds a handful of nodes unless the
         // nodes cluster); the fewer key bits, the fewer passes
-        const int rbits = std::min(5, 31 - (int)tbits - 5);
-        if (rbits < 1) return hipErrorInvalidValue;
-        // then the quadruple key (into keys, free now), carrying the permutation
-        hipLaunchKernelGGL(k_quad_keys, grid1d(M, 256), dim3(256), 0, s, ks, p.key_start, M,
-                           p.geom.kbits, rbits, keys);
-        e = hipGetLastError();
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(idx, p.perm, (size_t)M * sizeof(int), hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = radix_passes(keys, idx, M, tbits + 5 + (unsigned)rbits, kb, ib, keys_sorted, idx,
-                             hist, start, nullptr, p.perm, s);
-        if (e != hipSuccess) return e;
+        const int jbits = p.geom.kbits - 3;
+        const int rbits = std::min(5, 31 - (int)tbits - 3 - jbits);
+        if (rbits >= 1) {  // (else, with more tiles than the key holds, the first order stays)
+            // then the grouping key (into keys, free now), carrying the permutation
+            hipLaunchKernelGGL(k_quad_keys, grid1d(M, 256), dim3(256), 0, s, ks, p.key_start, M,
+                               p.geom.kbits, rbits, keys);
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(idx, p.perm, (size_t)M * sizeof(int), hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = radix_passes(keys, idx, M, tbits + 3 + (unsigned)(rbits + jbits), kb, ib,
+                                 keys_sorted, idx, hist, start, nullptr, p.perm, s);
+            if (e != hipSuccess) return e;
+        }
     }
     const bool f = p.dtype == NFFT_C64;
     switch (p.D) {

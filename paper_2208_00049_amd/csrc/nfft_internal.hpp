@@ -44,12 +44,15 @@ struct Geom {
     int taps;        // stencil points per axis: 2m, or 2m + 2 with the wide stencil
     int lo;          // stencil points before the node's cell: taps/2 - 1
     // Sort key of a node: tile << kbits | sub-key.  The sub-key is the class (a bit
-    // per axis, kbits = D) or, for the complex128 column sweeps (pair_R > 0, kbits =
-    // 5), the LDS bank slot of the node's first value in the interpolation ring
-    // (pair_R planes of P^2 values, P = kSweepQ + taps - 1): its 16-byte offset modulo
-    // 32, a 512-byte row of the banks.  (Those plans sort a second time inside each
-    // tile: see launch_node_sort.)
+    // per axis, kbits = D; D >= 4), or the LDS bank slot of the node's first value in
+    // the interpolation's LDS (slot_mod > 0: its offset in values modulo slot_mod = 32
+    // for complex128, 64 for complex64, a 512-byte row of the banks; kbits = 5 or 6):
+    // in the ring of the complex128 column sweeps (pair_R > 0: pair_R planes of P^2
+    // values, P = kSweepQ + taps - 1), else in the work item's tile with its trailing
+    // halo (Q_d + taps - 1 values per axis).  Those plans sort a second time inside
+    // each tile: see launch_node_sort.
     int kbits;
+    int slot_mod;
     int pair_R;
 };
 
