@@ -8,6 +8,9 @@
 * the exact adjointness of the GPU pair (A ~= B F D, A^H ~= D^T F^H B^T);
 * edge cases: M = 0, one node, all nodes in one tile, grid-aligned nodes,
   x = -1/2, a hot spot of coincident nodes, nodes outside the torus.
+* the order of the nodes (padded-tile plans of 2 and 3 axes): a plan of the
+  permuted nodes gives the permuted forward values bit for bit and the adjoint
+  within the rounding gate.
 
 Tolerances (derived from the arithmetic, not fitted).  Rounding errors of
 relative size u (2^-24 for c64, 2^-53 for c128) made on the oversampled grid
@@ -333,3 +336,28 @@ def test_odd_sizes(device, dt, N, M):
     assert rel2(yg, na.adjoint(xs, fh, N, m, sigma)) < tol
     gate = NDFT_GATE[(m, sigma)] + tol
     assert rel2(fg, ndft.ndft_forward(xs, f)) < gate
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("N,M,kw", [((64, 48), 5000, {}), ((32, 32), 20000, {}),
+                                    ((32, 32, 32), 6000, {"spread": "tiled"}),
+                                    ((32, 32, 32), 70000, {"spread": "tiled"})])
+def test_node_order_tiled(device, dt, N, M, kw):
+    # A plan of the permuted nodes gives the permuted forward values bit for bit: each
+    # node's interpolated value is summed by one group of lanes in a fixed order
+    # wherever the sort by LDS bank slot places the node.  The adjoint agrees within
+    # the rounding gate: its fixed-point sums are exact, but a work item's scale comes
+    # from the nodes it holds, and a dense tile's nodes split into work items by order.
+    x = wl.uniform_nodes(M, len(N), config=158, stream=0)
+    perm = wl.rng(158, 3).permutation(M)
+    f, fh = wl.cn01(N, config=158, stream=1), wl.cn01((M,), config=158, stream=2)
+    pa, _ = make_plan(device, x, N, 4, 2.0, dt, **kw)
+    pb, _ = make_plan(device, np.asarray(x)[perm], N, 4, 2.0, dt, **kw)
+    print("node order", dt, N, M, pa.info(), flush=True)
+    assert pa.info()["spread"] == "tiled"
+    pt = torch.as_tensor(perm, device=device)
+    fd = to_dev(f, dt, device)
+    assert torch.equal(pb.forward(fd), pa.forward(fd)[pt])
+    fhd = to_dev(fh, dt, device)
+    ya, yb = pa.adjoint(fhd).cpu().numpy(), pb.adjoint(fhd[pt].contiguous()).cpu().numpy()
+    assert rel2(yb, ya) < e2e_tol(N, 2.0, 4, dt)
