@@ -77,10 +77,10 @@ __global__ void k_node_keys(const T *x, int M, Geom g, int *keys, int *counts, i
         const int loc = c.o - p * g.Q[d];
         tile = tile * g.T[d] + p;
         cls |= (loc >= g.Q[d] - (g.taps - 1)) ? (1 << d) : 0;
-        if (g.pair_R > 0 && D == 3) {
+        if (g.ring_R > 0 && D == 3) {
             // the bank slot in the sweep's ring: (o_0 mod R) P^2 + (o_1 mod 16) P + o_2 mod 16
             const int P = kSweepQ + g.taps - 1;
-            slot += d == 0 ? (c.o % g.pair_R) * P * P : d == 1 ? (c.o % kSweepQ) * P : c.o % kSweepQ;
+            slot += d == 0 ? (c.o % g.ring_R) * P * P : d == 1 ? (c.o % kSweepQ) * P : c.o % kSweepQ;
         } else {
             // in the tile with its trailing halo: the row-major offset of the local cell
             slot = slot * (g.Q[d] + g.taps - 1) + loc;
@@ -436,7 +436,7 @@ static hipError_t radix_passes(const int *kin, const int *iin, int M, unsigned b
 // second stable sort 2^(kbits - 3) consecutive nodes of a tile -- four (complex128,
 // slots mod 32) or eight (complex64, mod 64) -- have slots 8 apart wherever those
 // slots have a node of that rank.
-__global__ void k_quad_keys(const int *__restrict__ ks, const int *__restrict__ key_start, int M,
+__global__ void k_slot_group_keys(const int *__restrict__ ks, const int *__restrict__ key_start, int M,
                             int kbits, int rbits, int *__restrict__ key2) {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= M) return;
@@ -474,13 +474,13 @@ hipError_t launch_node_sort(nfft_plan_s &p, const void *x, int *keys, int *keys_
         if (e != hipSuccess) return e;
         unsigned tbits = 1;
         while (tbits < 31 && (1u << tbits) < (unsigned)p.geom.ntiles) ++tbits;
-        // ranks past 31 keep their order (a bin holds a handful of nodes unless the
-        // nodes cluster); the fewer key bits, the fewer passes
+        // ranks from 2^rbits - 1 on (31 at most) keep their order (a bin holds a handful
+        // of nodes unless the nodes cluster); the fewer key bits, the fewer passes
         const int jbits = p.geom.kbits - 3;
         const int rbits = std::min(5, 31 - (int)tbits - 3 - jbits);
         if (rbits >= 1) {  // (else, with more tiles than the key holds, the first order stays)
             // then the grouping key (into keys, free now), carrying the permutation
-            hipLaunchKernelGGL(k_quad_keys, grid1d(M, 256), dim3(256), 0, s, ks, p.key_start, M,
+            hipLaunchKernelGGL(k_slot_group_keys, grid1d(M, 256), dim3(256), 0, s, ks, p.key_start, M,
                                p.geom.kbits, rbits, keys);
             e = hipGetLastError();
             if (e == hipSuccess)

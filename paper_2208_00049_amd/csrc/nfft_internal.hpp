@@ -47,13 +47,13 @@ struct Geom {
     // per axis, kbits = D; D >= 4), or the LDS bank slot of the node's first value in
     // the interpolation's LDS (slot_mod > 0: its offset in values modulo slot_mod = 32
     // for complex128, 64 for complex64, a 512-byte row of the banks; kbits = 5 or 6):
-    // in the ring of the complex128 column sweeps (pair_R > 0: pair_R planes of P^2
+    // in the ring of the complex128 column sweeps (ring_R > 0: ring_R planes of P^2
     // values, P = kSweepQ + taps - 1), else in the work item's tile with its trailing
     // halo (Q_d + taps - 1 values per axis).  Those plans sort a second time inside
     // each tile: see launch_node_sort.
     int kbits;
     int slot_mod;
-    int pair_R;
+    int ring_R;
 };
 
 // Tile-owner spreading (D >= 4): a workgroup owns one tile and visits the nodes

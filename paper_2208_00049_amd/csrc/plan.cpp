@@ -613,10 +613,10 @@ int nfft_plan_create_ex(nfft_plan_t *out, int D, const int64_t *N, int64_t M, co
         // D <= 3: a tile's nodes keyed by the LDS bank slot of their first value in the
         // interpolation (the complex128 column sweeps' ring, else the tile) and ordered in
         // groups of slots 8 apart (see launch_node_sort)
-        p->geom.pair_R = p->sweep.on && dtype == NFFT_C128 ? p->sweep.R : 0;
+        p->geom.ring_R = p->sweep.on && dtype == NFFT_C128 ? p->sweep.R : 0;
         p->geom.slot_mod = D <= 3 ? (dtype == NFFT_C128 ? 32 : 64) : 0;
         if (p->geom.slot_mod && ((long long)p->geom.ntiles << 6) >= (1LL << 30)) p->geom.slot_mod = 0;
-        if (!p->geom.slot_mod) p->geom.pair_R = 0;  // (the sweep then reads the class order)
+        if (!p->geom.slot_mod) p->geom.ring_R = 0;  // (the sweep then reads the class order)
         p->geom.kbits = p->geom.slot_mod == 32 ? 5 : p->geom.slot_mod == 64 ? 6 : D;
         p->nkeys = p->geom.ntiles << p->geom.kbits;
         if (!(opts && opts->max_block_nodes) && D <= 2 && M <= (int64_t)kSparseBlockNodes * p->geom.ntiles)

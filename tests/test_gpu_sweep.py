@@ -16,8 +16,8 @@ Algorithms 1 and 2) at the rounding gate of the type:
   plan that asks for sweeps where they are not available;
 * the order of the nodes: a plan of the permuted nodes gives the permuted forward
   values and the same adjoint, bit for bit (each node's value is summed by one group
-  of lanes in a fixed order wherever the sort and the bank-slot pairing of complex128
-  place it, and the spreading sums are exact).
+  of lanes in a fixed order wherever the sort by LDS bank slot places it, and the
+  spreading sums are exact).
 """
 import numpy as np
 import pytest
