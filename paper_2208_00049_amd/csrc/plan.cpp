@@ -302,9 +302,8 @@ int cus_of(int dev) {
 // Column-sweep spreading for a 3-D plan (see spread_sweep.hip): tiles (Q_0, 16, 16)
 // with the largest Q_0 in {8, 4, 2, 1} (or the requested one) whose ring of
 // Q_0 + taps - 1 planes fits the LDS beside the staged nodes, and whose
-// interpolation tile fits too; segments of L tiles along axis 0, L the smallest
-// divisor of T_0 that gives at most about four segments per compute unit and
-// spans >= taps - 1 planes.  Fills p.sweep and Q; false if the plan cannot sweep.
+// interpolation tile fits too; segments of L tiles along axis 0 (L chosen below).
+// Fills p.sweep and Q; false if the plan cannot sweep.
 bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q) {
     const int taps = 2 * p.m + (p.wide ? 2 : 0);
     if (p.D != 3 || p.wide || taps > 10) return false;
@@ -334,14 +333,25 @@ bool plan_sweep(nfft_plan_s &p, const int *req, size_t dev_lds, int cus, int *Q)
     }
     const int T0 = (int)(p.Nt[0] / q0);
     const int ncols = (int)(p.Nt[1] / kSweepQ) * (int)(p.Nt[2] / kSweepQ);
+    // Segments of L tiles (L divides T_0 and spans at least the 2m - 1 halo planes).  The
+    // workgroups (one per segment, one per compute unit: the ring takes most of the LDS) run
+    // in rounds of `cus`; a segment costs its L Q_0 planes of nodes plus its 2m - 1 halo
+    // planes, which are only loaded and written, at about a third of a plane each (a sweep
+    // of 1 .. 8 segments per column on the 3-D workloads): L minimises rounds x (3 L Q_0 +
+    // 2m - 1), so a column is cut only as far as the compute units need.
     const int lmin = std::max(1, (taps - 1 + q0 - 1) / q0);
-    const int target = std::max(1, 4 * cus / ncols);  // segments per column
     int L = 0;
-    for (int l = lmin; l <= std::min(T0, kSweepMaxSegTiles); ++l)
-        if (T0 % l == 0) {
-            L = l;  // the largest valid one so far
-            if (T0 / l <= target) break;
+    long long best = 0;
+    for (int l = lmin; l <= std::min(T0, kSweepMaxSegTiles); ++l) {
+        if (T0 % l) continue;
+        const long long wgs = (long long)ncols * (T0 / l);
+        const long long rounds = (wgs + cus - 1) / cus;
+        const long long cost = rounds * (3LL * l * q0 + taps - 1);
+        if (!L || cost < best) {
+            L = l;
+            best = cost;
         }
+    }
     if (!L) return false;
     p.sweep.on = 1;
     p.sweep.ncols = ncols;

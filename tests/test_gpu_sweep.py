@@ -8,7 +8,8 @@ Algorithms 1 and 2) at the rounding gate of the type:
 
 * several stencil widths (2m = 4 .. 10, which change the plane depth Q_0 and the
   segment length), both sigma, both types, several segments per column and the
-  cyclic wrap of the last segment's halo into the first;
+  cyclic wrap of the last segment's halo into the first, and columns swept as one
+  segment (the halo onto the segment's own first planes);
 * a clustered node set whose dense tiles hold several staged chunks;
 * the multi-channel call, bit for bit the single-channel one (the fixed-point
   sums are exact in both types), and repeated adjoints, bit for bit each other;
@@ -44,6 +45,22 @@ def test_sweep_matches_oracle(device, N, M, m, sigma, dt):
     assert info["spread"] == "sweep" and info["tile"][1:] == (16, 16)
     tol = e2e_tol(N, sigma, m, dt)
     assert rel2(yg, na.adjoint(xs, fh, N, m, sigma)) < tol, rel2(yg, na.adjoint(xs, fh, N, m, sigma))
+    assert rel2(fg, na.forward(xs, f, m, sigma)) < tol
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_sweep_single_segment_columns(device, dt):
+    """Oversampled 16 x 256 x 256: 256 columns of two tiles, which a device of 256 compute
+    units sweeps as one segment per column (one round of workgroups), so that a column's
+    last 2m - 1 planes wrap onto its own first ones."""
+    N, M, m, sigma = (8, 128, 128), 20000, 4, 2.0
+    x = wl.uniform_nodes(M, 3, config=156, stream=0)
+    f, fh = wl.cn01(N, config=156, stream=1), wl.cn01((M,), config=156, stream=2)
+    p, xs, fg, yg = run_pair(device, x, N, m, sigma, dt, f, fh)
+    print("sweep single segment", dt, p.info(), flush=True)
+    assert p.info()["spread"] == "sweep"
+    tol = e2e_tol(N, sigma, m, dt)
+    assert rel2(yg, na.adjoint(xs, fh, N, m, sigma)) < tol
     assert rel2(fg, na.forward(xs, f, m, sigma)) < tol
 
 
