@@ -49,11 +49,11 @@ WORKLOADS = {
 
 
 def kernel_source_hash():
-    """SHA-256 over the device-code sources of libnfft (.hip, .hpp), to tie stored
-    counters to the kernel version they were measured on."""
+    """SHA-256 over the sources of libnfft (.hip, .hpp and the host .cpp, which choose the
+    launch geometry), to tie stored counters to the version they were measured on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2208_00049_amd", "csrc")
-    for f in sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp"))):
+    for f in sorted(f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp", ".cpp"))):
         h.update(f.encode())
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
